@@ -1,0 +1,160 @@
+/*
+ * krr.h -- C ABI of a gfx950 (MI355X) library for kernel ridge regression
+ * solved by preconditioned conjugate gradient, following Diaz, Epperly,
+ * Frangella, Tropp & Webber, "Robust, randomized preconditioning for kernel
+ * ridge regression" (arXiv 2304.12465).
+ *
+ * Conventions, for every entry point:
+ *  - Array arguments are DEVICE pointers unless the comment says "host".
+ *    Matrices are row-major and densely packed: a point set X with N points
+ *    of dimension d is N x d (point i is X[i*d .. i*d+d)); a block of m
+ *    vectors V of length n is n x m (vector c is the strided column V[i*m+c]).
+ *  - The caller owns every array it passes in and every output buffer.
+ *  - Device memory the library needs beyond inputs and outputs comes from a
+ *    caller-allocated workspace `ws` of `ws_bytes` bytes (any alignment >= 256
+ *    bytes); the matching *_ws query returns the bytes needed, which is also
+ *    the HBM footprint of that object.  The library itself never allocates
+ *    device memory.
+ *  - Work is enqueued on `stream` (a hipStream_t; 0 is the null stream).
+ *    Calls return after enqueueing unless the comment says they synchronise.
+ *  - Return value: 0 = success, 1 = KRR_NOT_CONVERGED (a warning: outputs hold
+ *    the last iterate), a negative KRR_E* code on error.  Errors are reported,
+ *    never thrown; krr_last_error() describes the last failure on the calling
+ *    thread.  Shapes and parameters are validated before anything is
+ *    launched.
+ */
+#ifndef KRR_H
+#define KRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KRR_OK = 0,
+  KRR_NOT_CONVERGED = 1,
+  KRR_EINVAL = -1,      /* invalid shape or parameter */
+  KRR_EWORKSPACE = -2,  /* workspace too small (or NULL) */
+  KRR_ENOTSPD = -3,     /* Cholesky breakdown of a matrix that should be SPD */
+  KRR_ENAN = -4,        /* NaN or Inf in a residual */
+  KRR_EHIP = -5         /* a HIP runtime call failed */
+};
+
+/* Kernel functions.  Gaussian (squared exponential, Sec. 2.1.2):
+ *   K(x,y) = exp(-||x-y||^2 / (2 sigma^2)).
+ * l1 Laplace (Sec. 4.1):
+ *   K(x,y) = exp(-||x-y||_1 / sigma).                                      */
+typedef enum { KRR_GAUSSIAN = 0, KRR_LAPLACE = 1 } krr_kernel_kind;
+
+/* Arithmetic of the kernel tiles.  FP64: entries and sums in FP64.
+ * FP32: entries in FP32, sums over at most 256 columns in FP32, then FP64.
+ * MIXED: the Gaussian distance contraction on bf16 MFMA with a hi/lo split
+ * (three products), exp and in-tile sums in FP32, cross-tile sums in FP64;
+ * Laplace tiles under MIXED use the FP32 arithmetic.  Vectors of the CG
+ * recurrences and all CG scalars stay FP64 in every mode.                   */
+typedef enum { KRR_FP64 = 0, KRR_FP32 = 1, KRR_MIXED = 2 } krr_precision;
+
+/* Human-readable description of the last failure on this thread. */
+const char* krr_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Matrix-free kernel product (Alg. 1 "Product"; Sec. 4.1 blockwise scheme):
+ *   W[nr x m] = K(Xr, Xc) V[nc x m] + shift * V.
+ * Xr (nr x d) and Xc (nc x d) are FP64 points; V is FP64 nc x m; W is FP64
+ * nr x m and must not overlap V.  The kernel matrix is never stored: every
+ * entry is recomputed in registers and reduced against V at once.
+ * shift != 0 requires nr == nc (the caller passes the same point set).
+ * Limits: 1 <= d <= 64, 1 <= m <= 64, nr, nc >= 0 (nr == 0 is a no-op;
+ * nc == 0 gives W = 0 + shift V), sigma > 0.
+ * The reduction order is fixed, so results are bitwise reproducible.      */
+int krr_kernel_matvec_ws(krr_precision prec, int64_t nr, int64_t nc, int32_t d, int32_t m,
+                         size_t* bytes);
+int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precision prec,
+                      const double* Xr, int64_t nr, const double* Xc, int64_t nc, int32_t d,
+                      const double* V, int32_t m, double shift, double* W,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+
+/* Timing of the fused product tiles (the dominant kernel): when enabled,
+ * every tile launch is bracketed by HIP events recorded on the stream it
+ * runs on.  krr_timing_read waits for the recorded launches, returns their
+ * summed duration (ms) and count, and clears the record.                   */
+int krr_timing_enable(int on);
+int krr_timing_read(double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------
+ * Preconditioned solves.  A krr_precond is an opaque host object holding
+ * device pointers into the caller's workspace; it owns neither the points X
+ * (which must stay alive and unchanged while it is used) nor the workspace.
+ * One precond runs one solve at a time; calls on different preconds may
+ * run concurrently on different streams.                                   */
+typedef struct krr_precond_s* krr_precond;
+
+typedef struct {
+  int32_t iters;            /* PCG iterations (max over right-hand sides) */
+  int32_t converged_cols;   /* columns with recursive relative residual <= tol */
+  double relres_recursive;  /* max over columns of ||r_t|| / ||b|| (recurrence) */
+  double relres_true;       /* max over columns of ||b - M x|| / ||b||, FP64 product */
+  double build_seconds;     /* wall time of the preconditioner build */
+  double solve_seconds;     /* wall time of this solve */
+  double* history;          /* host, optional: max relative residual per iteration */
+  int32_t history_cap;      /* capacity of history (in entries) */
+  int32_t history_len;      /* entries written */
+} krr_solve_info;
+
+/* Full-data KRR (eq. exact_eqn): (A + mu I) beta = y with A_ij = K(x_i, x_j),
+ * preconditioned by P = F F^T + mu I where F (N x rank) comes from blocked
+ * RPCholesky (Appendix A, Alg. 3) with block size B; B = 0 selects
+ * min(100, ceil(r/10)) (Alg. 1).  Pivots are drawn from the residual
+ * diagonal with SplitMix64 keyed by `seed`.  The preconditioner is applied
+ * in the Woodbury form (r - Q Q^T r) / mu with Q = F L^{-T}, L L^T =
+ * mu I + F^T F, which equals the SVD form of Alg. 1.
+ * X: N x d FP64 device points.  1 <= r <= N, 0 <= B <= 128, mu > 0,
+ * 1 <= m_max <= 64 (largest number of right-hand sides solved at once).
+ * The build synchronises `stream` (pivot draws are read back per block).
+ * Returns KRR_ENOTSPD if mu I + F^T F cannot be factored.                  */
+int krr_rpchol_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d, int32_t r,
+                  int32_t B, int32_t m_max, size_t* bytes);
+int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec, const double* X,
+                     int64_t N, int32_t d, double mu, int32_t r, int32_t B, uint64_t seed,
+                     int32_t m_max, void* ws, size_t ws_bytes, krr_precond* out,
+                     hipStream_t stream);
+/* F^T (rank x N, row-major, device) of the RPCholesky factor, recomputed as
+ * L Q^T into the caller's buffer.                                          */
+int krr_rpchol_factor(krr_precond P, double* FT, hipStream_t stream);
+
+/* Number of pivots / centres (RPCholesky: accepted pivots, may be < r when
+ * the residual is exhausted; KRILL: k) and the system size n (N or k).     */
+int krr_precond_dims(krr_precond P, int32_t* rank, int64_t* n);
+/* Host copy of the pivot indices in selection order (RPCholesky) or of the
+ * centres in ascending order (KRILL); at most `cap` entries.              */
+int krr_precond_pivots(krr_precond P, int64_t* host_out, int32_t cap, int32_t* count);
+/* OUT = P^{-1} Z for n x m row-major device blocks (m <= m_max).           */
+int krr_precond_apply(krr_precond P, const double* Z, int32_t m, double* OUT,
+                      hipStream_t stream);
+/* OUT = M V with the system operator (full: K V + mu V; restricted:
+ * A(S,:)(A(:,S) V) + H V), in the build precision; n x m row-major.        */
+int krr_precond_operator(krr_precond P, const double* V, int32_t m, double* OUT,
+                         hipStream_t stream);
+/* Releases the host object (the workspace stays the caller's).             */
+void krr_precond_free(krr_precond P);
+
+/* PCG (Sec. 3, eq. psd_system) from a zero start until every column reaches
+ * ||r|| <= tol ||b|| on the recursive residual, or max_iter.  Y is N x m
+ * (targets, row-major, device); beta receives n x m (N for full-data, k for
+ * restricted).  The true residual is evaluated once at exit with an FP64
+ * product; on the FP64 path one residual-replacement restart is made if it
+ * exceeds 10 tol.  Synchronises `stream` once per iteration.  Returns
+ * KRR_NOT_CONVERGED (beta = last iterate) if a column did not converge and
+ * KRR_ENAN on a NaN/Inf residual.                                          */
+int krr_pcg_solve(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,
+                  double* beta, krr_solve_info* info, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRR_H */

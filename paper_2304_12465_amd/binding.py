@@ -1,0 +1,242 @@
+"""ctypes binding of libkrr.so (the C ABI declared in include/krr.h).
+
+Argument marshalling only: torch tensors provide device memory (their
+``data_ptr``) and the current HIP stream; every step of the method runs in
+the library's kernels.  The library must be built (``__graft_entry__.build``
+or ``python paper_2304_12465_amd/_build.py``); loading fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkrr.so")
+
+GAUSSIAN, LAPLACE = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
+NOT_CONVERGED = 1
+ERRORS = {-1: "EINVAL", -2: "EWORKSPACE", -3: "ENOTSPD", -4: "ENAN", -5: "EHIP"}
+
+_lib = None
+_c = ctypes
+_i32, _i64, _u64, _dbl, _vp, _sz = _c.c_int32, _c.c_int64, _c.c_uint64, _c.c_double, _c.c_void_p, _c.c_size_t
+_szp = _c.POINTER(_c.c_size_t)
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged_cols", ctypes.c_int32),
+                ("relres_recursive", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("build_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
+                ("history_len", ctypes.c_int32)]
+
+
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+_SIGS = {
+    "krr_last_error": ([], _c.c_char_p),
+    "krr_timing_enable": ([_i32], _i32),
+    "krr_timing_read": ([ctypes.POINTER(ctypes.c_double), _i64p], _i32),
+    "krr_rpchol_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _szp], _i32),
+    "krr_rpchol_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _i32, _i32, _u64, _i32, _vp,
+                          _sz, _pp, _vp], _i32),
+    "krr_rpchol_factor": ([_vp, _vp, _vp], _i32),
+    "krr_precond_dims": ([_vp, _i32p, _i64p], _i32),
+    "krr_precond_pivots": ([_vp, _i64p, _i32, _i32p], _i32),
+    "krr_precond_apply": ([_vp, _vp, _i32, _vp, _vp], _i32),
+    "krr_precond_operator": ([_vp, _vp, _i32, _vp, _vp], _i32),
+    "krr_precond_free": ([_vp], None),
+    "krr_pcg_solve": ([_vp, _vp, _i32, _dbl, _i32, _vp, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "krr_kernel_matvec_ws": ([_i32, _i64, _i64, _i32, _i32, _szp], _i32),
+    "krr_kernel_matvec": ([_i32, _dbl, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _i32, _dbl, _vp,
+                           _vp, _sz, _vp], _i32),
+}
+
+
+class KrrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"krr error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+def lib():
+    """Loads libkrr.so once; raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def check(rc):
+    if rc < 0:
+        raise KrrError(rc, lib().krr_last_error().decode())
+    return rc
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def workspace(nbytes, device):
+    """A caller-owned workspace buffer (256-byte aligned torch storage)."""
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+def _f64(t):
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return t
+
+
+def kernel_matvec_ws(prec, nr, nc, d, m):
+    b = ctypes.c_size_t(0)
+    check(lib().krr_kernel_matvec_ws(prec, nr, nc, d, m, ctypes.byref(b)))
+    return b.value
+
+
+def kernel_matvec(kind, sigma, prec, Xr, Xc, V, shift=0.0, out=None, ws=None):
+    """W = K(Xr, Xc) V + shift V on the GPU (all float64 device tensors)."""
+    _f64(Xr), _f64(Xc), _f64(V)
+    squeeze = V.dim() == 1
+    V2 = V.reshape(-1, 1) if squeeze else V
+    nr, d = Xr.shape
+    nc = Xc.shape[0]
+    m = V2.shape[1]
+    W = out if out is not None else torch.empty((nr, m), dtype=torch.float64, device=Xr.device)
+    if ws is None:
+        ws = workspace(kernel_matvec_ws(prec, nr, nc, d, m), Xr.device)
+    check(lib().krr_kernel_matvec(kind, float(sigma), prec, _ptr(Xr), nr, _ptr(Xc), nc, d,
+                                  _ptr(V2), m, float(shift), _ptr(W), _ptr(ws), ws.numel(),
+                                  _stream(Xr.device)))
+    return W.reshape(-1) if squeeze else W
+
+
+class Precond:
+    """A built preconditioner: owns its workspace tensor and keeps X alive."""
+
+    def __init__(self, handle, ws, X, m_max, kind):
+        self.h = handle
+        self.ws = ws
+        self.X = X
+        self.m_max = m_max
+        self.kind = kind
+        self.device = X.device
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().krr_precond_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def dims(self):
+        r = ctypes.c_int32(0)
+        n = ctypes.c_int64(0)
+        check(lib().krr_precond_dims(self.h, ctypes.byref(r), ctypes.byref(n)))
+        return r.value, n.value
+
+    def pivots(self):
+        cnt = ctypes.c_int32(0)
+        check(lib().krr_precond_pivots(self.h, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_int64 * max(cnt.value, 1))()
+        check(lib().krr_precond_pivots(self.h, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]
+
+    def _block(self, Z):
+        _f64(Z)
+        return Z.reshape(-1, 1) if Z.dim() == 1 else Z
+
+    def apply(self, Z):
+        """P^{-1} Z (n x m)."""
+        Z2 = self._block(Z)
+        out = torch.empty_like(Z2)
+        check(lib().krr_precond_apply(self.h, _ptr(Z2), Z2.shape[1], _ptr(out), _stream(self.device)))
+        return out.reshape(Z.shape)
+
+    def operator(self, V):
+        """M V with the system operator (n x m)."""
+        V2 = self._block(V)
+        out = torch.empty_like(V2)
+        check(lib().krr_precond_operator(self.h, _ptr(V2), V2.shape[1], _ptr(out),
+                                         _stream(self.device)))
+        return out.reshape(V.shape)
+
+    def factor(self):
+        """F^T (rank x N) of an RPCholesky preconditioner."""
+        r, _ = self.dims()
+        FT = torch.empty((r, self.X.shape[0]), dtype=torch.float64, device=self.device)
+        check(lib().krr_rpchol_factor(self.h, _ptr(FT), _stream(self.device)))
+        return FT
+
+    def solve(self, Y, tol, max_iter=1000, history=0):
+        """PCG; returns (beta, info dict).  Y: N x m targets."""
+        Y2 = self._block(Y)
+        r, n = self.dims()
+        beta = torch.empty((n, Y2.shape[1]), dtype=torch.float64, device=self.device)
+        info = SolveInfo()
+        hist = None
+        if history:
+            hist = (ctypes.c_double * history)()
+            info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+            info.history_cap = history
+        rc = check(lib().krr_pcg_solve(self.h, _ptr(Y2), Y2.shape[1], float(tol), int(max_iter),
+                                       _ptr(beta), ctypes.byref(info), _stream(self.device)))
+        d = dict(iters=info.iters, converged_cols=info.converged_cols,
+                 relres_recursive=info.relres_recursive, relres_true=info.relres_true,
+                 build_seconds=info.build_seconds, solve_seconds=info.solve_seconds,
+                 converged=(rc == 0))
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(info.history_len)]
+        return (beta.reshape(-1) if Y.dim() == 1 else beta), d
+
+
+def rpchol_ws(kind, prec, N, d, r, B=0, m_max=1):
+    b = ctypes.c_size_t(0)
+    check(lib().krr_rpchol_ws(kind, prec, N, d, r, B, m_max, ctypes.byref(b)))
+    return b.value
+
+
+def rpchol_build(kind, sigma, prec, X, mu, r, B=0, seed=0, m_max=1, ws=None):
+    """Blocked RPCholesky preconditioner for (A + mu I) beta = y."""
+    _f64(X)
+    N, d = X.shape
+    if ws is None:
+        ws = workspace(rpchol_ws(kind, prec, N, d, r, B, m_max), X.device)
+    h = ctypes.c_void_p(0)
+    check(lib().krr_rpchol_build(kind, float(sigma), prec, _ptr(X), N, d, float(mu), int(r),
+                                 int(B), ctypes.c_uint64(seed & (2 ** 64 - 1)), int(m_max), _ptr(ws),
+                                 ws.numel(), ctypes.byref(h), _stream(X.device)))
+    return Precond(h, ws, X, m_max, kind)
+
+
+def timing_enable(on=True):
+    check(lib().krr_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """(total ms, launches) of product tiles since the last read."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    check(lib().krr_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

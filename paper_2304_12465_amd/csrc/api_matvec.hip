@@ -1,0 +1,105 @@
+// C ABI: error state and the standalone kernel product.
+#include "product.h"
+#include <cmath>
+#include <cstring>
+
+namespace krr {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+static int validate_matvec(int kind, double sigma, int prec, int64_t nr, int64_t nc, int32_t d,
+                           int32_t m) {
+  if (kind != KRR_GAUSSIAN && kind != KRR_LAPLACE) {
+    set_error("unknown kernel kind %d", kind);
+    return KRR_EINVAL;
+  }
+  if (prec != KRR_FP64 && prec != KRR_FP32 && prec != KRR_MIXED) {
+    set_error("unknown precision %d", prec);
+    return KRR_EINVAL;
+  }
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) {
+    set_error("sigma must be positive and finite");
+    return KRR_EINVAL;
+  }
+  if (nr < 0 || nc < 0 || d < 1 || d > 64 || m < 1 || m > 64) {
+    set_error("invalid shape nr=%lld nc=%lld d=%d m=%d (need nr,nc >= 0, 1<=d<=64, 1<=m<=64)",
+              (long long)nr, (long long)nc, d, m);
+    return KRR_EINVAL;
+  }
+  return KRR_OK;
+}
+
+static size_t matvec_bytes(krr_kernel_kind kind, krr_precision prec, int64_t nr, int64_t nc,
+                           int32_t d, int32_t m) {
+  return pointset_bytes(kind, prec, nr, d) + pointset_bytes(kind, prec, nc, d) +
+         product_scratch_bytes(prec, nr, nc, m);
+}
+
+}  // namespace krr
+
+using namespace krr;
+
+extern "C" const char* krr_last_error(void) { return g_err; }
+
+extern "C" int krr_kernel_matvec_ws(krr_precision prec, int64_t nr, int64_t nc, int32_t d,
+                                    int32_t m, size_t* bytes) {
+  KRR_TRY(validate_matvec(KRR_LAPLACE, 1.0, prec, nr, nc, d, m));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return KRR_EINVAL;
+  }
+  // the Gaussian layout is at least as large as the Laplace one
+  size_t a = matvec_bytes(KRR_GAUSSIAN, prec, nr, nc, d, m);
+  size_t b = matvec_bytes(KRR_LAPLACE, prec, nr, nc, d, m);
+  *bytes = a > b ? a : b;
+  return KRR_OK;
+}
+
+extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                 const double* Xr, int64_t nr, const double* Xc, int64_t nc,
+                                 int32_t d, const double* V, int32_t m, double shift, double* W,
+                                 void* ws, size_t ws_bytes, hipStream_t stream) {
+  KRR_TRY(validate_matvec(kind, sigma, prec, nr, nc, d, m));
+  if (shift != 0.0 && nr != nc) {
+    set_error("shift != 0 needs a square product (nr == nc)");
+    return KRR_EINVAL;
+  }
+  if (!std::isfinite(shift)) {
+    set_error("shift must be finite");
+    return KRR_EINVAL;
+  }
+  if (nr == 0) return KRR_OK;
+  if (!W || (nc > 0 && (!Xc || !V)) || !Xr || (shift != 0.0 && !V)) {
+    set_error("NULL array argument");
+    return KRR_EINVAL;
+  }
+  const size_t need = matvec_bytes(kind, prec, nr, nc, d, m);
+  KRR_TRY(check_ws(ws, ws_bytes, need));
+  Arena arena(ws, ws_bytes);
+  PointSet rows, cols;
+  KRR_TRY(pack_points(kind, prec, Xr, nr, d, nullptr, arena, &rows, stream));
+  if (Xc == Xr && nc == nr) {
+    cols = rows;
+  } else {
+    KRR_TRY(pack_points(kind, prec, Xc, nc, d, nullptr, arena, &cols, stream));
+  }
+  VecView v{V, m, 1};
+  VecOut w{W, m, 1};
+  return product(kind, sigma, prec, rows, cols, v, m, shift, v, w, arena, stream);
+}
+
+extern "C" int krr_timing_enable(int on) {
+  tile_timing_enable(on != 0);
+  return KRR_OK;
+}
+
+extern "C" int krr_timing_read(double* total_ms, int64_t* launches) {
+  return tile_timing_read(total_ms, launches);
+}

@@ -1,0 +1,231 @@
+// C ABI: preconditioner builds, applications and the PCG solve.
+#include "solver.h"
+#include <cmath>
+#include <new>
+
+using namespace krr;
+
+struct krr_precond_s {
+  Precond P;
+};
+
+namespace {
+
+int check_kernel(int kind, double sigma, int prec) {
+  if (kind != KRR_GAUSSIAN && kind != KRR_LAPLACE) {
+    set_error("unknown kernel kind %d", kind);
+    return KRR_EINVAL;
+  }
+  if (prec != KRR_FP64 && prec != KRR_FP32 && prec != KRR_MIXED) {
+    set_error("unknown precision %d", prec);
+    return KRR_EINVAL;
+  }
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) {
+    set_error("sigma must be positive and finite");
+    return KRR_EINVAL;
+  }
+  return KRR_OK;
+}
+
+int rp_params(Precond& P, krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+              int32_t r, int32_t B, int32_t m_max) {
+  if (N < 1 || d < 1 || d > 64 || r < 1 || r > N || B < 0 || B > kBmax || m_max < 1 ||
+      m_max > 64) {
+    set_error("invalid RPCholesky shape N=%lld d=%d r=%d B=%d m_max=%d", (long long)N, d, r, B,
+              m_max);
+    return KRR_EINVAL;
+  }
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN && padded_dim(d) == 0) return KRR_EINVAL;
+  P.type = kRPChol;
+  P.kind = kind;
+  P.prec = prec;
+  P.N = N;
+  P.d = d;
+  P.r_req = r;
+  P.B = B > 0 ? B : std::min(100, (r + 9) / 10);
+  P.m_max = m_max;
+  return KRR_OK;
+}
+
+int finish_carve(Precond& P, void* ws, size_t ws_bytes, size_t need) {
+  KRR_TRY(check_ws(ws, ws_bytes, need));
+  P.ws_used = need;
+  return hip_check(hipHostMalloc((void**)&P.pcg.host, sizeof(double) * kScalars * P.m_max,
+                                 hipHostMallocDefault),
+                   "pinned host scalars");
+}
+
+int valid_precond(krr_precond P) {
+  if (!P) {
+    set_error("NULL precond");
+    return KRR_EINVAL;
+  }
+  return KRR_OK;
+}
+
+}  // namespace
+
+extern "C" int krr_rpchol_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+                             int32_t r, int32_t B, int32_t m_max, size_t* bytes) {
+  KRR_TRY(check_kernel(kind, 1.0, prec));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return KRR_EINVAL;
+  }
+  Precond P;
+  KRR_TRY(rp_params(P, kind, prec, N, d, r, B, m_max));
+  Arena a;
+  KRR_TRY(rpchol_layout(a, P));
+  *bytes = a.used;
+  return KRR_OK;
+}
+
+extern "C" int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                const double* X, int64_t N, int32_t d, double mu, int32_t r,
+                                int32_t B, uint64_t seed, int32_t m_max, void* ws,
+                                size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+  KRR_TRY(check_kernel(kind, sigma, prec));
+  if (!out || !X) {
+    set_error("NULL argument");
+    return KRR_EINVAL;
+  }
+  if (!(mu > 0.0) || !std::isfinite(mu)) {
+    set_error("mu must be positive and finite");
+    return KRR_EINVAL;
+  }
+  *out = nullptr;
+  krr_precond h = new (std::nothrow) krr_precond_s;
+  if (!h) {
+    set_error("out of host memory");
+    return KRR_EINVAL;
+  }
+  Precond& P = h->P;
+  int rc = rp_params(P, kind, prec, N, d, r, B, m_max);
+  if (rc == KRR_OK) {
+    P.sigma = sigma;
+    P.mu = mu;
+    P.seed = seed;
+    Arena meas;
+    rc = rpchol_layout(meas, P);
+    if (rc == KRR_OK) rc = finish_carve(P, ws, ws_bytes, meas.used);
+    if (rc == KRR_OK) {
+      Arena a(ws, ws_bytes);
+      rc = rpchol_layout(a, P);
+    }
+    if (rc == KRR_OK) rc = rpchol_build(P, X, stream);
+  }
+  if (rc != KRR_OK) {
+    krr_precond_free(h);
+    return rc;
+  }
+  *out = h;
+  return KRR_OK;
+}
+
+namespace {
+__global__ void lower_copy(const double* __restrict__ L, int64_t n, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t i = t / n, j = t % n;
+  out[t] = j <= i ? L[t] : 0.0;
+}
+}  // namespace
+
+extern "C" int krr_rpchol_factor(krr_precond h, double* FT, hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (P.type != kRPChol) {
+    set_error("not an RPCholesky preconditioner");
+    return KRR_EINVAL;
+  }
+  const int64_t rk = P.rank;
+  if (rk == 0) return KRR_OK;
+  if (!FT) {
+    set_error("NULL output");
+    return KRR_EINVAL;
+  }
+  const size_t mark = P.scratch.used;
+  double* L = P.scratch.take<double>((size_t)rk * rk);
+  if (!P.scratch.ok()) {
+    P.scratch.used = mark;
+    // fall back to the PCG direction vectors as staging (rank^2 <= N m_max)
+    if ((size_t)rk * rk > (size_t)P.N * P.m_max) {
+      set_error("no staging space for the factor export");
+      return KRR_EWORKSPACE;
+    }
+    L = P.pcg.p;
+  }
+  lower_copy<<<(unsigned)ceil_div(rk * rk, 256), 256, 0, stream>>>(P.core, rk, L);
+  KRR_LAUNCH_CHECK("lower_copy");
+  int rc = gemm_f64(false, rk, P.N, rk, 1.0, L, rk, P.QT, P.N, 0.0, FT, P.N, stream);
+  P.scratch.used = mark;
+  return rc;
+}
+
+extern "C" int krr_precond_dims(krr_precond h, int32_t* rank, int64_t* n) {
+  KRR_TRY(valid_precond(h));
+  const Precond& P = h->P;
+  if (rank) *rank = P.type == kRPChol ? P.rank : P.k;
+  if (n) *n = P.pcg.n;
+  return KRR_OK;
+}
+
+extern "C" int krr_precond_pivots(krr_precond h, int64_t* host_out, int32_t cap, int32_t* count) {
+  KRR_TRY(valid_precond(h));
+  const Precond& P = h->P;
+  const std::vector<int64_t>& v = P.type == kRPChol ? P.pivots : P.centers_host;
+  const int32_t n = (int32_t)v.size();
+  if (count) *count = n;
+  if (host_out)
+    for (int32_t i = 0; i < n && i < cap; ++i) host_out[i] = v[i];
+  return KRR_OK;
+}
+
+extern "C" int krr_precond_apply(krr_precond h, const double* Z, int32_t m, double* OUT,
+                                 hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (m < 1 || m > P.m_max || !Z || !OUT) {
+    set_error("invalid arguments (m=%d, m_max=%d)", m, P.m_max);
+    return KRR_EINVAL;
+  }
+  const int64_t n = P.pcg.n;
+  VecBlock R{P.pcg.r, n}, Zb{P.pcg.z, n};
+  KRR_TRY(to_colmajor(Z, n, m, R.p, stream));
+  KRR_TRY(apply_precond(P, R, m, Zb, stream));
+  return to_rowmajor(Zb.p, n, m, OUT, stream);
+}
+
+extern "C" int krr_precond_operator(krr_precond h, const double* V, int32_t m, double* OUT,
+                                    hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (m < 1 || m > P.m_max || !V || !OUT) {
+    set_error("invalid arguments (m=%d, m_max=%d)", m, P.m_max);
+    return KRR_EINVAL;
+  }
+  const int64_t n = P.pcg.n;
+  VecBlock Pv{P.pcg.p, n}, W{P.pcg.w, n};
+  KRR_TRY(to_colmajor(V, n, m, Pv.p, stream));
+  KRR_TRY(apply_operator(P, Pv, m, W, false, stream));
+  return to_rowmajor(W.p, n, m, OUT, stream);
+}
+
+extern "C" void krr_precond_free(krr_precond h) {
+  if (!h) return;
+  if (h->P.pcg.host) (void)hipHostFree(h->P.pcg.host);
+  delete h;
+}
+
+extern "C" int krr_pcg_solve(krr_precond h, const double* Y, int32_t m, double tol,
+                             int32_t max_iter, double* beta, krr_solve_info* info,
+                             hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (m < 1 || m > P.m_max || !Y || !beta || !(tol > 0.0) || max_iter < 0) {
+    set_error("invalid arguments (m=%d, m_max=%d, tol=%g, max_iter=%d)", m, P.m_max, tol,
+              max_iter);
+    return KRR_EINVAL;
+  }
+  return run_pcg(P, Y, m, tol, max_iter, beta, info, stream);
+}

@@ -1,0 +1,345 @@
+// FP64 dense linear algebra for the build steps of the method: the Woodbury
+// core F^T F + mu I (Alg. 1 preconditioner), its Cholesky factor, the KRILL
+// matrix B^T B + H and its Cholesky factor (Alg. 2), and the triangular
+// solves that apply them.  GEMM runs on the FP64 matrix cores.
+#include "la.h"
+#include <algorithm>
+
+namespace krr {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 64;   // output tile per workgroup (64 x 64)
+constexpr int kKStep = 16;  // K slice staged in LDS per iteration
+constexpr int kPad = 17;    // LDS row pitch in doubles
+
+// v_mfma_f64_16x16x4f64 operand layout (wave64):
+//   A (16 x 4): lane l holds A[l % 16][l / 16]
+//   B (4 x 16): lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l, element t holds D[4 t + l / 16][l % 16]
+template <bool BT>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
+                                                       double alpha, const double* __restrict__ A,
+                                                       int64_t lda, const double* __restrict__ B,
+                                                       int64_t ldb, double beta,
+                                                       double* __restrict__ C, int64_t ldc,
+                                                       int64_t kchunk, double* __restrict__ slots) {
+  __shared__ double As[kTile][kPad];  // [m][k]
+  __shared__ double Bs[kTile][kPad];  // [n][k]
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int ar = tid >> 2, ak = (tid & 3) * 4;  // A tile loader: 64 rows x 16 k
+  // split K: this workgroup covers [kb, ke); the bounds checks below use ke
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+    {
+      const int64_t gm = m0 + ar;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gk = k0 + ak + u;
+        As[ar][ak + u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
+      }
+    }
+    if (BT) {
+      const int64_t gn = n0 + ar;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gk = k0 + ak + u;
+        Bs[ar][ak + u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, nn = (tid & 15) * 4;  // 16 k x 64 n
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gn = n0 + nn + u;
+        Bs[nn + u][kk] = (gk < ke && gn < N) ? B[gk * ldb + gn] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKStep; ks += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t gm = m0 + wm + i * 16 + 4 * t + (lane >> 4);
+        const int64_t gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          double v = alpha * acc[i][j][t];
+          if (slots) {
+            slots[((int64_t)blockIdx.z * M + gm) * N + gn] = v;
+          } else {
+            if (beta != 0.0) v += beta * C[gm * ldc + gn];
+            C[gm * ldc + gn] = v;
+          }
+        }
+      }
+}
+
+// C = sum_z slots[z] (fixed order) + beta C
+__global__ __launch_bounds__(256) void splitk_reduce(const double* __restrict__ slots, int nz,
+                                                     int64_t M, int64_t N, double beta,
+                                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * N) return;
+  const int64_t m = t / N, n = t % N;
+  double v = 0.0;
+  for (int z = 0; z < nz; ++z) v += slots[((int64_t)z * M + m) * N + n];
+  if (beta != 0.0) v += beta * C[m * ldc + n];
+  C[m * ldc + n] = v;
+}
+
+int choose_ksplit(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(M, kTile) * ceil_div(N, kTile);
+  if (tiles >= 512 || K < 8192) return 1;
+  int64_t z = ceil_div(1024, tiles);
+  z = std::min<int64_t>(z, K / 2048);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(z, 4096));
+}
+
+constexpr int kNb = 64;  // block size of the blocked factorisation and solves
+
+// Cholesky of one nb x nb diagonal block held in LDS (right-looking).
+__global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ A, int64_t lda, int nb,
+                                                  int64_t col0, int* __restrict__ info) {
+  __shared__ double T[kNb][kNb + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = A[(e / nb) * lda + e % nb];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (tid == 0) {
+      const double p = T[k][k];
+      if (!(p > 0.0)) {
+        if (!bad) bad = (int)(col0 + k + 1);
+        T[k][k] = 1.0;  // keep going with finite values; info reports the failure
+      } else {
+        T[k][k] = sqrt(p);
+      }
+    }
+    __syncthreads();
+    const double piv = T[k][k];
+    for (int i = k + 1 + tid; i < nb; i += blockDim.x) T[i][k] /= piv;
+    __syncthreads();
+    const int rem = nb - k - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      if (j <= i) T[i][j] -= T[i][k] * T[j][k];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    if (j <= i) A[i * lda + j] = T[i][j];
+  }
+  if (tid == 0 && bad && *info == 0) *info = bad;
+}
+
+// Rows below the diagonal block: L_i = A_i L_kk^{-T}, one thread per row.
+__global__ __launch_bounds__(256) void potrf_panel(double* __restrict__ A, int64_t lda, int nb,
+                                                   int64_t nrows) {
+  __shared__ double L[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  // A points at the diagonal block; panel rows start nb rows below
+  for (int e = tid; e < nb * nb; e += blockDim.x) L[e / nb][e % nb] = A[(e / nb) * lda + e % nb];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (r >= nrows) return;
+  double* row = A + (nb + r) * lda;
+  double x[kNb];
+#pragma unroll 8
+  for (int q = 0; q < nb; ++q) x[q] = row[q];
+  for (int q = 0; q < nb; ++q) {
+    double s = x[q];
+    for (int p = 0; p < q; ++p) s -= x[p] * L[q][p];
+    x[q] = s / L[q][q];
+  }
+#pragma unroll 8
+  for (int q = 0; q < nb; ++q) row[q] = x[q];
+}
+
+// One block of a lower-triangular solve with many right-hand sides:
+// B_blk <- L_blk^{-1} B_blk (forward) or L_blk^{-T} B_blk (backward),
+// one thread per right-hand-side column.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void trsm_diag(const double* __restrict__ L, int64_t lda, int nb,
+                                                 double* __restrict__ B, int64_t ldb,
+                                                 int64_t ncols) {
+  __shared__ double T[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = L[(e / nb) * lda + e % nb];
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (c >= ncols) return;
+  double x[kNb];
+  for (int q = 0; q < nb; ++q) x[q] = B[q * ldb + c];
+  if (!TRANS) {
+    for (int q = 0; q < nb; ++q) {
+      double s = x[q];
+      for (int p = 0; p < q; ++p) s -= T[q][p] * x[p];
+      x[q] = s / T[q][q];
+    }
+  } else {
+    for (int q = nb - 1; q >= 0; --q) {
+      double s = x[q];
+      for (int p = q + 1; p < nb; ++p) s -= T[p][q] * x[p];
+      x[q] = s / T[q][q];
+    }
+  }
+  for (int q = 0; q < nb; ++q) B[q * ldb + c] = x[q];
+}
+
+// C[M x N] -= A^T-block product for the transposed backward solve:
+// C = C - Lsub^T * X where Lsub is K x M (row-major, lda) and X is K x N.
+__global__ __launch_bounds__(256) void gemm_tn_sub(int64_t M, int64_t N, int64_t K,
+                                                   const double* __restrict__ Lsub, int64_t lda,
+                                                   const double* __restrict__ X, int64_t ldx,
+                                                   double* __restrict__ C, int64_t ldc) {
+  // small-M path used by the backward solve: thread per (m, n)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * N) return;
+  const int64_t m = t / N, n = t % N;
+  double s = 0.0;
+  for (int64_t k = 0; k < K; ++k) s += Lsub[k * lda + m] * X[k * ldx + n];
+  C[m * ldc + n] -= s;
+}
+
+}  // namespace
+
+size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
+  const int z = choose_ksplit(M, N, K);
+  return z > 1 ? align_up((size_t)z * M * N * sizeof(double)) : 0;
+}
+
+int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+             int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+             hipStream_t s, Arena* scratch) {
+  if (M <= 0 || N <= 0) return KRR_OK;
+  const int64_t gx = ceil_div(N, kTile), gy = ceil_div(M, kTile);
+  if (gy > 65535) {
+    set_error("gemm_f64: M=%lld too large for the grid", (long long)M);
+    return KRR_EINVAL;
+  }
+  int z = scratch ? choose_ksplit(M, N, K) : 1;
+  double* slots = nullptr;
+  const size_t mark = scratch ? scratch->used : 0;
+  if (z > 1) {
+    slots = scratch->take<double>((size_t)z * M * N);
+    if (!scratch->ok()) {
+      scratch->used = mark;
+      z = 1;
+      slots = nullptr;
+    }
+  }
+  const int64_t kchunk = z > 1 ? ceil_div(ceil_div(K, z), kKStep) * kKStep : std::max<int64_t>(K, 1);
+  z = (int)std::max<int64_t>(1, ceil_div(K, kchunk));
+  if (z == 1 && slots) {
+    slots = nullptr;
+    scratch->used = mark;
+  }
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)z);
+  if (b_trans)
+    gemm_f64_kernel<true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                               kchunk, slots);
+  else
+    gemm_f64_kernel<false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                kchunk, slots);
+  KRR_LAUNCH_CHECK("gemm_f64");
+  if (slots) {
+    splitk_reduce<<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(slots, z, M, N, beta, C, ldc);
+    KRR_LAUNCH_CHECK("splitk_reduce");
+    scratch->used = mark;
+  }
+  return KRR_OK;
+}
+
+int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s) {
+  KRR_TRY(hip_check(hipMemsetAsync(info, 0, sizeof(int), s), "potrf info reset"));
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    double* Akk = A + k * lda + k;
+    potrf_diag<<<1, 256, 0, s>>>(Akk, lda, nb, k, info);
+    KRR_LAUNCH_CHECK("potrf_diag");
+    const int64_t rest = n - k - nb;
+    if (rest > 0) {
+      potrf_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(Akk, lda, nb, rest);
+      KRR_LAUNCH_CHECK("potrf_panel");
+      // trailing update A22 -= L21 L21^T (full square keeps A22 symmetric)
+      double* L21 = A + (k + nb) * lda + k;
+      double* A22 = A + (k + nb) * lda + (k + nb);
+      KRR_TRY(gemm_f64(true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, s));
+    }
+  }
+  return KRR_OK;
+}
+
+int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
+                    int64_t ldb, hipStream_t s) {
+  if (ncols <= 0 || n <= 0) return KRR_OK;
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    if (k > 0) {
+      // B_k -= L[k, 0:k] B[0:k]
+      KRR_TRY(gemm_f64(false, nb, ncols, k, -1.0, L + k * lda, lda, B, ldb, 1.0, B + k * ldb, ldb,
+                       s));
+    }
+    trsm_diag<false><<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
+                                                                    B + k * ldb, ldb, ncols);
+    KRR_LAUNCH_CHECK("trsm_diag");
+  }
+  return KRR_OK;
+}
+
+int trsm_lower_left_trans(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
+                          int64_t ldb, hipStream_t s) {
+  if (ncols <= 0 || n <= 0) return KRR_OK;
+  const int64_t nblk = ceil_div(n, kNb);
+  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
+    const int64_t k = bk * kNb;
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    const int64_t below = n - k - nb;
+    if (below > 0) {
+      // B_k -= L[k+nb:, k:k+nb]^T B[k+nb:]
+      const int64_t tot = (int64_t)nb * ncols;
+      gemm_tn_sub<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(nb, ncols, below,
+                                                              L + (k + nb) * lda + k, lda,
+                                                              B + (k + nb) * ldb, ldb,
+                                                              B + k * ldb, ldb);
+      KRR_LAUNCH_CHECK("gemm_tn_sub");
+    }
+    trsm_diag<true><<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
+                                                                   B + k * ldb, ldb, ncols);
+    KRR_LAUNCH_CHECK("trsm_diag<T>");
+  }
+  return KRR_OK;
+}
+
+}  // namespace krr

@@ -1,0 +1,401 @@
+// Preconditioned conjugate gradient (zero initial iterate, relative-residual
+// stop; Sec. 3, eq. psd_system) with m independent right-hand sides, and the
+// operator / preconditioner applications it calls (Alg. 1 and Alg. 2).
+//
+// Vectors live column-major in HBM (vector c of length n at p + c*n) so
+// every update and dot product streams contiguous memory.  Dot products are
+// two-stage with fixed per-block slots and a fixed-order final sum, so the
+// recurrence is bitwise reproducible run to run and independent of what
+// else shares the GPU.  CG scalars are FP64.
+#include "solver.h"
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace krr {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// part[c*nblk + blk] = sum over this block's rows of A_c * B_c
+__global__ __launch_bounds__(kThreads) void dot_part(const double* __restrict__ A,
+                                                     const double* __restrict__ B, int64_t n,
+                                                     int64_t chunk, int nblk,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.y, blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * chunk;
+  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  const double* a = A + (int64_t)c * n;
+  const double* b = B + (int64_t)c * n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) s += a[i] * b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(int64_t)c * nblk + blk] = s;
+}
+
+// x += alpha p; r -= alpha w; part = partial sums of r^2 (new r)
+__global__ __launch_bounds__(kThreads) void update_xr(double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ scal, int m_max,
+                                                      int64_t n, int64_t chunk, int nblk,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.y, blk = blockIdx.x;
+  const double alpha = scal[kAlpha * m_max + c];
+  const int64_t i0 = (int64_t)blk * chunk;
+  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  const int64_t off = (int64_t)c * n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    x[off + i] += alpha * p[off + i];
+    const double rv = r[off + i] - alpha * w[off + i];
+    r[off + i] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(int64_t)c * nblk + blk] = s;
+}
+
+// p = active ? z + beta p : 0
+__global__ __launch_bounds__(kThreads) void update_p(double* __restrict__ p,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ scal, int m_max,
+                                                     int64_t n) {
+  const int c = blockIdx.y;
+  const double beta = scal[kBeta * m_max + c];
+  const bool act = scal[kActive * m_max + c] != 0.0;
+  const int64_t off = (int64_t)c * n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[off + i] = act ? z[off + i] + beta * p[off + i] : 0.0;
+}
+
+enum FinalOp { kFinPW = 0, kFinRR = 1, kFinRZ = 2, kFinInit = 3, kFinSum = 4 };
+
+// One thread per column: sums the partial slots in a fixed order and applies
+// the scalar step of the recurrence.
+__global__ void finalize(const double* __restrict__ part, int nblk, int m, int m_max, int op,
+                         double tol2, int slot, double* __restrict__ scal) {
+  const int c = threadIdx.x;
+  if (c >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)c * nblk + b];
+  double* S = scal;
+  const bool act = S[kActive * m_max + c] != 0.0;
+  switch (op) {
+    case kFinPW:
+      S[kPW * m_max + c] = s;
+      S[kAlpha * m_max + c] = act ? S[kRZ * m_max + c] / s : 0.0;
+      break;
+    case kFinRR:
+      S[kRR * m_max + c] = s;
+      S[kActive * m_max + c] = (act && s > tol2 * S[kBB * m_max + c]) ? 1.0 : 0.0;
+      break;
+    case kFinRZ: {
+      const bool a2 = act;
+      S[kRZnew * m_max + c] = s;
+      S[kBeta * m_max + c] = a2 ? s / S[kRZ * m_max + c] : 0.0;
+      if (a2) S[kRZ * m_max + c] = s;
+      break;
+    }
+    case kFinInit:  // s = ||b||^2
+      S[kBB * m_max + c] = s;
+      S[kRR * m_max + c] = s;
+      S[kActive * m_max + c] = s > 0.0 ? 1.0 : 0.0;
+      break;
+    default:
+      S[slot * m_max + c] = s;
+  }
+}
+
+__global__ void colmajor_from_rowmajor(const double* __restrict__ src, int64_t n, int m,
+                                       double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * m) return;
+  const int64_t i = t / m;
+  const int c = (int)(t % m);
+  dst[(int64_t)c * n + i] = src[t];
+}
+
+__global__ void rowmajor_from_colmajor(const double* __restrict__ src, int64_t n, int m,
+                                       double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * m) return;
+  const int64_t i = t / m;
+  const int c = (int)(t % m);
+  dst[t] = src[(int64_t)c * n + i];
+}
+
+__global__ void axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
+                      int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) y[t] = a * x[t] + b * y[t];
+}
+
+__global__ void fill(double* __restrict__ y, double v, int64_t len) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < len) y[t] = v;
+}
+
+int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(n, 2048))); }
+
+struct Red {
+  int nblk;
+  int64_t chunk;
+};
+Red red_for(int64_t n) {
+  Red r;
+  r.nblk = blocks_for(n);
+  r.chunk = ceil_div(std::max<int64_t>(n, 1), r.nblk);
+  return r;
+}
+
+int dot_cols(const PcgState& st, const double* A, const double* B, int m, int op, double tol2,
+             int slot, hipStream_t s) {
+  const Red rd = red_for(st.n);
+  dim3 g((unsigned)rd.nblk, (unsigned)m);
+  dot_part<<<g, kThreads, 0, s>>>(A, B, st.n, rd.chunk, rd.nblk, st.part);
+  KRR_LAUNCH_CHECK("dot_part");
+  finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, m, st.m_max, op, tol2, slot, st.scal);
+  KRR_LAUNCH_CHECK("finalize");
+  return KRR_OK;
+}
+
+}  // namespace
+
+int to_colmajor(const double* src, int64_t n, int32_t m, double* dst, hipStream_t s) {
+  if (n * m == 0) return KRR_OK;
+  colmajor_from_rowmajor<<<(unsigned)ceil_div(n * m, 256), 256, 0, s>>>(src, n, m, dst);
+  KRR_LAUNCH_CHECK("colmajor_from_rowmajor");
+  return KRR_OK;
+}
+
+int to_rowmajor(const double* src, int64_t n, int32_t m, double* dst, hipStream_t s) {
+  if (n * m == 0) return KRR_OK;
+  rowmajor_from_colmajor<<<(unsigned)ceil_div(n * m, 256), 256, 0, s>>>(src, n, m, dst);
+  KRR_LAUNCH_CHECK("rowmajor_from_colmajor");
+  return KRR_OK;
+}
+
+size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_restricted, int32_t rank) {
+  Arena a;
+  PcgState st;
+  pcg_carve(a, st, n, m_max, N_restricted, rank);
+  return a.used;
+}
+
+void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_restricted,
+               int32_t rank) {
+  st.m_max = m_max;
+  st.n = n;
+  const size_t v = (size_t)std::max<int64_t>(n, 1) * m_max;
+  st.x = a.take<double>(v);
+  st.r = a.take<double>(v);
+  st.z = a.take<double>(v);
+  st.p = a.take<double>(v);
+  st.w = a.take<double>(v);
+  st.b = a.take<double>(v);
+  st.scal = a.take<double>((size_t)kScalars * m_max);
+  st.nblk = blocks_for(n);
+  st.part = a.take<double>((size_t)st.nblk * m_max);
+  st.tmpN = N_restricted > 0 ? a.take<double>((size_t)N_restricted * m_max) : nullptr;
+  st.tmpR = rank > 0 ? a.take<double>((size_t)rank * m_max) : nullptr;
+}
+
+int apply_operator(Precond& P, VecBlock V, int32_t m, VecBlock W, bool force64, hipStream_t s) {
+  const krr_precision pr = force64 ? KRR_FP64 : P.prec;
+  if (P.type == kRPChol) {
+    const PointSet& ps = force64 ? P.pts64 : P.pts;
+    return product(P.kind, P.sigma, pr, ps, ps, V.view(), m, P.mu, V.view(), W.out(), P.scratch,
+                   s);
+  }
+  // restricted: t = K_NS V, W = K_SN t + H V
+  const PointSet& xs = force64 ? P.pts64 : P.pts;
+  const PointSet& cs = force64 ? P.cpts64 : P.cpts;
+  VecBlock t{P.pcg.tmpN, P.N};
+  KRR_TRY(product(P.kind, P.sigma, pr, xs, cs, V.view(), m, 0.0, V.view(), t.out(), P.scratch, s));
+  KRR_TRY(product(P.kind, P.sigma, pr, cs, xs, t.view(), m, 0.0, t.view(), W.out(), P.scratch, s));
+  // W^T (m x k) += V^T (m x k) H  (H symmetric)
+  return gemm_f64(false, m, P.k, P.k, 1.0, V.p, P.k, P.H, P.k, 1.0, W.p, P.k, s, &P.scratch);
+}
+
+int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) {
+  if (P.type == kRPChol) {
+    // Woodbury form of (F F^T + mu I)^{-1}:  z = (r - Q (Q^T r)) / mu.
+    const int64_t N = P.N;
+    const int32_t rk = P.rank;
+    const double imu = 1.0 / P.mu;
+    if (Z.p != R.p)
+      KRR_TRY(hip_check(hipMemcpyAsync(Z.p, R.p, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s),
+                        "copy r"));
+    if (rk == 0) {
+      axpby<<<(unsigned)ceil_div(N * m, 256), 256, 0, s>>>(Z.p, Z.p, imu, 0.0, N * m);
+      KRR_LAUNCH_CHECK("axpby");
+      return KRR_OK;
+    }
+    double* TT = P.pcg.tmpR;  // m x rank: T^T = R^T Q
+    KRR_TRY(gemm_f64(true, m, rk, N, 1.0, R.p, N, P.QT, N, 0.0, TT, rk, s, &P.scratch));
+    // Z^T = R^T / mu - (1/mu) T^T Q^T
+    return gemm_f64(false, m, N, rk, -imu, TT, rk, P.QT, N, imu, Z.p, N, s, &P.scratch);
+  }
+  // KRILL: z = C^{-1} C^{-T} r with P = C^T C, C = L^T (lower L stored).
+  const int64_t k = P.k;
+  double* tmp = P.pcg.tmpN;  // k x m row-major staging (tmpN holds N >= k rows x m)
+  KRR_TRY(to_rowmajor(R.p, k, m, tmp, s));
+  KRR_TRY(trsm_lower_left(k, m, P.C, k, tmp, m, s));
+  KRR_TRY(trsm_lower_left_trans(k, m, P.C, k, tmp, m, s));
+  return to_colmajor(tmp, k, m, Z.p, s);
+}
+
+int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s) {
+  if (P.type == kRPChol) return to_colmajor(Y, P.N, m, B.p, s);
+  // b = A(S,:) y, evaluated in FP64 (Alg. 2, last step)
+  VecView y{Y, m, 1};
+  return product(P.kind, P.sigma, KRR_FP64, P.cpts64, P.pts64, y, m, 0.0, y, B.out(), P.scratch,
+                 s);
+}
+
+int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
+            krr_solve_info* info, hipStream_t s) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  PcgState& st = P.pcg;
+  const int64_t n = st.n;
+  const int mm = st.m_max;
+  const int64_t len = n * m;
+  const double tol2 = tol * tol;
+  VecBlock X{st.x, n}, R{st.r, n}, Z{st.z, n}, Pv{st.p, n}, W{st.w, n}, Bv{st.b, n};
+
+  KRR_TRY(system_rhs(P, Y, m, Bv, s));
+  fill<<<(unsigned)ceil_div(len, 256), 256, 0, s>>>(st.x, 0.0, len);
+  KRR_LAUNCH_CHECK("fill");
+  KRR_TRY(hip_check(hipMemcpyAsync(st.r, st.b, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                    "r = b"));
+  KRR_TRY(dot_cols(st, st.b, st.b, m, kFinInit, 0, 0, s));
+  KRR_TRY(apply_precond(P, R, m, Z, s));
+  KRR_TRY(dot_cols(st, st.r, st.z, m, kFinSum, 0, kRZ, s));
+  KRR_TRY(hip_check(hipMemcpyAsync(st.p, st.z, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                    "p = z"));
+
+  std::vector<int32_t> iters(m, 0);
+  std::vector<char> active(m, 0);
+  auto pull = [&]() -> int {
+    KRR_TRY(hip_check(hipMemcpyAsync(st.host, st.scal, sizeof(double) * kScalars * mm,
+                                     hipMemcpyDeviceToHost, s),
+                      "scalars D2H"));
+    return hip_check(hipStreamSynchronize(s), "stream sync");
+  };
+  KRR_TRY(pull());
+  for (int c = 0; c < m; ++c) active[c] = st.host[kActive * mm + c] != 0.0;
+  if (info && info->history) info->history_len = 0;
+
+  const Red rd = red_for(n);
+  int it = 0;
+  int restarts = 0;
+  double worst_true = 0.0;
+  for (;;) {
+    while (it < max_iter && std::any_of(active.begin(), active.end(), [](char a) { return a; })) {
+      KRR_TRY(apply_operator(P, Pv, m, W, false, s));
+      KRR_TRY(dot_cols(st, st.p, st.w, m, kFinPW, 0, 0, s));
+      update_xr<<<dim3((unsigned)rd.nblk, (unsigned)m), kThreads, 0, s>>>(
+          st.x, st.r, st.p, st.w, st.scal, mm, n, rd.chunk, rd.nblk, st.part);
+      KRR_LAUNCH_CHECK("update_xr");
+      finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, m, mm, kFinRR, tol2, 0, st.scal);
+      KRR_LAUNCH_CHECK("finalize rr");
+      KRR_TRY(pull());
+      ++it;
+      double worst = 0.0;
+      for (int c = 0; c < m; ++c) {
+        if (active[c]) iters[c] = it;
+        const double rr = st.host[kRR * mm + c], bb = st.host[kBB * mm + c];
+        if (!std::isfinite(rr)) {
+          set_error("NaN/Inf in the residual of column %d at iteration %d", c, it);
+          return KRR_ENAN;
+        }
+        if (bb > 0) worst = std::max(worst, std::sqrt(rr / bb));
+        active[c] = st.host[kActive * mm + c] != 0.0;
+      }
+      if (info && info->history && info->history_len < info->history_cap)
+        info->history[info->history_len++] = worst;
+      if (!std::any_of(active.begin(), active.end(), [](char a) { return a; })) break;
+      KRR_TRY(apply_precond(P, R, m, Z, s));
+      KRR_TRY(dot_cols(st, st.r, st.z, m, kFinRZ, 0, 0, s));
+      update_p<<<dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096), (unsigned)m), kThreads,
+                 0, s>>>(st.p, st.z, st.scal, mm, n);
+      KRR_LAUNCH_CHECK("update_p");
+    }
+    // True residual b - M x with an FP64 product.
+    KRR_TRY(apply_operator(P, X, m, W, true, s));
+    axpby<<<(unsigned)ceil_div(len, 256), 256, 0, s>>>(st.w, st.b, 1.0, -1.0, len);  // w = b - w
+    KRR_LAUNCH_CHECK("axpby");
+    KRR_TRY(dot_cols(st, st.w, st.w, m, kFinSum, 0, kTrue, s));
+    KRR_TRY(pull());
+    worst_true = 0.0;
+    bool replace = false;
+    for (int c = 0; c < m; ++c) {
+      const double bb = st.host[kBB * mm + c];
+      if (bb <= 0) continue;
+      const double rt = std::sqrt(st.host[kTrue * mm + c] / bb);
+      worst_true = std::max(worst_true, rt);
+      if (P.prec == KRR_FP64 && rt > 10.0 * tol) replace = true;
+    }
+    // One residual-replacement restart on the FP64 path when the recursive
+    // residual drifted away from the true one.
+    if (!replace || restarts >= 1 || it >= max_iter) break;
+    ++restarts;
+    KRR_TRY(hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                      "r = true residual"));
+    KRR_TRY(dot_cols(st, st.r, st.r, m, kFinSum, 0, kRR, s));
+    KRR_TRY(apply_precond(P, R, m, Z, s));
+    KRR_TRY(dot_cols(st, st.r, st.z, m, kFinSum, 0, kRZ, s));
+    KRR_TRY(hip_check(hipMemcpyAsync(st.p, st.z, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                      "p = z"));
+    KRR_TRY(pull());
+    for (int c = 0; c < m; ++c) {
+      const double bb = st.host[kBB * mm + c];
+      active[c] = bb > 0 && st.host[kRR * mm + c] > tol2 * bb;
+      st.host[kActive * mm + c] = active[c] ? 1.0 : 0.0;
+    }
+    KRR_TRY(hip_check(hipMemcpyAsync(st.scal + kActive * mm, st.host + kActive * mm,
+                                     sizeof(double) * mm, hipMemcpyHostToDevice, s),
+                      "active H2D"));
+  }
+  KRR_TRY(to_rowmajor(st.x, n, m, beta, s));
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "stream sync"));
+  double worst_rec = 0.0;
+  int conv = 0;
+  for (int c = 0; c < m; ++c) {
+    const double bb = st.host[kBB * mm + c];
+    const double rr = st.host[kRR * mm + c];
+    const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    worst_rec = std::max(worst_rec, rel);
+    if (rel <= tol) ++conv;
+  }
+  if (info) {
+    info->iters = *std::max_element(iters.begin(), iters.end());
+    info->converged_cols = conv;
+    info->relres_recursive = worst_rec;
+    info->relres_true = worst_true;
+    info->build_seconds = P.build_seconds;
+    info->solve_seconds = std::chrono::duration<double>(clk::now() - t0).count();
+  }
+  return conv == m ? KRR_OK : KRR_NOT_CONVERGED;
+}
+
+}  // namespace krr

@@ -1,0 +1,62 @@
+// Internal interface of the matrix-free kernel product engine.
+#pragma once
+#include "common.h"
+
+namespace krr {
+
+// A point set in the compute layout of one precision: n x dpad, zero padded
+// from d to dpad (zero coordinates add nothing to either distance).
+struct PointSet {
+  int64_t n = 0;
+  int32_t d = 0;
+  int32_t dpad = 0;
+  const double* x64 = nullptr;  // FP64 layout (KRR_FP64)
+  const float* x32 = nullptr;   // FP32 layout (KRR_FP32, Laplace under KRR_MIXED)
+  // bf16 hi/lo split and FP32 squared norms (Gaussian under KRR_MIXED)
+  const uint16_t* xhi = nullptr;  // n x kpad bf16 bits
+  const uint16_t* xlo = nullptr;
+  const float* nrm = nullptr;     // n, ||x||^2 in FP32 of the centred point
+  int32_t kpad = 0;
+};
+
+int padded_dim(int32_t d);                       // 0 if d unsupported
+int mfma_kdim(int32_t d);                        // bf16 K padding (multiple of 32)
+
+// Bytes of the packed layout for one precision and kernel.
+size_t pointset_bytes(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d);
+// Carves the layout `prec` needs for n points of dimension d from `arena`
+// (no GPU work; with a measuring arena only the size is recorded).
+int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d, Arena& arena,
+                 PointSet* out);
+// Fills a carved layout from FP64 points X (n x d, row-major, device).
+// `centre` (d doubles, device, or null) is subtracted first.
+int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* centre,
+                const PointSet& ps, hipStream_t s);
+// carve_points + fill_points.
+int pack_points(krr_kernel_kind kind, krr_precision prec, const double* X, int64_t n, int32_t d,
+                const double* centre, Arena& arena, PointSet* out, hipStream_t s);
+
+// Scratch bytes for product(rows=nr, cols=nc, m).
+size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t m);
+
+// Strided view of a block of m vectors: element (i, c) at p[i*rs + c*cs].
+struct VecView {
+  const double* p = nullptr;
+  int64_t rs = 1, cs = 1;
+};
+struct VecOut {
+  double* p = nullptr;
+  int64_t rs = 1, cs = 1;
+};
+
+// W = K(rows, cols) V + shift * Vs  (V: cols.n x m, Vs and W: rows.n x m).
+// Deterministic reduction order.
+int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointSet& rows,
+            const PointSet& cols, VecView V, int32_t m, double shift, VecView Vs, VecOut W,
+            Arena& scratch, hipStream_t s);
+
+// Event timing of the product tile kernel launches (process-wide).
+void tile_timing_enable(bool on);
+int tile_timing_read(double* total_ms, int64_t* launches);
+
+}  // namespace krr

@@ -1,0 +1,437 @@
+// VALU kernel tiles for the matrix-free product W = K(Xr, Xc) V (+ shift V).
+//
+// Design (gfx950, wave64):
+//  * Each lane owns R rows of the output.  Its R points stay in VGPRs for
+//    the whole launch; the wave sweeps a contiguous range of columns.
+//  * A column's point and its V row are wave-uniform, so they are read with
+//    scalar loads and enter VALU instructions as SGPR operands: no LDS
+//    traffic and no VGPRs for column data.  Four waves of a workgroup walk
+//    the same columns at the same time and share the scalar cache.
+//  * Entries are computed by direct differences (Laplace: |x-y| summed;
+//    Gaussian: (x-y)^2 summed), exponentiated and reduced against V at once:
+//    the kernel matrix is never stored.
+//  * FP32 tiles sum at most 256 columns in FP32, then fold into FP64
+//    accumulators.  Per-split partial sums go to fixed slots and a second
+//    kernel adds them in a fixed order, so results are bitwise reproducible
+//    and independent of scheduling.
+#include "product.h"
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+namespace krr {
+
+namespace {
+
+constexpr int kWaves = 4;           // waves per workgroup
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float abs_t(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double abs_t(double a) { return __builtin_fabs(a); }
+constexpr int kFold = 256;          // FP32 columns per FP64 fold
+
+template <int KIND, typename T, int D, int M, int R>
+__global__ __launch_bounds__(256) void tile_valu(const T* __restrict__ Xr, int64_t nr,
+                                                 const T* __restrict__ Xc,
+                                                 const T* __restrict__ Vc, int64_t nc,
+                                                 T scale, int nsplit, int64_t cols_per_split,
+                                                 double* __restrict__ part) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t bid = blockIdx.x;
+  const int split = (int)(bid % nsplit);
+  const int64_t rg = bid / nsplit;
+  const int64_t row0 = (rg * kWaves + wave) * 64 * R;
+  if (row0 >= nr) return;  // whole wave idle (wave-uniform)
+
+  T x[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int64_t i = row0 + lane + 64 * r;
+    if (i > nr - 1) i = nr - 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[r][k] = Xr[i * D + k];
+  }
+  double acc64[R][M];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc64[r][c] = 0.0;
+
+  const int64_t j0 = (int64_t)split * cols_per_split;
+  int64_t j1 = j0 + cols_per_split;
+  if (j1 > nc) j1 = nc;
+
+  for (int64_t jb = j0; jb < j1; jb += kFold) {
+    const int64_t je = (jb + kFold < j1) ? jb + kFold : j1;
+    T acc[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[r][c] = T(0);
+#pragma unroll 2
+    for (int64_t j = jb; j < je; ++j) {
+      const T* __restrict__ xc = Xc + j * D;
+      const T* __restrict__ vc = Vc + j * M;
+      T y[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) y[k] = xc[k];
+      T v[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) v[c] = vc[c];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // two interleaved partial sums break the dependency chain
+        T s0, s1 = T(0);
+#pragma unroll
+        for (int k = 0; k < D; k += 2) {
+          const T t0 = x[r][k] - y[k];
+          const T a0 = KIND == KRR_LAPLACE ? abs_t(t0) : t0 * t0;
+          s0 = k == 0 ? a0 : (KIND == KRR_LAPLACE ? s0 + a0 : fma_t(t0, t0, s0));
+          if (k + 1 < D) {
+            const T t1 = x[r][k + 1] - y[k + 1];
+            const T a1 = KIND == KRR_LAPLACE ? abs_t(t1) : t1 * t1;
+            s1 = k == 0 ? a1 : (KIND == KRR_LAPLACE ? s1 + a1 : fma_t(t1, t1, s1));
+          }
+        }
+        T e;
+        if constexpr (sizeof(T) == 4) e = __builtin_amdgcn_exp2f((s0 + s1) * scale);
+        else e = exp((s0 + s1) * scale);
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[r][c] = fma_t(e, v[c], acc[r][c]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc64[r][c] += (double)acc[r][c];
+  }
+  double* __restrict__ out = part + (int64_t)split * nr * M;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int64_t i = row0 + lane + 64 * r;
+    if (i < nr) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) out[i * M + c] = acc64[r][c];
+    }
+  }
+}
+
+// W[i, c0+c] = sum_s part[s, i, c] + shift * Vs[i, c0+c], fixed order over s.
+__global__ __launch_bounds__(256) void reduce_splits(const double* __restrict__ part, int nsplit,
+                                                     int64_t nr, int M, int mc, int c0,
+                                                     double shift, VecView Vs, VecOut W) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nr * mc) return;
+  const int64_t i = t / mc;
+  const int c = (int)(t % mc);
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * nr + i) * M + c];
+  if (shift != 0.0) s += shift * Vs.p[i * Vs.rs + (int64_t)(c0 + c) * Vs.cs];
+  W.p[i * W.rs + (int64_t)(c0 + c) * W.cs] = s;
+}
+
+template <typename T>
+__global__ void pack_pts(const double* __restrict__ X, int64_t n, int d, int dpad,
+                         const double* __restrict__ centre, T* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * dpad) return;
+  const int64_t i = t / dpad;
+  const int k = (int)(t % dpad);
+  double v = 0.0;
+  if (k < d) v = X[i * d + k] - (centre ? centre[k] : 0.0);
+  out[t] = (T)v;
+}
+
+// Vp[j, c] = V[j, c0 + c] for c < mc, 0 for mc <= c < M.
+template <typename T>
+__global__ void pack_vec(VecView V, int64_t n, int c0, int mc, int M, T* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * M) return;
+  const int64_t j = t / M;
+  const int c = (int)(t % M);
+  out[t] = (c < mc) ? (T)V.p[j * V.rs + (int64_t)(c0 + c) * V.cs] : T(0);
+}
+
+using TileFn32 = void (*)(const float*, int64_t, const float*, const float*, int64_t, float, int,
+                          int64_t, double*);
+using TileFn64 = void (*)(const double*, int64_t, const double*, const double*, int64_t, double,
+                          int, int64_t, double*);
+
+constexpr int kDims[] = {4, 8, 16, 20, 24, 32, 48, 64};
+constexpr int kMs[] = {1, 2, 4, 8, 16};
+
+template <int D>
+constexpr int rows_per_lane() { return D <= 32 ? 2 : 1; }
+
+template <int KIND, typename T, int D, int M>
+void* tile_ptr() {
+  return reinterpret_cast<void*>(&tile_valu<KIND, T, D, M, rows_per_lane<D>()>);
+}
+
+template <int KIND, typename T, int D>
+void* pick_m(int M) {
+  switch (M) {
+    case 1: return tile_ptr<KIND, T, D, 1>();
+    case 2: return tile_ptr<KIND, T, D, 2>();
+    case 4: return tile_ptr<KIND, T, D, 4>();
+    case 8: return tile_ptr<KIND, T, D, 8>();
+    default: return tile_ptr<KIND, T, D, 16>();
+  }
+}
+
+template <int KIND, typename T>
+void* pick_d(int D, int M) {
+  switch (D) {
+    case 4: return pick_m<KIND, T, 4>(M);
+    case 8: return pick_m<KIND, T, 8>(M);
+    case 16: return pick_m<KIND, T, 16>(M);
+    case 20: return pick_m<KIND, T, 20>(M);
+    case 24: return pick_m<KIND, T, 24>(M);
+    case 32: return pick_m<KIND, T, 32>(M);
+    case 48: return pick_m<KIND, T, 48>(M);
+    default: return pick_m<KIND, T, 64>(M);
+  }
+}
+
+int mpad(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16; }
+
+struct Split {
+  int nsplit;
+  int64_t per;
+};
+
+Split choose_split(int64_t nr, int64_t nc, int R) {
+  const int64_t rows_per_wg = (int64_t)kWaves * 64 * R;
+  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
+  int64_t ns = ceil_div(2048, rg);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / 128));
+  if (ns >= 8) ns = ns / 8 * 8;  // keep a split on one XCD: wg id % 8 == split % 8
+  ns = std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+  return {(int)ns, ceil_div(std::max<int64_t>(nc, 1), ns)};
+}
+
+int rows_for_dpad(int D) { return D <= 32 ? 2 : 1; }
+
+// Optional HIP-event timing of the product tiles (the dominant kernel).
+struct TileTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+TileTimer& timer() {
+  static TileTimer t;
+  return t;
+}
+
+}  // namespace
+
+void tile_timing_enable(bool on) {
+  TileTimer& t = timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.on = on;
+}
+
+int tile_timing_read(double* total_ms, int64_t* launches) {
+  TileTimer& t = timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  double tot = 0.0;
+  for (auto& pr : t.ev) {
+    KRR_TRY(hip_check(hipEventSynchronize(pr.second), "timing sync"));
+    float ms = 0.f;
+    KRR_TRY(hip_check(hipEventElapsedTime(&ms, pr.first, pr.second), "elapsed"));
+    tot += ms;
+    t.pool.push_back(pr.first);
+    t.pool.push_back(pr.second);
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)t.ev.size();
+  t.ev.clear();
+  return KRR_OK;
+}
+
+int padded_dim(int32_t d) {
+  for (int D : kDims)
+    if (d <= D) return D;
+  return 0;
+}
+
+int mfma_kdim(int32_t d) { return (int)((d + 31) / 32 * 32); }
+
+size_t pointset_bytes(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d) {
+  Arena a;
+  PointSet ps;
+  if (carve_points(kind, prec, n, d, a, &ps) != KRR_OK) return 0;
+  return a.used;
+}
+
+int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d, Arena& arena,
+                 PointSet* out) {
+  const int D = padded_dim(d);
+  if (D == 0) {
+    set_error("dimension d=%d unsupported (1 <= d <= 64)", d);
+    return KRR_EINVAL;
+  }
+  *out = PointSet();
+  out->n = n;
+  out->d = d;
+  out->dpad = D;
+  if (prec == KRR_FP64) {
+    out->x64 = arena.take<double>((size_t)n * D);
+    return KRR_OK;
+  }
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) {
+    set_error("MIXED Gaussian tiles are not available in this build");
+    return KRR_EINVAL;
+  }
+  out->x32 = arena.take<float>((size_t)n * D);
+  return KRR_OK;
+}
+
+int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* centre,
+                const PointSet& ps, hipStream_t s) {
+  const int64_t n = ps.n;
+  if (n == 0) return KRR_OK;
+  const int D = ps.dpad;
+  const int64_t tot = n * D;
+  if (X == nullptr) {
+    set_error("fill_points: NULL points");
+    return KRR_EINVAL;
+  }
+  if (prec == KRR_FP64) {
+    if (!ps.x64) {
+      set_error("fill_points: layout not carved");
+      return KRR_EINVAL;
+    }
+    pack_pts<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, centre, const_cast<double*>(ps.x64));
+    KRR_LAUNCH_CHECK("pack_pts<double>");
+    return KRR_OK;
+  }
+  (void)kind;
+  if (!ps.x32) {
+    set_error("fill_points: layout not carved");
+    return KRR_EINVAL;
+  }
+  pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, centre, const_cast<float*>(ps.x32));
+  KRR_LAUNCH_CHECK("pack_pts<float>");
+  return KRR_OK;
+}
+
+int pack_points(krr_kernel_kind kind, krr_precision prec, const double* X, int64_t n, int32_t d,
+                const double* centre, Arena& arena, PointSet* out, hipStream_t s) {
+  KRR_TRY(carve_points(kind, prec, n, d, arena, out));
+  if (arena.base == nullptr) return KRR_OK;  // measuring
+  if (!arena.ok()) {
+    set_error("workspace too small for the point layout");
+    return KRR_EWORKSPACE;
+  }
+  return fill_points(kind, prec, X, centre, *out, s);
+}
+
+size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t m) {
+  const size_t es = prec == KRR_FP64 ? 8 : 4;
+  const int M = mpad(std::min(m, 16));
+  // worst case over the row-per-lane choices (more rows per lane -> fewer
+  // row groups -> more column splits)
+  int64_t ns = 1;
+  for (int R = 1; R <= 2; ++R) ns = std::max<int64_t>(ns, choose_split(nr, nc, R).nsplit);
+  Arena a;
+  a.take<char>((size_t)std::max<int64_t>(nc, 1) * M * es);
+  a.take<double>((size_t)ns * std::max<int64_t>(nr, 1) * M);
+  return a.used;
+}
+
+int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointSet& rows,
+            const PointSet& cols, VecView V, int32_t m, double shift, VecView Vs, VecOut W,
+            Arena& scratch, hipStream_t s) {
+  const int64_t nr = rows.n, nc = cols.n;
+  if (nr == 0 || m == 0) return KRR_OK;
+  if (rows.dpad != cols.dpad) {
+    set_error("row and column point sets differ in dimension");
+    return KRR_EINVAL;
+  }
+  const int D = rows.dpad;
+  const bool f64 = prec == KRR_FP64;
+  const int R = rows_for_dpad(D);
+  const size_t mark = scratch.used;
+  for (int c0 = 0; c0 < m; c0 += 16) {
+    const int mc = std::min(16, m - c0);
+    const int M = mpad(mc);
+    scratch.used = mark;
+    Split sp = choose_split(nr, nc, R);
+    void* vp = f64 ? (void*)scratch.take<double>((size_t)std::max<int64_t>(nc, 1) * M)
+                   : (void*)scratch.take<float>((size_t)std::max<int64_t>(nc, 1) * M);
+    double* part = scratch.take<double>((size_t)sp.nsplit * nr * M);
+    if (!scratch.ok()) {
+      set_error("product scratch too small");
+      return KRR_EWORKSPACE;
+    }
+    if (nc > 0) {
+      const int64_t tot = nc * M;
+      if (f64)
+        pack_vec<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(V, nc, c0, mc, M,
+                                                                        (double*)vp);
+      else
+        pack_vec<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(V, nc, c0, mc, M,
+                                                                       (float*)vp);
+      KRR_LAUNCH_CHECK("pack_vec");
+      const int64_t rg = ceil_div(nr, (int64_t)kWaves * 64 * R);
+      const unsigned grid = (unsigned)(rg * sp.nsplit);
+      hipEvent_t ev0 = nullptr, ev1 = nullptr;
+      {
+        TileTimer& tt = timer();
+        std::lock_guard<std::mutex> g(tt.mu);
+        if (tt.on) {
+          ev0 = tt.get();
+          ev1 = tt.get();
+          if (ev0 && ev1) (void)hipEventRecord(ev0, s);
+        }
+      }
+      const double log2e = 1.4426950408889634;
+      if (f64) {
+        const double sc = kind == KRR_LAPLACE ? -1.0 / sigma : -1.0 / (2.0 * sigma * sigma);
+        void* fn = kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, double>(D, M)
+                                       : pick_d<KRR_GAUSSIAN, double>(D, M);
+        reinterpret_cast<TileFn64>(fn)<<<grid, 256, 0, s>>>(rows.x64, nr, cols.x64,
+                                                            (const double*)vp, nc, sc, sp.nsplit,
+                                                            sp.per, part);
+      } else {
+        const float sc = (float)(kind == KRR_LAPLACE ? -log2e / sigma
+                                                     : -log2e / (2.0 * sigma * sigma));
+        void* fn = kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, float>(D, M)
+                                       : pick_d<KRR_GAUSSIAN, float>(D, M);
+        reinterpret_cast<TileFn32>(fn)<<<grid, 256, 0, s>>>(rows.x32, nr, cols.x32,
+                                                           (const float*)vp, nc, sc, sp.nsplit,
+                                                           sp.per, part);
+      }
+      KRR_LAUNCH_CHECK("tile_valu");
+      if (ev0 && ev1) {
+        (void)hipEventRecord(ev1, s);
+        TileTimer& tt = timer();
+        std::lock_guard<std::mutex> g(tt.mu);
+        tt.ev.emplace_back(ev0, ev1);
+      }
+    }
+    const int ns = nc > 0 ? sp.nsplit : 0;
+    const int64_t tot = nr * mc;
+    reduce_splits<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(part, ns, nr, M, mc, c0, shift,
+                                                               Vs, W);
+    KRR_LAUNCH_CHECK("reduce_splits");
+  }
+  scratch.used = mark;
+  return KRR_OK;
+}
+
+}  // namespace krr

@@ -1,0 +1,399 @@
+// Blocked RPCholesky (Appendix A, Alg. 3) on gfx950, the Woodbury factor of
+// the Nystrom preconditioner of Alg. 1, and the FP64 kernel-column tile used
+// by the build steps.
+//
+// Readings of the algorithm (identical rules are written out independently in
+// the CPU reference):
+//  * draws are i.i.d. with replacement: draw t of block b uses
+//    u = u53(sm(sm(sm(seed, 1), b), t)) and picks the smallest index whose
+//    inclusive prefix sum exceeds u*T; prefix sums follow a fixed order
+//    (chunks of 1024 summed left to right, then a left-to-right running sum
+//    of chunk totals) so both implementations round identically;
+//  * the distinct draws are taken in ascending index order;
+//  * the small Cholesky proceeds pivot by pivot and drops a pivot whose Schur
+//    diagonal is <= eps * tr(A); dropped pivots create no column;
+//  * after each block the drawn entries of the residual diagonal are set to
+//    zero and the diagonal is clamped at zero;
+//  * the loop stops early once the residual trace is <= eps * tr(A).
+#include "solver.h"
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace krr {
+
+namespace {
+
+constexpr int kChunk = 1024;
+
+__global__ void fill_d(double* __restrict__ d, double v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) d[t] = v;
+}
+
+// S[c] = ((0 + d[c*1024]) + d[c*1024+1]) + ... , one thread per chunk.
+__global__ void chunk_sums(const double* __restrict__ d, int64_t n, int64_t nch,
+                           double* __restrict__ S) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  const int64_t i0 = c * kChunk;
+  const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+  double s = 0.0;
+  for (int64_t i = i0; i < i1; ++i) s = __dadd_rn(s, d[i]);
+  S[c] = s;
+}
+
+// O[0] = 0, O[c+1] = O[c] + S[c] (sequential, one thread).
+__global__ void chunk_offsets(const double* __restrict__ S, int64_t nch, double* __restrict__ O) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double o = 0.0;
+  O[0] = 0.0;
+  for (int64_t c = 0; c < nch; ++c) {
+    o = __dadd_rn(o, S[c]);
+    O[c + 1] = o;
+  }
+}
+
+__global__ void draw_pivots(const double* __restrict__ d, int64_t n, const double* __restrict__ O,
+                            int64_t nch, uint64_t block_key, int count,
+                            int64_t* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const double T = O[nch];
+  const double u = u53(sm64(block_key, (uint64_t)t));
+  const double thr = __dmul_rn(u, T);
+  // smallest chunk c with O[c+1] > thr
+  int64_t lo = 0, hi = nch;  // search in [lo, hi)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (O[mid + 1] > thr) hi = mid;
+    else lo = mid + 1;
+  }
+  int64_t pick = -1;
+  if (lo < nch) {
+    const int64_t i0 = lo * kChunk;
+    const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+    const double base = O[lo];
+    double p = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+      p = __dadd_rn(p, d[i]);
+      if (__dadd_rn(base, p) > thr) {
+        pick = i;
+        break;
+      }
+    }
+  }
+  if (pick < 0) {  // u*T rounded up to T: last index with positive mass
+    for (int64_t i = n - 1; i >= 0; --i)
+      if (d[i] > 0.0) {
+        pick = i;
+        break;
+      }
+    if (pick < 0) pick = 0;
+  }
+  out[t] = pick;
+}
+
+// out[q][j] = K(A_q, B_j) in FP64, direct differences.  One thread per j;
+// the row points A_q are wave-uniform (scalar loads).
+template <int KIND, int D>
+__global__ __launch_bounds__(256) void kblock64(const double* __restrict__ A, int64_t na,
+                                                const double* __restrict__ B, int64_t nb,
+                                                double scale, double* __restrict__ out,
+                                                int64_t ld) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t jj = j < nb ? j : nb - 1;
+  double y[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) y[k] = B[jj * D + k];
+  const int64_t q0 = (int64_t)blockIdx.y * 16;
+  const int64_t q1 = (q0 + 16 < na) ? q0 + 16 : na;
+  for (int64_t q = q0; q < q1; ++q) {
+    const double* __restrict__ a = A + q * D;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double t = a[k] - y[k];
+      if (KIND == KRR_LAPLACE) s += __builtin_fabs(t);
+      else s = __builtin_fma(t, t, s);
+    }
+    if (j < nb) out[q * ld + j] = exp(s * scale);
+  }
+}
+
+template <int KIND>
+void* kblock_pick(int D) {
+  switch (D) {
+    case 4: return (void*)&kblock64<KIND, 4>;
+    case 8: return (void*)&kblock64<KIND, 8>;
+    case 16: return (void*)&kblock64<KIND, 16>;
+    case 20: return (void*)&kblock64<KIND, 20>;
+    case 24: return (void*)&kblock64<KIND, 24>;
+    case 32: return (void*)&kblock64<KIND, 32>;
+    case 48: return (void*)&kblock64<KIND, 48>;
+    default: return (void*)&kblock64<KIND, 64>;
+  }
+}
+using KBlockFn = void (*)(const double*, int64_t, const double*, int64_t, double, double*, int64_t);
+
+__global__ void gather_points(const double* __restrict__ X, int D, const int64_t* __restrict__ idx,
+                              int64_t cnt, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt * D) return;
+  const int64_t q = t / D;
+  const int k = (int)(t % D);
+  out[t] = X[idx[q] * D + k];
+}
+
+// Fs[q][p] = FT[p][idx[q]]  (cnt x i, row-major)
+__global__ void gather_cols(const double* __restrict__ FT, int64_t ldf, int64_t i,
+                            const int64_t* __restrict__ idx, int64_t cnt,
+                            double* __restrict__ Fs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt * i) return;
+  const int64_t q = t / i, p = t % i;
+  Fs[t] = FT[p * ldf + idx[q]];
+}
+
+// Pivot-by-pivot Cholesky of G(S',S') with the drop rule, in LDS.
+// R (upper) is built in place over the upper triangle.  Outputs the lower
+// factor of the accepted pivots, Lacc = R_acc^T (acc x acc, ld = ldl), the
+// accepted positions and their count.
+__global__ __launch_bounds__(256) void chol_drop(const double* __restrict__ GT, int64_t ldg,
+                                                 const int64_t* __restrict__ sp, int bp,
+                                                 double thresh, double* __restrict__ Lacc,
+                                                 int ldl, int* __restrict__ acc_out,
+                                                 int* __restrict__ acc_count) {
+  __shared__ double R[kBmax][kBmax + 1];
+  __shared__ int acc[kBmax];
+  __shared__ int nacc;
+  __shared__ int take;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < bp * bp; e += blockDim.x) {
+    const int q = e / bp, q2 = e % bp;
+    R[q][q2] = GT[(int64_t)q * ldg + sp[q2]];  // G(S'_q, S'_q2)
+  }
+  if (tid == 0) nacc = 0;
+  __syncthreads();
+  for (int q = 0; q < bp; ++q) {
+    if (tid == 0) {
+      double s = 0.0;
+      for (int a = 0; a < nacc; ++a) s = __dadd_rn(s, __dmul_rn(R[acc[a]][q], R[acc[a]][q]));
+      s = __dsub_rn(R[q][q], s);
+      take = s > thresh ? 1 : 0;
+      if (take) R[q][q] = sqrt(s);
+    }
+    __syncthreads();
+    if (take) {
+      const double rqq = R[q][q];
+      for (int q2 = q + 1 + tid; q2 < bp; q2 += blockDim.x) {
+        double s = 0.0;
+        for (int a = 0; a < nacc; ++a) s = __dadd_rn(s, __dmul_rn(R[acc[a]][q], R[acc[a]][q2]));
+        R[q][q2] = __ddiv_rn(__dsub_rn(R[q][q2], s), rqq);
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && take) acc[nacc++] = q;
+    __syncthreads();
+  }
+  const int na = nacc;
+  for (int e = tid; e < na * na; e += blockDim.x) {
+    const int a = e / na, b = e % na;
+    Lacc[a * ldl + b] = (b <= a) ? R[acc[b]][acc[a]] : 0.0;
+  }
+  for (int a = tid; a < na; a += blockDim.x) acc_out[a] = acc[a];
+  if (tid == 0) *acc_count = na;
+}
+
+// FT[i0 + a][j] = GT[acc[a]][j]
+__global__ void copy_rows(const double* __restrict__ GT, int64_t ld, const int* __restrict__ acc,
+                          int na, int64_t n, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)na * n) return;
+  const int64_t a = t / n, j = t % n;
+  dst[a * n + j] = GT[(int64_t)acc[a] * ld + j];
+}
+
+// d[j] = max(d[j] - sum_a Fnew[a][j]^2, 0)
+__global__ void d_update(double* __restrict__ d, const double* __restrict__ Fnew, int na,
+                         int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int a = 0; a < na; ++a) {
+    const double f = Fnew[(int64_t)a * n + j];
+    s += f * f;
+  }
+  const double v = d[j] - s;
+  d[j] = v > 0.0 ? v : 0.0;
+}
+
+__global__ void zero_at(double* __restrict__ d, const int64_t* __restrict__ idx, int cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < cnt) d[idx[t]] = 0.0;
+}
+
+__global__ void add_diag(double* __restrict__ A, int64_t n, int64_t lda, double v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) A[t * lda + t] += v;
+}
+
+}  // namespace
+
+int kernel_block64(krr_kernel_kind kind, double sigma, const PointSet& A, const PointSet& B,
+                   double* out, int64_t ld, hipStream_t s) {
+  if (A.n == 0 || B.n == 0) return KRR_OK;
+  const double scale = kind == KRR_LAPLACE ? -1.0 / sigma : -1.0 / (2.0 * sigma * sigma);
+  const int D = A.dpad;
+  void* fn = kind == KRR_LAPLACE ? kblock_pick<KRR_LAPLACE>(D) : kblock_pick<KRR_GAUSSIAN>(D);
+  dim3 g((unsigned)ceil_div(B.n, 256), (unsigned)ceil_div(A.n, 16));
+  if (g.y > 65535) {
+    set_error("kernel_block64: too many rows");
+    return KRR_EINVAL;
+  }
+  reinterpret_cast<KBlockFn>(fn)<<<g, 256, 0, s>>>(A.x64, A.n, B.x64, B.n, scale, out, ld);
+  KRR_LAUNCH_CHECK("kblock64");
+  return KRR_OK;
+}
+
+int rpchol_layout(Arena& a, Precond& P) {
+  KRR_TRY(carve_points(P.kind, KRR_FP64, P.N, P.d, a, &P.pts64));
+  if (P.prec != KRR_FP64)
+    KRR_TRY(carve_points(P.kind, P.prec, P.N, P.d, a, &P.pts));
+  else
+    P.pts = P.pts64;
+  const int64_t N = P.N;
+  P.QT = a.take<double>((size_t)P.r_req * N);
+  P.core = a.take<double>((size_t)P.r_req * P.r_req);
+  pcg_carve(a, P.pcg, N, P.m_max, 0, P.r_req);
+  RPWork& w = P.rp;
+  const int64_t nch = ceil_div(N, kChunk);
+  w.d = a.take<double>(N);
+  w.S = a.take<double>(nch);
+  w.O = a.take<double>(nch + 1);
+  w.draws = a.take<int64_t>(kBmax);
+  w.sp = a.take<int64_t>(kBmax);
+  w.GT = a.take<double>((size_t)P.B * N);
+  w.Fs = a.take<double>((size_t)P.B * P.r_req);
+  w.Lacc = a.take<double>((size_t)kBmax * kBmax);
+  w.acc = a.take<int>(kBmax);
+  w.ints = a.take<int>(4);
+  w.spx = a.take<double>((size_t)kBmax * 64);
+  // scratch for products, split-K GEMMs of the build and of the applies
+  const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max);
+  const size_t ps64 = product_scratch_bytes(KRR_FP64, N, N, P.m_max);
+  const size_t gs = std::max(gemm_scratch_bytes(P.m_max, P.r_req, N),
+                             std::max(gemm_scratch_bytes(P.r_req, P.r_req, N),
+                                      gemm_scratch_bytes(P.B, N, P.r_req)));
+  const size_t sb = std::max(std::max(ps, ps64), gs) + kAlign;
+  char* sc = a.take<char>(sb);
+  P.scratch = Arena(sc, sb);
+  return KRR_OK;
+}
+
+int rpchol_build(Precond& P, const double* X, hipStream_t s) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  const int64_t N = P.N;
+  const int64_t nch = ceil_div(N, kChunk);
+  RPWork& w = P.rp;
+  // fill the point layouts carved by rpchol_layout
+  KRR_TRY(fill_points(P.kind, KRR_FP64, X, nullptr, P.pts64, s));
+  if (P.prec != KRR_FP64) KRR_TRY(fill_points(P.kind, P.prec, X, nullptr, P.pts, s));
+  // d = diag(A): both kernels equal exp(0) = 1 on the diagonal
+  fill_d<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(w.d, 1.0, N);
+  KRR_LAUNCH_CHECK("fill_d");
+  const double trA = (double)N;
+  const double thresh = kEps * trA;
+  const uint64_t kpiv = sm64(P.seed, kTagPivot);
+  const int D = P.pts64.dpad;
+  P.pivots.clear();
+  int64_t i = 0;
+  int64_t b = 0;
+  std::vector<int64_t> draws(kBmax), sp;
+  std::vector<int> acc(kBmax);
+  int hbuf[2];
+  double T = 0.0;
+  while (i < P.r_req && b <= N) {
+    chunk_sums<<<(unsigned)ceil_div(nch, 256), 256, 0, s>>>(w.d, N, nch, w.S);
+    KRR_LAUNCH_CHECK("chunk_sums");
+    chunk_offsets<<<1, 1, 0, s>>>(w.S, nch, w.O);
+    KRR_LAUNCH_CHECK("chunk_offsets");
+    KRR_TRY(hip_check(hipMemcpyAsync(&T, w.O + nch, sizeof(double), hipMemcpyDeviceToHost, s), "T"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    if (!(T > thresh)) break;  // residual exhausted (exact recovery)
+    const int cnt = (int)std::min<int64_t>(P.B, P.r_req - i);
+    draw_pivots<<<(unsigned)ceil_div(cnt, 64), 64, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
+                                                           cnt, w.draws);
+    KRR_LAUNCH_CHECK("draw_pivots");
+    KRR_TRY(hip_check(hipMemcpyAsync(draws.data(), w.draws, sizeof(int64_t) * cnt,
+                                     hipMemcpyDeviceToHost, s), "draws"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    sp.assign(draws.begin(), draws.begin() + cnt);
+    std::sort(sp.begin(), sp.end());
+    sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
+    const int bp = (int)sp.size();
+    KRR_TRY(hip_check(hipMemcpyAsync(w.sp, sp.data(), sizeof(int64_t) * bp, hipMemcpyHostToDevice, s),
+                      "S'"));
+    // G^T = A(S', :) - F(S', 1:i) F(:, 1:i)^T
+    gather_points<<<(unsigned)ceil_div((int64_t)bp * D, 256), 256, 0, s>>>(P.pts64.x64, D, w.sp, bp,
+                                                                          w.spx);
+    KRR_LAUNCH_CHECK("gather_points");
+    PointSet sps;
+    sps.n = bp;
+    sps.d = P.d;
+    sps.dpad = D;
+    sps.x64 = w.spx;
+    KRR_TRY(kernel_block64(P.kind, P.sigma, sps, P.pts64, w.GT, N, s));
+    if (i > 0) {
+      gather_cols<<<(unsigned)ceil_div((int64_t)bp * i, 256), 256, 0, s>>>(P.QT, N, i, w.sp, bp,
+                                                                          w.Fs);
+      KRR_LAUNCH_CHECK("gather_cols");
+      KRR_TRY(gemm_f64(false, bp, N, i, -1.0, w.Fs, i, P.QT, N, 1.0, w.GT, N, s, &P.scratch));
+    }
+    chol_drop<<<1, 256, 0, s>>>(w.GT, N, w.sp, bp, thresh, w.Lacc, kBmax, w.acc, w.ints);
+    KRR_LAUNCH_CHECK("chol_drop");
+    KRR_TRY(hip_check(hipMemcpyAsync(hbuf, w.ints, sizeof(int), hipMemcpyDeviceToHost, s), "acc"));
+    KRR_TRY(hip_check(hipMemcpyAsync(acc.data(), w.acc, sizeof(int) * bp, hipMemcpyDeviceToHost, s),
+                      "acc list"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    const int na = hbuf[0];
+    if (na > 0) {
+      double* Fnew = P.QT + i * N;
+      copy_rows<<<(unsigned)ceil_div((int64_t)na * N, 256), 256, 0, s>>>(w.GT, N, w.acc, na, N, Fnew);
+      KRR_LAUNCH_CHECK("copy_rows");
+      // F_new^T = R_acc^{-T} G_acc^T
+      KRR_TRY(trsm_lower_left(na, N, w.Lacc, kBmax, Fnew, N, s));
+      d_update<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(w.d, Fnew, na, N);
+      KRR_LAUNCH_CHECK("d_update");
+    }
+    zero_at<<<1, kBmax, 0, s>>>(w.d, w.sp, bp);
+    KRR_LAUNCH_CHECK("zero_at");
+    for (int a2 = 0; a2 < na; ++a2) P.pivots.push_back(sp[acc[a2]]);
+    i += na;
+    ++b;
+  }
+  P.rank = (int32_t)i;
+  const int64_t rk = i;
+  if (rk > 0) {
+    // core = mu I + F^T F, its Cholesky factor L, then Q^T = L^{-1} F^T in place
+    KRR_TRY(gemm_f64(true, rk, rk, N, 1.0, P.QT, N, P.QT, N, 0.0, P.core, rk, s, &P.scratch));
+    add_diag<<<(unsigned)ceil_div(rk, 256), 256, 0, s>>>(P.core, rk, rk, P.mu);
+    KRR_LAUNCH_CHECK("add_diag");
+    KRR_TRY(potrf_lower(rk, P.core, rk, w.ints + 1, s));
+    int info = 0;
+    KRR_TRY(hip_check(hipMemcpyAsync(&info, w.ints + 1, sizeof(int), hipMemcpyDeviceToHost, s),
+                      "info"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    if (info != 0) {
+      set_error("Cholesky of mu I + F^T F failed at column %d", info);
+      return KRR_ENOTSPD;
+    }
+    KRR_TRY(trsm_lower_left(rk, N, P.core, rk, P.QT, N, s));
+  }
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+  P.build_seconds = std::chrono::duration<double>(clk::now() - t0).count();
+  return KRR_OK;
+}
+
+}  // namespace krr

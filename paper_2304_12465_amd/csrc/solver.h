@@ -1,0 +1,129 @@
+// Internal: preconditioner objects and the PCG driver.
+#pragma once
+#include <vector>
+#include "product.h"
+#include "la.h"
+
+namespace krr {
+
+// SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based generator:
+// sm(s, n) is the n-th output of the generator seeded with s.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm64(uint64_t seed, uint64_t n) {
+  return mix64(seed + (n + 1) * 0x9E3779B97F4A7C15ull);
+}
+enum : uint64_t { kTagPivot = 1, kTagCenter = 2, kTagSketchRow = 3, kTagSketchSign = 4 };
+__host__ __device__ inline double u53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+constexpr double kEps = 0x1.0p-52;  // FP64 machine epsilon
+constexpr int kBmax = 128;          // largest RPCholesky block
+
+enum PrecondType { kRPChol = 0, kKrill = 1 };
+
+// Column-major block of m vectors of length n (vector c at p + c*n).
+struct VecBlock {
+  double* p = nullptr;
+  int64_t n = 0;
+  VecView view() const { return VecView{p, 1, n}; }
+  VecOut out() const { return VecOut{p, 1, n}; }
+};
+
+struct PcgState {
+  int32_t m_max = 0;
+  int64_t n = 0;                            // system size: N (full) or k (restricted)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr, *b = nullptr;
+  double* scal = nullptr;                   // per-column scalars, kScalars x m_max
+  double* part = nullptr;                   // reduction partials
+  int nblk = 0;                             // reduction blocks per column
+  double* host = nullptr;                   // pinned host mirror of scal
+  double* tmpN = nullptr;                   // N x m_max (restricted: K_NS p)
+  double* tmpR = nullptr;                   // rank x m_max (Woodbury: Q^T r)
+};
+
+// Build-time buffers of RPCholesky (part of the workspace footprint).
+struct RPWork {
+  double* d = nullptr;      // residual diagonal, N
+  double* S = nullptr;      // chunk totals
+  double* O = nullptr;      // chunk offsets
+  int64_t* draws = nullptr; // block draws
+  int64_t* sp = nullptr;    // distinct draws (ascending)
+  double* GT = nullptr;     // B x N: G^T of the block
+  double* Fs = nullptr;     // B x r: F(S', 1:i)
+  double* Lacc = nullptr;   // kBmax x kBmax
+  int* acc = nullptr;       // accepted positions
+  int* ints = nullptr;      // [0] accepted count, [1] Cholesky info
+  double* spx = nullptr;    // pivot points, kBmax x dpad
+};
+
+struct Precond {
+  PrecondType type = kRPChol;
+  krr_kernel_kind kind = KRR_GAUSSIAN;
+  double sigma = 1.0;
+  krr_precision prec = KRR_FP64;
+  double mu = 0.0;
+  int64_t N = 0;
+  int32_t d = 0;
+  int32_t m_max = 1;
+  PointSet pts64;  // FP64 layout of X (build steps, true residuals)
+  PointSet pts;    // layout of the product precision (== pts64 for FP64)
+  // RPCholesky: Q^T (rank x N, row-major) with Q Q^T = F (mu I + F^T F)^{-1} F^T,
+  // and the lower Cholesky factor L of mu I + F^T F (rank x rank).
+  int32_t r_req = 0, B = 0, rank = 0;
+  uint64_t seed = 0;
+  double* QT = nullptr;
+  double* core = nullptr;
+  std::vector<int64_t> pivots;
+  RPWork rp;
+  // KRILL
+  int32_t k = 0, sketch_rows = 0, zeta = 0;
+  double shift = 0.0;             // N eps tr(A_SS)
+  int64_t* centers = nullptr;     // device, k
+  PointSet cpts64, cpts;          // centres in both layouts
+  double* H = nullptr;            // k x k: mu A_SS + shift I
+  double* C = nullptr;            // k x k: lower Cholesky factor of P = B^T B + H
+  std::vector<int64_t> centers_host;
+  // PCG state and scratch
+  PcgState pcg;
+  Arena scratch;
+  size_t ws_used = 0;
+  double build_seconds = 0.0;
+};
+
+// Fixed-order reductions and vector updates (pcg.hip).
+constexpr int kScalars = 12;
+enum ScalarSlot { kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp };
+
+size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_for_restricted, int32_t rank);
+void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_for_restricted,
+               int32_t rank);
+
+// System operator M V (full: K V + mu V; restricted: K_SN K_NS V + H V) in the
+// product precision `prec` (or FP64 when force64).
+int apply_operator(Precond& P, VecBlock V, int32_t m, VecBlock W, bool force64, hipStream_t s);
+// Preconditioner Z = P^{-1} R.
+int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s);
+// Right-hand side of the system for targets Y (N x m, row-major).
+int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s);
+
+int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
+            krr_solve_info* info, hipStream_t s);
+
+// Layout helpers used for both measuring and carving.
+int rpchol_layout(Arena& a, Precond& P);
+int rpchol_build(Precond& P, const double* X, hipStream_t s);
+int krill_layout(Arena& a, Precond& P);
+int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t s);
+
+// Dense kernel block out[q][j] = K(A_q, B_j) in FP64 (out: na x nb, ld).
+int kernel_block64(krr_kernel_kind kind, double sigma, const PointSet& A, const PointSet& B,
+                   double* out, int64_t ld, hipStream_t s);
+
+// Layout conversions between the ABI's row-major blocks and column-major.
+int to_colmajor(const double* src, int64_t n, int32_t m, double* dst, hipStream_t s);
+int to_rowmajor(const double* src, int64_t n, int32_t m, double* dst, hipStream_t s);
+
+}  // namespace krr

@@ -1,0 +1,137 @@
+"""Parity of the fused kernel product (krr_kernel_matvec) against the FP64
+oracle, element by element, with tolerances derived from the arithmetic:
+
+* FP64 tiles: |W - W_ref| <= 1e-13 * sum_j |K_ij| |V_jc| + 1e-300.
+* FP32 tiles: entries carry a relative error of about
+  |arg| (d + 2) 2^-24 + 2 ulp(exp) <= 0.37 (d + 2) 6e-8 absolute, V is rounded
+  to FP32 (6e-8 relative) and at most 256 terms are summed in FP32 before
+  the FP64 fold (<= 256 * 6e-8 relative to the partial sum of |terms|).
+  The bound used is 2e-5 * sum_j |K_ij| |V_jc|.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as OK
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-13, 1: 2e-5}
+
+
+def B():
+    from paper_2304_12465_amd import binding
+    return binding
+
+
+def run(kind, prec, Xr, Xc, V, sigma, shift=0.0):
+    b = B()
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    Xr_t = t(Xr)
+    Xc_t = Xr_t if Xc is Xr else t(Xc)
+    W = b.kernel_matvec(kind, sigma, prec, Xr_t, Xc_t, t(V), shift=shift)
+    torch.cuda.synchronize()
+    return W.cpu().numpy()
+
+
+def check(kind, prec, Xr, Xc, V, sigma, shift=0.0):
+    W = run(kind, prec, Xr, Xc, V, sigma, shift)
+    V2 = V if V.ndim == 2 else V[:, None]
+    W2 = W if W.ndim == 2 else W[:, None]
+    Kb = OK.block(Xr, Xc, kind, sigma)
+    ref = Kb @ V2 + shift * V2 if shift else Kb @ V2
+    scale = np.abs(Kb) @ np.abs(V2) + abs(shift) * np.abs(V2 if shift else 0)
+    err = np.abs(W2 - ref)
+    bound = TOL[prec] * scale + 1e-300
+    worst = float(np.max(err / bound)) if err.size else 0.0
+    assert np.all(err <= bound), f"worst err/bound = {worst}"
+    return worst
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("d", [1, 3, 8, 17, 20, 32, 33, 64])
+def test_square_with_shift(kind, prec, d):
+    g = np.random.default_rng(100 + d)
+    n = 1337  # several 512-row workgroups and a ragged tail
+    X = g.standard_normal((n, d))
+    V = g.standard_normal(n)
+    check(kind, prec, X, X, V, sigma=np.sqrt(d) * (1.0 if kind == 0 else 1.5), shift=0.37)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 8, 16, 17, 40])
+def test_multiple_rhs(m):
+    g = np.random.default_rng(7 + m)
+    Xr = g.standard_normal((700, 16))
+    Xc = g.standard_normal((2100, 16))
+    V = g.standard_normal((2100, m))
+    for kind in (0, 1):
+        for prec in (0, 1):
+            check(kind, prec, Xr, Xc, V, sigma=3.0)
+
+
+def test_rectangular_shapes_and_edges():
+    g = np.random.default_rng(3)
+    # one row, many columns (many splits); many rows, one column
+    for nr, nc in [(1, 5000), (4000, 1), (65, 129), (513, 257)]:
+        Xr = g.standard_normal((nr, 5))
+        Xc = g.standard_normal((nc, 5))
+        V = g.standard_normal((nc, 2))
+        for kind in (0, 1):
+            check(kind, 0, Xr, Xc, V, sigma=2.0)
+            check(kind, 1, Xr, Xc, V, sigma=2.0)
+
+
+def test_empty_inputs():
+    b = B()
+    dev = torch.device("cuda:0")
+    X = torch.zeros((0, 4), dtype=torch.float64, device=dev)
+    Y = torch.randn((5, 4), dtype=torch.float64, device=dev)
+    V0 = torch.zeros((0, 1), dtype=torch.float64, device=dev)
+    W = b.kernel_matvec(0, 1.0, 0, Y, X, V0)   # nc = 0: W = 0
+    torch.cuda.synchronize()
+    assert torch.all(W == 0)
+    W = b.kernel_matvec(0, 1.0, 0, X, Y, torch.ones((5, 1), dtype=torch.float64, device=dev))
+    assert W.shape == (0, 1)
+
+
+def test_identical_points_and_far_clusters_exact():
+    # All-equal points give A = 11^T exactly; two far clusters give the rank-2
+    # block matrix of the uniform-sampling failure example (Sec. 3.1).
+    X = np.vstack([np.zeros((300, 6)), np.full((40, 6), 1e3)])
+    V = np.arange(340.0)[:, None]
+    for kind in (0, 1):
+        for prec in (0, 1):
+            W = run(kind, prec, X, X, V, 1.0)
+            np.testing.assert_array_equal(W[:300, 0], np.full(300, V[:300].sum()))
+            np.testing.assert_array_equal(W[300:, 0], np.full(40, V[300:].sum()))
+
+
+def test_invalid_arguments_raise():
+    b = B()
+    dev = torch.device("cuda:0")
+    X = torch.randn((10, 3), dtype=torch.float64, device=dev)
+    V = torch.randn((10, 1), dtype=torch.float64, device=dev)
+    with pytest.raises(b.KrrError):
+        b.kernel_matvec(0, -1.0, 0, X, X, V)
+    with pytest.raises(b.KrrError):
+        b.kernel_matvec(0, 1.0, 0, X, X[:5].contiguous(), V[:5].contiguous(), shift=1.0)
+    with pytest.raises(b.KrrError) as e:
+        b.kernel_matvec(0, 1.0, 0, X, X, V, ws=b.workspace(16, dev))
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_laplace_sampled_rows(prec):
+    # The 100,000-point, d = 20 Laplace workload: the product over all columns
+    # is checked on 192 sampled rows that the oracle computes one by one.
+    p = synth.c2()
+    g = np.random.default_rng(11)
+    V = g.standard_normal((p.X.shape[0], 1))
+    W = run(p.kind, prec, p.X, p.X, V, p.sigma, shift=p.mu)
+    rows = np.sort(g.choice(p.X.shape[0], 192, replace=False))
+    Kb = OK.block(p.X[rows], p.X, p.kind, p.sigma)
+    ref = Kb @ V + p.mu * V[rows]
+    scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
+    assert np.all(np.abs(W[rows] - ref) <= TOL[prec] * scale)

@@ -1,0 +1,199 @@
+"""Parity of the RPCholesky build (Alg. 3), the Nystrom/Woodbury
+preconditioner apply (Alg. 1) and the PCG solve against the FP64 oracle.
+
+Tolerances (derived from the arithmetic, stated per check):
+* pivots: bit-exact.  Sampling follows one written rule on both sides; a
+  flip needs u*T within ~1e-16 T of a prefix boundary (probability ~N*1e-16
+  per draw), so a mismatch signals a bug.
+* F: forward error of a Cholesky-based factor, ||dF||_F / ||F||_F <=
+  100 r eps kappa(A(S,S)).
+* P^{-1} z: ||dz|| / ||z|| <= 100 r eps kappa(P), kappa(P) = (mu + ||F||^2)/mu.
+* solutions: relative error <= 1e-6 on the FP64 path (full-data, against a
+  dense Cholesky solve); fitted values A beta within 1e-6 (FP64) / 1e-4
+  (FP32 tiles) of the oracle's PCG with the same pivots.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as OK
+from oracle import rpcholesky as ORP
+from oracle import pcg as OPCG
+from oracle import direct
+import synth
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -52
+DEV = torch.device("cuda:0")
+
+
+def B():
+    from paper_2304_12465_amd import binding
+    return binding
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def build(p, prec, r=None, B_=0, m_max=1, seed=None):
+    return B().rpchol_build(p.kind, p.sigma, prec, T(p.X), p.mu, r or p.rank, B=B_,
+                            seed=p.algo_seed if seed is None else seed, m_max=m_max)
+
+
+def oracle_factor(p, r=None, B_=None, seed=None):
+    return ORP.rpcholesky(p.X, p.kind, p.sigma, r or p.rank, B=B_,
+                          seed=p.algo_seed if seed is None else seed)
+
+
+def first_mismatch(a, b):
+    for i, (x, y) in enumerate(zip(a, b)):
+        if x != y:
+            return i
+    return None if len(a) == len(b) else min(len(a), len(b))
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_pivots_and_factor_match_oracle_c1(kind):
+    p = synth.c1()
+    p.kind = kind
+    if kind == 1:
+        p.sigma = 8.0
+    P = build(p, 0)
+    F_o, piv_o = oracle_factor(p)
+    piv = P.pivots()
+    assert piv == piv_o, f"first mismatch at {first_mismatch(piv, piv_o)}"
+    FT = P.factor().cpu().numpy()
+    F = FT.T
+    S = np.array(piv_o)
+    kap = np.linalg.cond(OK.block(p.X[S], p.X[S], p.kind, p.sigma))
+    rel = np.linalg.norm(F - F_o) / np.linalg.norm(F_o)
+    assert rel <= 100 * len(S) * EPS * kap, (rel, kap)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_matches_svd_form(prec):
+    p = synth.c1(n=1500)
+    P = build(p, prec, m_max=3)
+    F_o, piv_o = oracle_factor(p)
+    assert P.pivots() == piv_o
+    g = np.random.default_rng(5)
+    Z = g.standard_normal((1500, 3))
+    got = P.apply(T(Z)).cpu().numpy()
+    ref = ORP.NystromPreconditioner(F_o, p.mu).apply(Z)
+    kapP = (p.mu + np.linalg.norm(F_o, 2) ** 2) / p.mu
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 100 * len(piv_o) * EPS * kapP, (rel, kapP)
+
+
+def test_c1_solve_matches_dense_cholesky():
+    p = synth.c1()
+    P = build(p, 0)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=500)
+    beta = beta.cpu().numpy()
+    xd = direct.full_krr(p.X, p.Y, p.kind, p.sigma, p.mu)
+    assert info["converged"] and info["relres_true"] <= 10 * p.tol
+    rel = np.linalg.norm(beta - xd) / np.linalg.norm(xd)
+    assert rel <= 1e-6, rel
+    # iterate parity with the oracle's PCG on the same preconditioner (the
+    # oracle's kernel matrix is formed once: N = 2000)
+    F_o, piv_o = oracle_factor(p)
+    Pc = ORP.NystromPreconditioner(F_o, p.mu)
+    A = OK.block(p.X, p.X, p.kind, p.sigma)
+    prod = lambda V: A @ V + p.mu * V
+    xo, io = OPCG.pcg(prod, Pc.apply, p.Y, p.tol, 500)
+    assert abs(info["iters"] - int(io["iters"][0])) <= 1, (info["iters"], io["iters"])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-4)])
+def test_laplace_mixture_reduced_solve(prec, tol):
+    # The 100,000-point Laplace workload's distribution at N = 4,000.
+    p = synth.c2(n=4_000)
+    r = 300
+    P = build(p, prec, r=r)
+    F_o, piv_o = oracle_factor(p, r=r)
+    assert P.pivots() == piv_o, f"first mismatch {first_mismatch(P.pivots(), piv_o)}"
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=400)
+    beta = beta.cpu().numpy()
+    Pc = ORP.NystromPreconditioner(F_o, p.mu)
+    A = OK.block(p.X, p.X, p.kind, p.sigma)
+    prod = lambda V: A @ V + p.mu * V
+    xo, io = OPCG.pcg(prod, Pc.apply, p.Y, p.tol, 400)
+    assert io["converged"] and info["converged"]
+    fit = A @ beta
+    fit_o = A @ xo
+    rel = np.linalg.norm(fit - fit_o) / np.linalg.norm(fit_o)
+    assert rel <= tol, rel
+    if prec == 0:
+        assert abs(info["iters"] - int(io["iters"][0])) <= 1
+
+
+def test_multiple_rhs_independent_and_zero_column():
+    p = synth.c1(n=800)
+    g = np.random.default_rng(9)
+    Y = np.column_stack([p.Y[:, 0], np.zeros(800), g.standard_normal(800)])
+    P = build(p, 0, m_max=4)
+    beta, info = P.solve(T(Y), 1e-9, 500)
+    beta = beta.cpu().numpy()
+    assert np.all(beta[:, 1] == 0)
+    for c in (0, 2):
+        b1, i1 = P.solve(T(Y[:, c].copy()), 1e-9, 500)
+        np.testing.assert_allclose(beta[:, c], b1.cpu().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_exact_recovery_stops_early_and_converges_in_one_iteration():
+    g = np.random.default_rng(2)
+    q = 7
+    base = 3 * g.standard_normal((q, 4))
+    X = base[g.integers(0, q, size=3000)]
+    X[:q] = base
+    p = synth.Problem("dup", X, g.standard_normal((3000, 1)), 0, 1.0, 1e-2, rank=50)
+    P = build(p, 0, B_=5)
+    r, n = P.dims()
+    F_o, piv_o = oracle_factor(p, B_=5)
+    assert r == q == len(piv_o) and P.pivots() == piv_o
+    beta, info = P.solve(T(p.Y), 1e-10, 20)
+    assert info["iters"] == 1
+
+
+def test_errors():
+    b = B()
+    p = synth.c1(n=200)
+    with pytest.raises(b.KrrError) as e:
+        b.rpchol_build(0, 1.0, 0, T(p.X), -1.0, 10)
+    assert e.value.code == -1
+    with pytest.raises(b.KrrError) as e:
+        b.rpchol_build(0, 1.0, 0, T(p.X), 1.0, 300)  # r > N
+    assert e.value.code == -1
+    with pytest.raises(b.KrrError) as e:
+        b.rpchol_build(0, 1.0, 0, T(p.X), 1.0, 10, ws=b.workspace(1024, DEV))
+    assert e.value.code == -2
+    P = build(p, 0)
+    Y = p.Y.copy()
+    Y[3, 0] = np.nan
+    with pytest.raises(b.KrrError) as e:
+        P.solve(T(Y), 1e-6, 50)
+    assert e.value.code == -4
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_size_laplace_solve(prec):
+    # 100,000 points, d = 20, rank 1000: build + PCG to 1e-6; the residual
+    # is re-checked by the oracle on 256 sampled rows.
+    p = synth.c2()
+    P = build(p, prec)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=500)
+    assert info["converged"], info
+    if prec == 0:
+        assert info["relres_true"] <= 10 * p.tol, info
+    beta = beta.cpu().numpy()
+    g = np.random.default_rng(1)
+    rows = np.sort(g.choice(p.X.shape[0], 256, replace=False))
+    res = p.Y[rows] - (OK.matvec(p.X[rows], p.X, beta, p.kind, p.sigma) + p.mu * beta[rows])
+    est = np.sqrt(p.X.shape[0] / 256) * np.linalg.norm(res) / np.linalg.norm(p.Y)
+    assert est <= 20 * p.tol if prec == 0 else est <= 1e-4, est
+    # first block of pivots: diag(A) = 1, so they follow the closed form of the sampler
+    from oracle.rng import sm, key, u53, TAG_PIVOT
+    kb = sm(key(p.algo_seed, TAG_PIVOT), 0)
+    first = sorted(set(int(u53(sm(kb, t)) * p.X.shape[0]) for t in range(100)))
+    assert P.pivots()[:len(first)] == first
