@@ -14,6 +14,17 @@ int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const 
              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
              hipStream_t s, Arena* scratch = nullptr);
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K);
+// As gemm_f64; a_trans = true reads A as K x M (C = A^T op(B)).
+int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                int64_t ldc, hipStream_t s, Arena* scratch = nullptr);
+
+// Triangular solves with a few right-hand sides (B: n x m row-major, ld m),
+// blocked: a small diagonal solve per 64-row block and a right-looking
+// update of the remaining rows spread over many workgroups.
+int trsv_lower(int64_t n, int32_t m, const double* L, int64_t lda, double* B, hipStream_t s);
+int trsv_lower_trans(int64_t n, int32_t m, const double* L, int64_t lda, double* B,
+                     hipStream_t s);
 
 // In-place lower Cholesky of the n x n SPD matrix A (row-major, lda):
 // A = L L^T, L in the lower triangle (the strict upper triangle is left

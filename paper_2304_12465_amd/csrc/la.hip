@@ -19,7 +19,7 @@ constexpr int kPad = 17;    // LDS row pitch in doubles
 //   A (16 x 4): lane l holds A[l % 16][l / 16]
 //   B (4 x 16): lane l holds B[l / 16][l % 16]
 //   D (16 x 16): lane l, element t holds D[4 t + l / 16][l % 16]
-template <bool BT>
+template <bool AT, bool BT>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
                                                        double alpha, const double* __restrict__ A,
                                                        int64_t lda, const double* __restrict__ B,
@@ -43,12 +43,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
-    {
+    if (!AT) {
       const int64_t gm = m0 + ar;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t gk = k0 + ak + u;
         As[ar][ak + u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, mm = (tid & 15) * 4;  // A is K x M: 16 k x 64 m
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t gm = m0 + mm + u;
+        As[mm + u][kk] = (gk < ke && gm < M) ? A[gk * lda + gm] : 0.0;
       }
     }
     if (BT) {
@@ -232,6 +240,45 @@ __global__ __launch_bounds__(256) void gemm_tn_sub(int64_t M, int64_t N, int64_t
   C[m * ldc + n] -= s;
 }
 
+
+// Right-looking updates of the blocked triangular solves with m <= 64
+// right-hand sides (B row-major n x m).
+// Forward: rows i >= r0 get B_i -= L[i, k0:k0+nb] Y_blk.
+__global__ __launch_bounds__(256) void trsv_update_below(const double* __restrict__ L, int64_t lda,
+                                                         int64_t k0, int nb, int64_t r0,
+                                                         int64_t n, int m,
+                                                         double* __restrict__ B) {
+  __shared__ double Y[kNb][64];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * m; e += blockDim.x) Y[e / m][e % m] = B[(k0 + e / m) * m + e % m];
+  __syncthreads();
+  const int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + tid;
+  if (i >= n) return;
+  const double* Li = L + i * lda + k0;
+  for (int c = 0; c < m; ++c) {
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += Li[q] * Y[q][c];
+    B[i * m + c] -= s;
+  }
+}
+
+// Backward (L^T): rows i < k0 get B_i -= sum_q L[k0+q, i] Z_q.
+__global__ __launch_bounds__(256) void trsv_update_above(const double* __restrict__ L, int64_t lda,
+                                                         int64_t k0, int nb, int m,
+                                                         double* __restrict__ B) {
+  __shared__ double Z[kNb][64];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * m; e += blockDim.x) Z[e / m][e % m] = B[(k0 + e / m) * m + e % m];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (i >= k0) return;
+  for (int c = 0; c < m; ++c) {
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += L[(k0 + q) * lda + i] * Z[q][c];
+    B[i * m + c] -= s;
+  }
+}
+
 }  // namespace
 
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
@@ -242,6 +289,12 @@ size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
 int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
              hipStream_t s, Arena* scratch) {
+  return gemm_f64_ex(false, b_trans, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s, scratch);
+}
+
+int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                int64_t ldc, hipStream_t s, Arena* scratch) {
   if (M <= 0 || N <= 0) return KRR_OK;
   const int64_t gx = ceil_div(N, kTile), gy = ceil_div(M, kTile);
   if (gy > 65535) {
@@ -266,12 +319,21 @@ int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const 
     scratch->used = mark;
   }
   dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)z);
-  if (b_trans)
-    gemm_f64_kernel<true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                               kchunk, slots);
-  else
-    gemm_f64_kernel<false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                                                kchunk, slots);
+  if (a_trans) {
+    if (b_trans)
+      gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                       ldc, kchunk, slots);
+    else
+      gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                        ldc, kchunk, slots);
+  } else {
+    if (b_trans)
+      gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                        ldc, kchunk, slots);
+    else
+      gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                         ldc, kchunk, slots);
+  }
   KRR_LAUNCH_CHECK("gemm_f64");
   if (slots) {
     splitk_reduce<<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(slots, z, M, N, beta, C, ldc);
@@ -338,6 +400,47 @@ int trsm_lower_left_trans(int64_t n, int64_t ncols, const double* L, int64_t lda
     trsm_diag<true><<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
                                                                    B + k * ldb, ldb, ncols);
     KRR_LAUNCH_CHECK("trsm_diag<T>");
+  }
+  return KRR_OK;
+}
+
+
+int trsv_lower(int64_t n, int32_t m, const double* L, int64_t lda, double* B, hipStream_t s) {
+  if (n <= 0 || m <= 0) return KRR_OK;
+  if (m > 64) {
+    set_error("trsv_lower: at most 64 right-hand sides");
+    return KRR_EINVAL;
+  }
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    trsm_diag<false><<<1, 64, 0, s>>>(L + k * lda + k, lda, nb, B + k * m, m, m);
+    KRR_LAUNCH_CHECK("trsv diag");
+    const int64_t rest = n - k - nb;
+    if (rest > 0) {
+      trsv_update_below<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(L, lda, k, nb, k + nb, n, m, B);
+      KRR_LAUNCH_CHECK("trsv_update_below");
+    }
+  }
+  return KRR_OK;
+}
+
+int trsv_lower_trans(int64_t n, int32_t m, const double* L, int64_t lda, double* B,
+                     hipStream_t s) {
+  if (n <= 0 || m <= 0) return KRR_OK;
+  if (m > 64) {
+    set_error("trsv_lower_trans: at most 64 right-hand sides");
+    return KRR_EINVAL;
+  }
+  const int64_t nblk = ceil_div(n, kNb);
+  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
+    const int64_t k = bk * kNb;
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    trsm_diag<true><<<1, 64, 0, s>>>(L + k * lda + k, lda, nb, B + k * m, m, m);
+    KRR_LAUNCH_CHECK("trsv diag T");
+    if (k > 0) {
+      trsv_update_above<<<(unsigned)ceil_div(k, 256), 256, 0, s>>>(L, lda, k, nb, m, B);
+      KRR_LAUNCH_CHECK("trsv_update_above");
+    }
   }
   return KRR_OK;
 }

@@ -258,8 +258,8 @@ int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) 
   const int64_t k = P.k;
   double* tmp = P.pcg.tmpN;  // k x m row-major staging (tmpN holds N >= k rows x m)
   KRR_TRY(to_rowmajor(R.p, k, m, tmp, s));
-  KRR_TRY(trsm_lower_left(k, m, P.C, k, tmp, m, s));
-  KRR_TRY(trsm_lower_left_trans(k, m, P.C, k, tmp, m, s));
+  KRR_TRY(trsv_lower(k, m, P.C, k, tmp, s));        // L^{-1} r
+  KRR_TRY(trsv_lower_trans(k, m, P.C, k, tmp, s));  // L^{-T} (L^{-1} r)
   return to_colmajor(tmp, k, m, Z.p, s);
 }
 
@@ -302,7 +302,13 @@ int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter
     return hip_check(hipStreamSynchronize(s), "stream sync");
   };
   KRR_TRY(pull());
-  for (int c = 0; c < m; ++c) active[c] = st.host[kActive * mm + c] != 0.0;
+  for (int c = 0; c < m; ++c) {
+    if (!std::isfinite(st.host[kBB * mm + c]) || !std::isfinite(st.host[kRZ * mm + c])) {
+      set_error("NaN/Inf in the right-hand side or its preconditioned residual, column %d", c);
+      return KRR_ENAN;
+    }
+    active[c] = st.host[kActive * mm + c] != 0.0;
+  }
   if (info && info->history) info->history_len = 0;
 
   const Red rd = red_for(n);

@@ -59,6 +59,22 @@ struct RPWork {
   double* spx = nullptr;    // pivot points, kBmax x dpad
 };
 
+// Build-time buffers of KRILL.
+struct KrillWork {
+  int* flags = nullptr;       // N
+  int* counts = nullptr;      // per 1024-block counts
+  int64_t* offs = nullptr;    // block offsets / sketch row offsets
+  int64_t* cand = nullptr;    // centre candidates
+  double* craw = nullptr;     // k x d centre points
+  int* rows = nullptr;        // N x zeta sketch rows
+  int* neg = nullptr;         // N x zeta sign bits
+  int* row_count = nullptr;   // d_rows + 1
+  int64_t* entries = nullptr; // N zeta: 2 j + neg, grouped by row
+  int64_t* tmp = nullptr;     // N zeta: sorted row lists
+  double* B = nullptr;        // d_rows x k sketch
+  int* ints = nullptr;        // [0] error flag, [1] Cholesky info
+};
+
 struct Precond {
   PrecondType type = kRPChol;
   krr_kernel_kind kind = KRR_GAUSSIAN;
@@ -86,6 +102,7 @@ struct Precond {
   double* H = nullptr;            // k x k: mu A_SS + shift I
   double* C = nullptr;            // k x k: lower Cholesky factor of P = B^T B + H
   std::vector<int64_t> centers_host;
+  KrillWork kw;
   // PCG state and scratch
   PcgState pcg;
   Arena scratch;
