@@ -127,6 +127,31 @@ int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec, con
  * L Q^T into the caller's buffer.                                          */
 int krr_rpchol_factor(krr_precond P, double* FT, hipStream_t stream);
 
+/* Restricted KRR (Sec. 2.2, eq. restricted_krr_eqn):
+ *   [A(S,:) A(:,S) + mu A(S,S)] beta = A(S,:) y
+ * with KRILL preconditioning (Alg. 2): H = mu A(S,S) + N eps tr(A(S,S)) I
+ * (eps = 2^-52), a sparse sign embedding Phi with `sketch_rows` rows
+ * (0 -> 2k) and `zeta` nonzeros per column (0 -> ceil(ln(k+1))),
+ * B = Phi A(:,S), P = B^T B + H = C^T C.  PCG runs on the shifted system
+ * (H in place of mu A(S,S)); the right-hand side A(S,:) y is formed in FP64.
+ * `centers`: device int64[k] of distinct indices in [0, N), or NULL to draw
+ * k centres uniformly without replacement with SplitMix64 keyed by `seed`.
+ * Limits: 1 <= k <= min(N, 65536), 1 <= zeta <= sketch_rows.
+ * The build synchronises `stream`.  Returns KRR_ENOTSPD if P cannot be
+ * factored.                                                                */
+int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d, int32_t k,
+                 int32_t sketch_rows, int32_t zeta, int32_t m_max, size_t* bytes);
+int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec, const double* X,
+                    int64_t N, int32_t d, double mu, const int64_t* centers, int32_t k,
+                    int32_t sketch_rows, int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
+                    size_t ws_bytes, krr_precond* out, hipStream_t stream);
+/* Copies a KRILL build product into a caller device buffer of `bytes`:
+ * what = 0: sketch rows, int32 N x zeta (column j's rows in draw order);
+ * 1: sketch signs, int32 N x zeta (+1 / -1); 2: B, FP64 sketch_rows x k;
+ * 3: H, FP64 k x k; 4: the lower factor L = C^T of P, FP64 k x k (strict
+ * upper triangle zero).                                                    */
+int krr_krill_export(krr_precond P, int32_t what, void* dst, size_t bytes, hipStream_t stream);
+
 /* Number of pivots / centres (RPCholesky: accepted pivots, may be < r when
  * the residual is exhausted; KRILL: k) and the system size n (N or k).     */
 int krr_precond_dims(krr_precond P, int32_t* rank, int64_t* n);
@@ -146,9 +171,11 @@ void krr_precond_free(krr_precond P);
 /* PCG (Sec. 3, eq. psd_system) from a zero start until every column reaches
  * ||r|| <= tol ||b|| on the recursive residual, or max_iter.  Y is N x m
  * (targets, row-major, device); beta receives n x m (N for full-data, k for
- * restricted).  The true residual is evaluated once at exit with an FP64
- * product; on the FP64 path one residual-replacement restart is made if it
- * exceeds 10 tol.  Synchronises `stream` once per iteration.  Returns
+ * restricted).  At exit the true residual is evaluated with an FP64 product.
+ * FP64 tiles: one residual-replacement restart if it exceeds 10 tol.
+ * FP32 / MIXED tiles: up to 4 rounds of iterative refinement (CG restarted
+ * from the FP64 true residual) until it meets tol; relres_true reports the
+ * final FP64 value.  Synchronises `stream` once per iteration.  Returns
  * KRR_NOT_CONVERGED (beta = last iterate) if a column did not converge and
  * KRR_ENAN on a NaN/Inf residual.                                          */
 int krr_pcg_solve(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,

@@ -84,11 +84,15 @@ extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precisi
   KRR_TRY(check_ws(ws, ws_bytes, need));
   Arena arena(ws, ws_bytes);
   PointSet rows, cols;
-  KRR_TRY(pack_points(kind, prec, Xr, nr, d, nullptr, arena, &rows, stream));
   if (Xc == Xr && nc == nr) {
+    KRR_TRY(pack_points(kind, prec, Xr, nr, d, nullptr, arena, &rows, stream));
     cols = rows;
   } else {
+    // columns first: under MIXED Gaussian tiles both sets share the
+    // columns' centre (distances are translation invariant)
     KRR_TRY(pack_points(kind, prec, Xc, nc, d, nullptr, arena, &cols, stream));
+    KRR_TRY(pack_points(kind, prec, Xr, nr, d, nc > 0 ? cols.centre : nullptr, arena, &rows,
+                        stream));
   }
   VecView v{V, m, 1};
   VecOut w{W, m, 1};

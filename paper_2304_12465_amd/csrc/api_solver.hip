@@ -229,3 +229,139 @@ extern "C" int krr_pcg_solve(krr_precond h, const double* Y, int32_t m, double t
   }
   return run_pcg(P, Y, m, tol, max_iter, beta, info, stream);
 }
+
+namespace {
+
+int krill_params(Precond& P, krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+                 int32_t k, int32_t sketch_rows, int32_t zeta, int32_t m_max) {
+  if (N < 1 || d < 1 || d > 64 || k < 1 || k > N || k > 65536 || m_max < 1 || m_max > 64 ||
+      sketch_rows < 0 || zeta < 0) {
+    set_error("invalid KRILL shape N=%lld d=%d k=%d sketch_rows=%d zeta=%d m_max=%d",
+              (long long)N, d, k, sketch_rows, zeta, m_max);
+    return KRR_EINVAL;
+  }
+  const int32_t ds = sketch_rows > 0 ? sketch_rows : 2 * k;
+  const int32_t z = zeta > 0 ? zeta : (int32_t)std::ceil(std::log((double)k + 1.0));
+  if (z > ds) {
+    set_error("zeta=%d exceeds the sketch rows %d", z, ds);
+    return KRR_EINVAL;
+  }
+  P.type = kKrill;
+  P.kind = kind;
+  P.prec = prec;
+  P.N = N;
+  P.d = d;
+  P.k = k;
+  P.sketch_rows = ds;
+  P.zeta = z;
+  P.m_max = m_max;
+  return KRR_OK;
+}
+
+__global__ void widen_signs(const int* __restrict__ neg, int64_t n, int* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = neg[t] ? -1 : 1;
+}
+
+}  // namespace
+
+extern "C" int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+                            int32_t k, int32_t sketch_rows, int32_t zeta, int32_t m_max,
+                            size_t* bytes) {
+  KRR_TRY(check_kernel(kind, 1.0, prec));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return KRR_EINVAL;
+  }
+  Precond P;
+  KRR_TRY(krill_params(P, kind, prec, N, d, k, sketch_rows, zeta, m_max));
+  Arena a;
+  KRR_TRY(krill_layout(a, P));
+  *bytes = a.used;
+  return KRR_OK;
+}
+
+extern "C" int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec,
+                               const double* X, int64_t N, int32_t d, double mu,
+                               const int64_t* centers, int32_t k, int32_t sketch_rows,
+                               int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
+                               size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+  KRR_TRY(check_kernel(kind, sigma, prec));
+  if (!out || !X) {
+    set_error("NULL argument");
+    return KRR_EINVAL;
+  }
+  if (!(mu > 0.0) || !std::isfinite(mu)) {
+    set_error("mu must be positive and finite");
+    return KRR_EINVAL;
+  }
+  *out = nullptr;
+  krr_precond h = new (std::nothrow) krr_precond_s;
+  if (!h) {
+    set_error("out of host memory");
+    return KRR_EINVAL;
+  }
+  Precond& P = h->P;
+  int rc = krill_params(P, kind, prec, N, d, k, sketch_rows, zeta, m_max);
+  if (rc == KRR_OK) {
+    P.sigma = sigma;
+    P.mu = mu;
+    P.seed = seed;
+    Arena meas;
+    rc = krill_layout(meas, P);
+    if (rc == KRR_OK) rc = finish_carve(P, ws, ws_bytes, meas.used);
+    if (rc == KRR_OK) {
+      Arena a(ws, ws_bytes);
+      rc = krill_layout(a, P);
+    }
+    if (rc == KRR_OK) rc = krill_build(P, X, centers, stream);
+  }
+  if (rc != KRR_OK) {
+    krr_precond_free(h);
+    return rc;
+  }
+  *out = h;
+  return KRR_OK;
+}
+
+extern "C" int krr_krill_export(krr_precond h, int32_t what, void* dst, size_t bytes,
+                                hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (P.type != kKrill) {
+    set_error("not a KRILL preconditioner");
+    return KRR_EINVAL;
+  }
+  const int64_t nz = P.N * P.zeta, kk = (int64_t)P.k * P.k;
+  size_t need = 0;
+  switch (what) {
+    case 0:
+    case 1: need = sizeof(int) * nz; break;
+    case 2: need = sizeof(double) * (size_t)P.sketch_rows * P.k; break;
+    case 3:
+    case 4: need = sizeof(double) * kk; break;
+    default:
+      set_error("unknown export %d", what);
+      return KRR_EINVAL;
+  }
+  if (!dst || bytes < need) {
+    set_error("export buffer too small: %zu < %zu", bytes, need);
+    return KRR_EINVAL;
+  }
+  switch (what) {
+    case 0:
+      return hip_check(hipMemcpyAsync(dst, P.kw.rows, need, hipMemcpyDeviceToDevice, stream), "export");
+    case 1:
+      widen_signs<<<(unsigned)ceil_div(nz, 256), 256, 0, stream>>>(P.kw.neg, nz, (int*)dst);
+      KRR_LAUNCH_CHECK("widen_signs");
+      return KRR_OK;
+    case 2:
+      return hip_check(hipMemcpyAsync(dst, P.kw.B, need, hipMemcpyDeviceToDevice, stream), "export");
+    case 3:
+      return hip_check(hipMemcpyAsync(dst, P.H, need, hipMemcpyDeviceToDevice, stream), "export");
+    default:
+      lower_copy<<<(unsigned)ceil_div(kk, 256), 256, 0, stream>>>(P.C, P.k, (double*)dst);
+      KRR_LAUNCH_CHECK("lower_copy");
+      return KRR_OK;
+  }
+}

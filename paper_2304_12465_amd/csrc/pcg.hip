@@ -18,6 +18,7 @@ namespace krr {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kMaxRefine = 4;  // refinement rounds for FP32 / MIXED tiles
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -359,11 +360,17 @@ int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter
       if (bb <= 0) continue;
       const double rt = std::sqrt(st.host[kTrue * mm + c] / bb);
       worst_true = std::max(worst_true, rt);
-      if (P.prec == KRR_FP64 && rt > 10.0 * tol) replace = true;
+      if (!std::isfinite(rt)) {
+        set_error("NaN/Inf in the true residual of column %d", c);
+        return KRR_ENAN;
+      }
+      // FP64 tiles: replace when the recurrence drifted (> 10 tol).
+      // FP32 / MIXED tiles: iterative refinement with the FP64 residual until
+      // it meets tol (the lower-precision operator limits the recurrence).
+      if (rt > (P.prec == KRR_FP64 ? 10.0 * tol : tol)) replace = true;
     }
-    // One residual-replacement restart on the FP64 path when the recursive
-    // residual drifted away from the true one.
-    if (!replace || restarts >= 1 || it >= max_iter) break;
+    const int max_restarts = P.prec == KRR_FP64 ? 1 : kMaxRefine;
+    if (!replace || restarts >= max_restarts || it >= max_iter) break;
     ++restarts;
     KRR_TRY(hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
                       "r = true residual"));

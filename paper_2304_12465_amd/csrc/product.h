@@ -16,6 +16,8 @@ struct PointSet {
   const uint16_t* xhi = nullptr;  // n x kpad bf16 bits
   const uint16_t* xlo = nullptr;
   const float* nrm = nullptr;     // n, ||x||^2 in FP32 of the centred point
+  const double* centre = nullptr; // d doubles subtracted before the split
+  double* cpart = nullptr;        // 256 x 64 partial sums for the centre
   int32_t kpad = 0;
 };
 
@@ -54,6 +56,19 @@ struct VecOut {
 int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointSet& rows,
             const PointSet& cols, VecView V, int32_t m, double shift, VecView Vs, VecOut W,
             Arena& scratch, hipStream_t s);
+
+// bf16-split MFMA path for Gaussian tiles (product_mfma.hip).
+int carve_mixed(int64_t n, int32_t d, Arena& arena, PointSet* out);
+int compute_centre(const double* X, int64_t n, int32_t d, double* centre, double* part,
+                   hipStream_t s);
+int fill_mixed(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
+size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc);
+int product_mfma(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int32_t m,
+                 double shift, VecView Vs, VecOut W, Arena& scratch, hipStream_t s);
+
+// Tile timer hooks: start returns a token (or null when timing is off).
+void* tile_timer_start(hipStream_t s);
+void tile_timer_stop(void* token, hipStream_t s);
 
 // Event timing of the product tile kernel launches (process-wide).
 void tile_timing_enable(bool on);

@@ -1,0 +1,417 @@
+// Gaussian kernel tiles on the bf16 matrix cores (precision KRR_MIXED).
+//
+// The squared distance is ||x||^2 + ||y||^2 - 2 x.y with the contraction x.y
+// on v_mfma_f32_16x16x32_bf16 using a hi/lo split of each coordinate
+// (x = hi + lo, three products hi.hi + hi.lo + lo.hi, FP32 accumulation),
+// after centring the points (distances are translation invariant; centring
+// shrinks ||x|| and with it the cancellation).  exp runs on the VALU in FP32.
+// The reduction against V is a second split-bf16 contraction on the matrix
+// cores: the output layout of the distance MFMA (lane l holds rows
+// 4(l/16)..4(l/16)+3 of a 16-column tile, column l%16) is, up to a fixed
+// permutation of the K index, the A-operand layout of the 16x16x32 MFMA,
+// so the exponentiated tile feeds the second MFMA without any lane shuffle.
+// FP32 partial sums fold into FP64 every 256 columns; per-split partials
+// go to fixed slots, so results are bitwise reproducible.
+#include "product.h"
+#include <algorithm>
+
+namespace krr {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// (a, b) -> bf16 hi parts (one v_cvt_pk_bf16_f32) and bf16 lo parts of the
+// remainders, packed as two 32-bit words.
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  const float ha = __builtin_bit_cast(float, hi << 16);
+  const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+  const bf16x2 l = __builtin_convertvector(f32x2{a - ha, b - hb}, bf16x2);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+constexpr int kRT = 4;       // 16-row tiles per wave
+constexpr int kCols = 32;    // columns per LDS chunk (two 16-column MFMA tiles)
+constexpr int kFoldChunks = 8;  // FP32 chunks per FP64 fold (256 columns)
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+__device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
+
+// Column permutation of the V-reduction MFMA's K index: slot v (0..7) of
+// lane group g holds column (v < 4 ? 4g + v : 16 + 4g + v - 4) of the chunk.
+__device__ __forceinline__ int slot_col(int g, int v) { return v < 4 ? 4 * g + v : 16 + 4 * g + (v - 4); }
+
+template <int KP>
+__global__ __launch_bounds__(256) void tile_mfma_gauss(
+    const uint16_t* __restrict__ Xhi, const uint16_t* __restrict__ Xlo,
+    const float* __restrict__ Xn, int64_t nr, const uint16_t* __restrict__ Yhi,
+    const uint16_t* __restrict__ Ylo, const float* __restrict__ Yn,
+    const uint16_t* __restrict__ Vhi, const uint16_t* __restrict__ Vlo, int64_t nc, float s,
+    int nsplit, int64_t cols_per_split, int M, double* __restrict__ part) {
+  constexpr int KS = KP / 32;      // MFMA K steps of the distance contraction
+  constexpr int YP = KP + 8;       // LDS row pitch (bf16) of the column points
+  __shared__ __attribute__((aligned(16))) __bf16 sYh[kCols][YP];
+  __shared__ __attribute__((aligned(16))) __bf16 sYl[kCols][YP];
+  __shared__ __attribute__((aligned(16))) float sAy[kCols];
+  __shared__ __attribute__((aligned(16))) __bf16 sVh[16][kCols + 8];  // [c][slot], slot = 8g + v
+  __shared__ __attribute__((aligned(16))) __bf16 sVl[16][kCols + 8];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t bid = blockIdx.x;
+  const int split = (int)(bid % nsplit);
+  const int64_t rg = bid / nsplit;
+  const int64_t row0 = (rg * 4 + wave) * (16 * kRT);
+
+  // row operands (B of the distance MFMA): X[i0 + li][8g .. 8g+8] per K step
+  bf16x8 xh[kRT][KS], xl[kRT][KS];
+  float ax[kRT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+    int64_t i = row0 + rt * 16 + li;
+    if (i > nr - 1) i = nr - 1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      xh[rt][ks] = *reinterpret_cast<const bf16x8*>(Xhi + i * KP + ks * 32 + g * 8);
+      xl[rt][ks] = *reinterpret_cast<const bf16x8*>(Xlo + i * KP + ks * 32 + g * 8);
+    }
+    ax[rt] = -s * Xn[i];
+  }
+  f32x4 acc[kRT];
+  double acc64[kRT][4];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+    acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc64[rt][u] = 0.0;
+  }
+  const float s2 = 2.0f * s;
+
+  const int64_t j0 = (int64_t)split * cols_per_split;
+  int64_t j1 = j0 + cols_per_split;
+  if (j1 > nc) j1 = nc;
+  int chunk = 0;
+  for (int64_t jb = j0; jb < j1; jb += kCols, ++chunk) {
+    __syncthreads();
+    // stage the chunk: points (hi/lo), -s*||y||^2, and V (hi/lo, permuted)
+    for (int e = tid; e < kCols * (KP / 8); e += 256) {
+      const int jj = e / (KP / 8), seg = e % (KP / 8);
+      const int64_t j = jb + jj;
+      bf16x8 h, l;
+      if (j < j1) {
+        h = *reinterpret_cast<const bf16x8*>(Yhi + j * KP + seg * 8);
+        l = *reinterpret_cast<const bf16x8*>(Ylo + j * KP + seg * 8);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          h[q] = to_bf16(0.f);
+          l[q] = to_bf16(0.f);
+        }
+      }
+      *reinterpret_cast<bf16x8*>(&sYh[jj][seg * 8]) = h;
+      *reinterpret_cast<bf16x8*>(&sYl[jj][seg * 8]) = l;
+    }
+    if (tid < kCols) {
+      const int64_t j = jb + tid;
+      // columns past the range get a huge distance: exp -> 0
+      sAy[tid] = (j < j1) ? -s * Yn[j] : -3.0e38f;
+    }
+    for (int e = tid; e < 16 * kCols; e += 256) {
+      const int c = e / kCols, slot = e % kCols;
+      const int col = slot_col(slot / 8, slot % 8);
+      const int64_t j = jb + col;
+      uint16_t vh = 0, vl = 0;
+      if (j < j1 && c < M) {
+        vh = Vhi[j * 16 + c];
+        vl = Vlo[j * 16 + c];
+      }
+      sVh[c][slot] = __builtin_bit_cast(__bf16, vh);
+      sVl[c][slot] = __builtin_bit_cast(__bf16, vl);
+    }
+    __syncthreads();
+    if (row0 >= nr) continue;  // idle wave still joins the barriers
+    // A operands of the distance MFMA for the two column tiles
+    bf16x8 yh[2][KS], yl[2][KS];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        yh[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYh[ct * 16 + li][ks * 32 + g * 8]);
+        yl[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYl[ct * 16 + li][ks * 32 + g * 8]);
+      }
+    float ay[2][4];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ay[ct][u] = sAy[ct * 16 + 4 * g + u];
+    const bf16x8 vh = *reinterpret_cast<const bf16x8*>(&sVh[li][g * 8]);
+    const bf16x8 vl = *reinterpret_cast<const bf16x8*>(&sVl[li][g * 8]);
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      uint32_t eh[4], el[4];  // 8 bf16 each: K slots 8g .. 8g+7
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        f32x4 dot = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xh[rt][ks], dot, 0, 0, 0);
+          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xl[rt][ks], dot, 0, 0, 0);
+          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[ct][ks], xh[rt][ks], dot, 0, 0, 0);
+        }
+        // dot[u] = y_{4g+u} . x_{li} of column tile ct; the exponent
+        // -s (||x||^2 + ||y||^2 - 2 x.y) is left unclamped: rounding can make
+        // it ~1e-6 positive, within the split's error budget.
+        float e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          e[u] = __builtin_amdgcn_exp2f(__builtin_fmaf(dot[u], s2, ax[rt] + ay[ct][u]));
+        split_pair(e[0], e[1], eh[ct * 2 + 0], el[ct * 2 + 0]);
+        split_pair(e[2], e[3], eh[ct * 2 + 1], el[ct * 2 + 1]);
+      }
+      const bf16x8 EH = __builtin_bit_cast(bf16x8, eh);
+      const bf16x8 EL = __builtin_bit_cast(bf16x8, el);
+      // W[i][c] += sum_j E[i][j] V[j][c]: A = E (rows li, K slots 8g..8g+7)
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vh, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vl, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EL, vh, acc[rt], 0, 0, 0);
+    }
+    if ((chunk + 1) % kFoldChunks == 0) {
+#pragma unroll
+      for (int rt = 0; rt < kRT; ++rt) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc64[rt][u] += (double)acc[rt][u];
+        acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+  if (row0 >= nr) return;
+  double* __restrict__ out = part + (int64_t)split * nr * 16;
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // E.V output: lane l holds W[i0 + 4g + u][c = li]
+      const int64_t i = row0 + rt * 16 + 4 * g + u;
+      if (i < nr && li < M) out[i * 16 + li] = acc64[rt][u] + (double)acc[rt][u];
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace krr
+
+namespace krr {
+
+namespace {
+
+// centre = mean of the points, two fixed-order stages
+__global__ __launch_bounds__(64) void centre_part(const double* __restrict__ X, int64_t n, int d,
+                                                  int64_t chunk, double* __restrict__ part) {
+  const int k = threadIdx.x;
+  if (k >= d) return;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  double s = 0.0;
+  for (int64_t i = i0; i < i1; ++i) s += X[i * d + k];
+  part[(int64_t)blockIdx.x * d + k] = s;
+}
+
+__global__ void centre_final(const double* __restrict__ part, int nb, int d, int64_t n,
+                             double* __restrict__ c) {
+  const int k = threadIdx.x;
+  if (k >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * d + k];
+  c[k] = s / (double)n;
+}
+
+// hi/lo bf16 split of the centred coordinates and FP32 squared norms
+__global__ void pack_split(const double* __restrict__ X, int64_t n, int d, int kp,
+                           const double* __restrict__ centre, uint16_t* __restrict__ hi,
+                           uint16_t* __restrict__ lo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * kp) return;
+  const int64_t i = t / kp;
+  const int k = (int)(t % kp);
+  double v = 0.0;
+  if (k < d) v = X[i * d + k] - (centre ? centre[k] : 0.0);
+  const __bf16 h = (__bf16)(float)v;
+  const __bf16 l = (__bf16)(float)(v - (double)(float)h);
+  hi[t] = __builtin_bit_cast(uint16_t, h);
+  lo[t] = __builtin_bit_cast(uint16_t, l);
+}
+
+__global__ void pack_norms(const double* __restrict__ X, int64_t n, int d,
+                           const double* __restrict__ centre, float* __restrict__ nrm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double v = X[i * d + k] - (centre ? centre[k] : 0.0);
+    s += v * v;
+  }
+  nrm[i] = (float)s;
+}
+
+// V (n x m, strided) -> hi/lo bf16, n x 16, columns c0 .. c0+mc, zero padded
+__global__ void pack_vsplit(VecView V, int64_t n, int c0, int mc, uint16_t* __restrict__ hi,
+                            uint16_t* __restrict__ lo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 16) return;
+  const int64_t j = t / 16;
+  const int c = (int)(t % 16);
+  float v = 0.f;
+  double vd = 0.0;
+  if (c < mc) {
+    vd = V.p[j * V.rs + (int64_t)(c0 + c) * V.cs];
+    v = (float)vd;
+  }
+  const __bf16 h = (__bf16)v;
+  const __bf16 l = (__bf16)(float)(vd - (double)(float)h);
+  hi[t] = __builtin_bit_cast(uint16_t, h);
+  lo[t] = __builtin_bit_cast(uint16_t, l);
+}
+
+__global__ void reduce_splits16(const double* __restrict__ part, int nsplit, int64_t nr, int mc,
+                                int c0, double shift, VecView Vs, VecOut W) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nr * mc) return;
+  const int64_t i = t / mc;
+  const int c = (int)(t % mc);
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * nr + i) * 16 + c];
+  if (shift != 0.0) s += shift * Vs.p[i * Vs.rs + (int64_t)(c0 + c) * Vs.cs];
+  W.p[i * W.rs + (int64_t)(c0 + c) * W.cs] = s;
+}
+
+struct MSplit {
+  int nsplit;
+  int64_t per;
+};
+
+MSplit mfma_split(int64_t nr, int64_t nc) {
+  const int64_t rows_per_wg = 4 * 16 * kRT;
+  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
+  int64_t ns = ceil_div(2048, rg);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / 256));
+  if (ns >= 8) ns = ns / 8 * 8;
+  ns = std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+  int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
+  per = ceil_div(per, kCols) * kCols;  // whole chunks per split
+  return {(int)ns, per};
+}
+
+}  // namespace
+
+int carve_mixed(int64_t n, int32_t d, Arena& arena, PointSet* out) {
+  const int kp = mfma_kdim(d);
+  if (kp > 64) {
+    set_error("MIXED Gaussian tiles support d <= 64");
+    return KRR_EINVAL;
+  }
+  out->kpad = kp;
+  out->xhi = arena.take<uint16_t>((size_t)n * kp);
+  out->xlo = arena.take<uint16_t>((size_t)n * kp);
+  out->nrm = arena.take<float>(n);
+  out->centre = arena.take<double>(64);
+  out->cpart = arena.take<double>(256 * 64);
+  return KRR_OK;
+}
+
+int compute_centre(const double* X, int64_t n, int32_t d, double* centre, double* part,
+                   hipStream_t s) {
+  if (n <= 0) return hip_check(hipMemsetAsync(centre, 0, sizeof(double) * d, s), "centre");
+  const int nb = (int)std::min<int64_t>(256, n);
+  const int64_t chunk = ceil_div(n, nb);
+  const int nbe = (int)ceil_div(n, chunk);
+  centre_part<<<nbe, 64, 0, s>>>(X, n, d, chunk, part);
+  KRR_LAUNCH_CHECK("centre_part");
+  centre_final<<<1, 64, 0, s>>>(part, nbe, d, n, centre);
+  KRR_LAUNCH_CHECK("centre_final");
+  return KRR_OK;
+}
+
+int fill_mixed(const double* X, const double* centre, const PointSet& ps, hipStream_t s) {
+  const int64_t n = ps.n;
+  if (n == 0) return KRR_OK;
+  if (!X || !ps.xhi) {
+    set_error("fill_mixed: NULL points or layout");
+    return KRR_EINVAL;
+  }
+  if (centre && centre != ps.centre)
+    KRR_TRY(hip_check(hipMemcpyAsync(const_cast<double*>(ps.centre), centre, sizeof(double) * ps.d,
+                                     hipMemcpyDeviceToDevice, s), "centre copy"));
+  if (!centre) KRR_TRY(compute_centre(X, n, ps.d, const_cast<double*>(ps.centre), ps.cpart, s));
+  const double* c = ps.centre;
+  pack_split<<<(unsigned)ceil_div(n * ps.kpad, 256), 256, 0, s>>>(
+      X, n, ps.d, ps.kpad, c, const_cast<uint16_t*>(ps.xhi), const_cast<uint16_t*>(ps.xlo));
+  KRR_LAUNCH_CHECK("pack_split");
+  pack_norms<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(X, n, ps.d, c, const_cast<float*>(ps.nrm));
+  KRR_LAUNCH_CHECK("pack_norms");
+  return KRR_OK;
+}
+
+size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc) {
+  MSplit sp = mfma_split(nr, nc);
+  Arena a;
+  a.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  a.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  a.take<double>((size_t)sp.nsplit * std::max<int64_t>(nr, 1) * 16);
+  return a.used;
+}
+
+int product_mfma(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int32_t m,
+                 double shift, VecView Vs, VecOut W, Arena& scratch, hipStream_t s) {
+  const int64_t nr = rows.n, nc = cols.n;
+  if (rows.kpad != cols.kpad || !rows.xhi || !cols.xhi) {
+    set_error("MIXED product: point layouts missing or inconsistent");
+    return KRR_EINVAL;
+  }
+  const int KP = rows.kpad;
+  const float sc = (float)(1.4426950408889634 / (2.0 * sigma * sigma));
+  const size_t mark = scratch.used;
+  for (int c0 = 0; c0 < m; c0 += 16) {
+    const int mc = std::min(16, m - c0);
+    scratch.used = mark;
+    MSplit sp = mfma_split(nr, nc);
+    uint16_t* vh = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+    uint16_t* vl = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+    double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
+    if (!scratch.ok()) {
+      set_error("MIXED product scratch too small");
+      return KRR_EWORKSPACE;
+    }
+    if (nc > 0) {
+      pack_vsplit<<<(unsigned)ceil_div(nc * 16, 256), 256, 0, s>>>(V, nc, c0, mc, vh, vl);
+      KRR_LAUNCH_CHECK("pack_vsplit");
+      const int64_t rg = ceil_div(nr, (int64_t)4 * 16 * kRT);
+      const unsigned grid = (unsigned)(rg * sp.nsplit);
+      void* tok = tile_timer_start(s);
+      if (KP == 32)
+        tile_mfma_gauss<32><<<grid, 256, 0, s>>>(rows.xhi, rows.xlo, rows.nrm, nr, cols.xhi,
+                                                 cols.xlo, cols.nrm, vh, vl, nc, sc, sp.nsplit,
+                                                 sp.per, mc, part);
+      else
+        tile_mfma_gauss<64><<<grid, 256, 0, s>>>(rows.xhi, rows.xlo, rows.nrm, nr, cols.xhi,
+                                                 cols.xlo, cols.nrm, vh, vl, nc, sc, sp.nsplit,
+                                                 sp.per, mc, part);
+      KRR_LAUNCH_CHECK("tile_mfma_gauss");
+      tile_timer_stop(tok, s);
+    }
+    const int ns = nc > 0 ? sp.nsplit : 0;
+    reduce_splits16<<<(unsigned)ceil_div(nr * mc, 256), 256, 0, s>>>(part, ns, nr, mc, c0, shift,
+                                                                     Vs, W);
+    KRR_LAUNCH_CHECK("reduce_splits16");
+  }
+  scratch.used = mark;
+  return KRR_OK;
+}
+
+}  // namespace krr

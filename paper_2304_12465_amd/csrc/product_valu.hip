@@ -238,6 +238,25 @@ TileTimer& timer() {
 
 }  // namespace
 
+void* tile_timer_start(hipStream_t s) {
+  TileTimer& tt = timer();
+  std::lock_guard<std::mutex> g(tt.mu);
+  if (!tt.on) return nullptr;
+  hipEvent_t e0 = tt.get(), e1 = tt.get();
+  if (!e0 || !e1) return nullptr;
+  (void)hipEventRecord(e0, s);
+  tt.ev.emplace_back(e0, e1);
+  return reinterpret_cast<void*>(tt.ev.size());  // 1-based index
+}
+
+void tile_timer_stop(void* token, hipStream_t s) {
+  if (!token) return;
+  TileTimer& tt = timer();
+  std::lock_guard<std::mutex> g(tt.mu);
+  const size_t i = reinterpret_cast<size_t>(token) - 1;
+  if (i < tt.ev.size()) (void)hipEventRecord(tt.ev[i].second, s);
+}
+
 void tile_timing_enable(bool on) {
   TileTimer& t = timer();
   std::lock_guard<std::mutex> g(t.mu);
@@ -292,11 +311,8 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
     out->x64 = arena.take<double>((size_t)n * D);
     return KRR_OK;
   }
-  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) {
-    set_error("MIXED Gaussian tiles are not available in this build");
-    return KRR_EINVAL;
-  }
   out->x32 = arena.take<float>((size_t)n * D);
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) KRR_TRY(carve_mixed(n, d, arena, out));
   return KRR_OK;
 }
 
@@ -319,13 +335,14 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     KRR_LAUNCH_CHECK("pack_pts<double>");
     return KRR_OK;
   }
-  (void)kind;
   if (!ps.x32) {
     set_error("fill_points: layout not carved");
     return KRR_EINVAL;
   }
-  pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, centre, const_cast<float*>(ps.x32));
+  // FP32 points are not centred (VALU tiles use direct differences)
+  pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr, const_cast<float*>(ps.x32));
   KRR_LAUNCH_CHECK("pack_pts<float>");
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) return fill_mixed(X, centre, ps, s);
   return KRR_OK;
 }
 
@@ -350,6 +367,7 @@ size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t
   Arena a;
   a.take<char>((size_t)std::max<int64_t>(nc, 1) * M * es);
   a.take<double>((size_t)ns * std::max<int64_t>(nr, 1) * M);
+  if (prec == KRR_MIXED) return std::max(a.used, product_mfma_scratch_bytes(nr, nc));
   return a.used;
 }
 
@@ -362,6 +380,8 @@ int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointS
     set_error("row and column point sets differ in dimension");
     return KRR_EINVAL;
   }
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN)
+    return product_mfma(sigma, rows, cols, V, m, shift, Vs, W, scratch, s);
   const int D = rows.dpad;
   const bool f64 = prec == KRR_FP64;
   const int R = rows_for_dpad(D);
@@ -389,16 +409,7 @@ int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointS
       KRR_LAUNCH_CHECK("pack_vec");
       const int64_t rg = ceil_div(nr, (int64_t)kWaves * 64 * R);
       const unsigned grid = (unsigned)(rg * sp.nsplit);
-      hipEvent_t ev0 = nullptr, ev1 = nullptr;
-      {
-        TileTimer& tt = timer();
-        std::lock_guard<std::mutex> g(tt.mu);
-        if (tt.on) {
-          ev0 = tt.get();
-          ev1 = tt.get();
-          if (ev0 && ev1) (void)hipEventRecord(ev0, s);
-        }
-      }
+      void* tok = tile_timer_start(s);
       const double log2e = 1.4426950408889634;
       if (f64) {
         const double sc = kind == KRR_LAPLACE ? -1.0 / sigma : -1.0 / (2.0 * sigma * sigma);
@@ -417,12 +428,7 @@ int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointS
                                                            sp.per, part);
       }
       KRR_LAUNCH_CHECK("tile_valu");
-      if (ev0 && ev1) {
-        (void)hipEventRecord(ev1, s);
-        TileTimer& tt = timer();
-        std::lock_guard<std::mutex> g(tt.mu);
-        tt.ev.emplace_back(ev0, ev1);
-      }
+      tile_timer_stop(tok, s);
     }
     const int ns = nc > 0 ? sp.nsplit : 0;
     const int64_t tot = nr * mc;

@@ -1,0 +1,202 @@
+"""Parity of the KRILL build and restricted solve (Alg. 2) against the FP64
+oracle.
+
+Tolerances:
+* centres, sketch rows and signs: bit-exact (integer work).
+* H (FP64 kernel entries): 1e-13 relative to max |H|.
+* B = Phi A(:,S): FP64 tiles 1e-12 * (|Phi| |A(:,S)|); FP32 tiles
+  2e-5 * (|Phi| |A(:,S)|) (same entry bound as the product tiles).
+* P = L L^T (FP64 tiles): 1e-10 relative to max |P|.
+* restricted operator M v: FP64 1e-12, FP32 tiles 4e-5, relative to
+  (|A_SN| |A_NS| |v| + |H| |v|).
+* solutions: fitted values A(:,S) beta within 1e-6 (FP64) / 1e-4 (FP32) of
+  the oracle's, relative 2-norm.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as OK
+from oracle import krill as OKR
+from oracle import pcg as OPCG
+from oracle.rng import sm, key, below, TAG_SKETCH_ROW
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def B():
+    from paper_2304_12465_amd import binding
+    return binding
+
+
+def T(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(DEV)
+
+
+def small(n=2000, k=100):
+    return synth.c4(n=n, k=k)
+
+
+def build(p, prec, centers=None, m_max=1, zeta=None):
+    c = None if centers is None else T(centers, np.int64)
+    return B().krill_build(p.kind, p.sigma, prec, T(p.X), p.mu, p.centers, centers=c,
+                           sketch_rows=p.sketch_rows, zeta=zeta or p.zeta, seed=p.algo_seed,
+                           m_max=m_max)
+
+
+def test_centres_and_sketch_bit_exact():
+    p = small()
+    P = build(p, 0)
+    S_o = OKR.sample_centers(p.X.shape[0], p.centers, p.algo_seed)
+    assert P.pivots() == [int(v) for v in S_o]
+    N, z = p.X.shape[0], p.zeta
+    rows = B().krill_export(P, 0, (N, z), torch.int32).cpu().numpy()
+    signs = B().krill_export(P, 1, (N, z), torch.int32).cpu().numpy()
+    r_o, s_o = OKR.sketch_columns(N, p.sketch_rows, z, p.algo_seed)
+    np.testing.assert_array_equal(rows, r_o)
+    np.testing.assert_array_equal(signs, s_o.astype(np.int32))
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_sketch_H_and_factor(prec, tol):
+    p = small()
+    P = build(p, prec)
+    k = p.centers
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, np.array(P.pivots()), sketch_rows=p.sketch_rows,
+                   zeta=p.zeta, seed=p.algo_seed)
+    Bg = B().krill_export(P, 2, (p.sketch_rows, k), torch.float64).cpu().numpy()
+    bound = tol * (np.abs(kr.Phi) @ np.abs(kr.AnS)) + 1e-300
+    assert np.all(np.abs(Bg - kr.B) <= bound), np.max(np.abs(Bg - kr.B) / bound)
+    Hg = B().krill_export(P, 3, (k, k), torch.float64).cpu().numpy()
+    np.testing.assert_allclose(Hg, kr.H, rtol=0, atol=1e-13 * np.abs(kr.H).max())
+    if prec == 0:
+        L = B().krill_export(P, 4, (k, k), torch.float64).cpu().numpy()
+        assert np.all(np.triu(L, 1) == 0)
+        np.testing.assert_allclose(L @ L.T, kr.P, rtol=0, atol=1e-10 * np.abs(kr.P).max())
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 4e-5)])
+def test_restricted_operator(prec, tol):
+    p = small()
+    P = build(p, prec, m_max=2)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    V = np.random.default_rng(3).standard_normal((p.centers, 2))
+    got = P.operator(T(V)).cpu().numpy()
+    ref = kr.product(V)
+    scale = np.abs(kr.AnS).T @ (np.abs(kr.AnS) @ np.abs(V)) + np.abs(kr.H) @ np.abs(V)
+    assert np.all(np.abs(got - ref) <= tol * scale), np.max(np.abs(got - ref) / scale)
+
+
+def test_restricted_solve_matches_oracle_fp64():
+    p = small(n=3000, k=150)
+    P = build(p, 0)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=200)
+    b = kr.rhs(p.Y)
+    xo, io = OPCG.pcg(kr.product, kr.precondition, b, p.tol, 200)
+    assert info["converged"] and io["converged"]
+    assert info["iters"] <= 60
+    fit = kr.AnS @ beta.cpu().numpy()
+    fit_o = kr.AnS @ xo
+    rel = np.linalg.norm(fit - fit_o) / np.linalg.norm(fit_o)
+    assert rel <= 1e-6, rel
+    assert abs(info["iters"] - int(io["iters"][0])) <= 1
+
+
+def test_restricted_solve_fp32_tiles_within_derived_bounds():
+    # FP32 tiles perturb the restricted operator by at most
+    # delta * (|A_SN||A_NS| + |H|)|v| with delta = 4e-5 (test_restricted_operator).
+    # The FP64 true residual of the returned beta is therefore bounded by
+    # tol ||b|| + delta ||(|A_SN||A_NS| + |H|)|beta|||, and its distance to the
+    # oracle's solution in the M-norm by (||b - M beta|| + ||b - M x_o||) /
+    # sqrt(lambda_min(M)).  (With mu/N = 1e-5 the restricted matrix is
+    # ill-conditioned, so fitted values can differ by more than the operator
+    # error; the bounds above are what the arithmetic guarantees.)
+    p = small(n=3000, k=150)
+    P = build(p, 1)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=200)
+    assert info["converged"] and info["iters"] <= 60
+    beta = beta.cpu().numpy()
+    b = kr.rhs(p.Y)
+    M = kr.restricted_matrix()
+    xo, io = OPCG.pcg(kr.product, kr.precondition, b, p.tol, 200)
+    absop = np.abs(kr.AnS).T @ (np.abs(kr.AnS) @ np.abs(beta)) + np.abs(kr.H) @ np.abs(beta)
+    r_true = np.linalg.norm(b - M @ beta)
+    assert r_true <= p.tol * np.linalg.norm(b) + 4e-5 * np.linalg.norm(absop)
+    e = (beta - xo)[:, 0]
+    bound = (r_true + np.linalg.norm(b - M @ xo)) / np.sqrt(np.linalg.eigvalsh(M).min())
+    assert np.sqrt(e @ M @ e) <= 1.01 * bound
+    rel = np.linalg.norm(kr.AnS @ e) / np.linalg.norm(kr.AnS @ xo)
+    print(f"fp32-tile fitted-value difference vs oracle: {rel:.2e}")
+
+
+def test_given_centres_and_multi_rhs():
+    p = small()
+    S = np.sort(np.random.default_rng(4).choice(p.X.shape[0], p.centers, replace=False))
+    P = build(p, 0, centers=S, m_max=3)
+    assert P.pivots() == [int(v) for v in S]
+    Y = np.column_stack([p.Y[:, 0], np.random.default_rng(5).standard_normal(p.X.shape[0])])
+    beta, info = P.solve(T(Y), 1e-8, 200)
+    assert info["converged"]
+    beta = beta.cpu().numpy()
+    for c in range(2):
+        b1, _ = P.solve(T(Y[:, c].copy()), 1e-8, 200)
+        np.testing.assert_allclose(beta[:, c], b1.cpu().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_all_points_as_centres():
+    # S = [N] with A well conditioned: (A^2 + mu A) b = A y gives
+    # b = (A + mu I)^{-1} y (Sec. 2.2); same instance as the oracle's pin.
+    g = np.random.default_rng(3)
+    n = 150
+    X = 3.0 * g.standard_normal((n, 3))
+    y = g.standard_normal((n, 1))
+    assert np.linalg.eigvalsh(OK.block(X, X, 0, 1.0)).min() > 1e-3
+    p = synth.Problem("all", X, y, 0, 1.0, 0.3, centers=n, sketch_rows=2 * n, zeta=4)
+    P = build(p, 0, centers=np.arange(n))
+    beta, info = P.solve(T(y), 1e-13, 300)
+    assert info["converged"]
+    from oracle import direct
+    xf = direct.full_krr(X, y, 0, 1.0, 0.3)
+    np.testing.assert_allclose(beta.cpu().numpy(), xf, rtol=1e-8, atol=1e-9 * np.abs(xf).max())
+
+
+def test_invalid_arguments():
+    b = B()
+    p = small(n=500, k=50)
+    with pytest.raises(b.KrrError):
+        b.krill_build(p.kind, p.sigma, 0, T(p.X), p.mu, 600)            # k > N
+    with pytest.raises(b.KrrError):
+        b.krill_build(p.kind, p.sigma, 0, T(p.X), p.mu, 50, sketch_rows=4, zeta=8)
+    with pytest.raises(b.KrrError):
+        b.krill_build(p.kind, p.sigma, 0, T(p.X), -1.0, 50)
+
+
+def test_full_size_restricted_solve():
+    # 2,000,000 points, d = 16, k = 10,000 centres, sketch 20,000 x 8.
+    p = synth.c4()
+    P = build(p, 1)
+    N = p.X.shape[0]
+    S_o = OKR.sample_centers(N, p.centers, p.algo_seed)
+    assert P.pivots() == [int(v) for v in S_o]
+    g = np.random.default_rng(8)
+    cols = np.sort(g.choice(N, 64, replace=False))
+    rows = B().krill_export(P, 0, (N, p.zeta), torch.int32).cpu().numpy()
+    for j in cols:
+        r, _ = OKR.sketch_column(int(j), p.sketch_rows, p.zeta, p.algo_seed)
+        assert list(rows[j]) == r
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=100)
+    assert info["converged"], info
+    assert info["iters"] <= 60, info
+    assert info["relres_true"] <= 10 * p.tol, info

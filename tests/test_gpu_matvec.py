@@ -135,3 +135,71 @@ def test_full_size_laplace_sampled_rows(prec):
     ref = Kb @ V + p.mu * V[rows]
     scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
     assert np.all(np.abs(W[rows] - ref) <= TOL[prec] * scale)
+
+
+def mixed_tol(Xr, Xc, sigma):
+    """Bound on |dW| / sum|K||V| for the bf16-split MFMA tiles.
+
+    With centred points (radius R = max ||x - c||, c = mean of the columns)
+    the split dot product misses lo.lo (<= 2^-16 |x||y|) and accumulates in
+    FP32 (<= 3 d 2^-24 |x||y|), so each exponent is off by at most
+    2 (2^-16 + 3 d 2^-24) R^2 / (2 sigma^2); the exponentiated entry and V
+    are split again (2 x 2^-16) and at most 256 terms are summed in FP32.
+    """
+    c = Xc.mean(axis=0)
+    R2 = max(np.max(np.sum((Xr - c) ** 2, axis=1)), np.max(np.sum((Xc - c) ** 2, axis=1)))
+    d = Xr.shape[1]
+    return 2 * (2 ** -16 + 3 * d * 2 ** -24) * R2 / (2 * sigma ** 2) + 3 * 2 ** -16 + 256 * 2 ** -24
+
+
+def check_mixed(Xr, Xc, V, sigma, shift=0.0):
+    W = run(0, 2, Xr, Xc, V, sigma, shift)
+    Kb = OK.block(Xr, Xc, 0, sigma)
+    ref = Kb @ V + (shift * V if shift else 0)
+    scale = np.abs(Kb) @ np.abs(V) + (abs(shift) * np.abs(V) if shift else 0)
+    tol = mixed_tol(Xr, Xc, sigma)
+    err = np.abs(W - ref)
+    assert np.all(err <= tol * scale + 1e-300), (np.max(err / scale), tol)
+    return float(np.max(err / scale))
+
+
+@pytest.mark.parametrize("d", [3, 8, 16, 20, 32, 33, 64])
+def test_mixed_gaussian_square(d):
+    g = np.random.default_rng(200 + d)
+    n = 1337
+    X = g.standard_normal((n, d))
+    V = g.standard_normal((n, 1))
+    check_mixed(X, X, V, np.sqrt(d), shift=0.37)
+
+
+@pytest.mark.parametrize("m", [1, 3, 16, 17, 40])
+def test_mixed_gaussian_rectangular_rhs(m):
+    g = np.random.default_rng(300 + m)
+    Xr = g.standard_normal((700, 24)) + 1.0
+    Xc = g.standard_normal((2100, 24))
+    V = g.standard_normal((2100, m))
+    check_mixed(Xr, Xc, V, 4.0)
+
+
+def test_mixed_laplace_is_fp32_tiles():
+    g = np.random.default_rng(9)
+    X = g.standard_normal((900, 12))
+    V = g.standard_normal((900, 2))
+    W2 = run(1, 2, X, X, V, 5.0)
+    W1 = run(1, 1, X, X, V, 5.0)
+    np.testing.assert_array_equal(W2, W1)
+
+
+def test_mixed_full_size_uniform_sampled_rows():
+    # 1,000,000 points in [0,1]^32 with near-duplicates, 8 right-hand sides:
+    # 64 sampled rows against the oracle.
+    p = synth.c3()
+    g = np.random.default_rng(12)
+    V = g.standard_normal((p.X.shape[0], 8))
+    W = run(0, 2, p.X, p.X, V, p.sigma, shift=p.mu)
+    rows = np.sort(g.choice(p.X.shape[0], 64, replace=False))
+    Kb = OK.block(p.X[rows], p.X, 0, p.sigma)
+    ref = Kb @ V + p.mu * V[rows]
+    scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
+    tol = mixed_tol(p.X[rows], p.X, p.sigma)
+    assert np.all(np.abs(W[rows] - ref) <= tol * scale), np.max(np.abs(W[rows] - ref) / scale)
