@@ -181,6 +181,25 @@ void krr_precond_free(krr_precond P);
 int krr_pcg_solve(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,
                   double* beta, krr_solve_info* info, hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Stepped solves for serving (continuous batching).  A krr_solve is the
+ * PCG state of one request (kept in its precond's workspace: one active
+ * solve per precond).  krr_solve_step advances n solves by one PCG step
+ * each: their direction products share kernel launches (tiles of every
+ * product that uses the same kernel instantiation are dealt over one grid),
+ * then one host synchronisation serves all of them.  Each product keeps the
+ * tile decomposition it has alone, so every result is bitwise identical
+ * alone and in any mix.  state (host, n entries) receives 0 = running,
+ * 1 = finished, or a negative error of that solve only (the others go on).
+ * krr_solve_end writes beta (n x m, row-major) and info, frees the solve
+ * and returns what krr_pcg_solve would; krr_solve_free abandons a solve.  */
+typedef struct krr_solve_s* krr_solve;
+int krr_solve_begin(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,
+                    krr_solve* out, hipStream_t stream);
+int krr_solve_step(krr_solve* solves, int32_t n, int32_t* state, hipStream_t stream);
+int krr_solve_end(krr_solve S, double* beta, krr_solve_info* info, hipStream_t stream);
+void krr_solve_free(krr_solve S);
+
 #ifdef __cplusplus
 }
 #endif

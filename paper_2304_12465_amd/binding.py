@@ -52,6 +52,10 @@ _SIGS = {
     "krr_precond_apply": ([_vp, _vp, _i32, _vp, _vp], _i32),
     "krr_precond_operator": ([_vp, _vp, _i32, _vp, _vp], _i32),
     "krr_precond_free": ([_vp], None),
+    "krr_solve_begin": ([_vp, _vp, _i32, _dbl, _i32, _pp, _vp], _i32),
+    "krr_solve_step": ([_pp, _i32, _i32p, _vp], _i32),
+    "krr_solve_end": ([_vp, _vp, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "krr_solve_free": ([_vp], None),
     "krr_pcg_solve": ([_vp, _vp, _i32, _dbl, _i32, _vp, ctypes.POINTER(SolveInfo), _vp], _i32),
     "krr_kernel_matvec_ws": ([_i32, _i64, _i64, _i32, _i32, _szp], _i32),
     "krr_kernel_matvec": ([_i32, _dbl, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _i32, _dbl, _vp,
@@ -275,4 +279,61 @@ def krill_export(P, what, shape, dtype):
     out = torch.empty(shape, dtype=dtype, device=P.device)
     check(lib().krr_krill_export(P.h, int(what), _ptr(out), out.numel() * out.element_size(),
                                  _stream(P.device)))
+    return out
+
+
+class Solve:
+    """An in-flight stepped PCG solve on a Precond (one per precond)."""
+
+    def __init__(self, P, Y, tol, max_iter=1000):
+        self.P = P
+        self.Y = P._block(Y)
+        self.m = self.Y.shape[1]
+        h = ctypes.c_void_p(0)
+        check(lib().krr_solve_begin(P.h, _ptr(self.Y), self.m, float(tol), int(max_iter),
+                                    ctypes.byref(h), _stream(P.device)))
+        self.h = h
+        self.state = 0
+
+    def end(self, history=0):
+        r, n = self.P.dims()
+        beta = torch.empty((n, self.m), dtype=torch.float64, device=self.P.device)
+        info = SolveInfo()
+        hist = None
+        if history:
+            hist = (ctypes.c_double * history)()
+            info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+            info.history_cap = history
+        h, self.h = self.h, None
+        rc = check(lib().krr_solve_end(h, _ptr(beta), ctypes.byref(info), _stream(self.P.device)))
+        d = dict(iters=info.iters, converged_cols=info.converged_cols,
+                 relres_recursive=info.relres_recursive, relres_true=info.relres_true,
+                 build_seconds=info.build_seconds, solve_seconds=info.solve_seconds,
+                 converged=(rc == 0))
+        if hist is not None:
+            d["history"] = [hist[i] for i in range(info.history_len)]
+        return beta, d
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().krr_solve_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def solve_step(solves, device=None):
+    """One PCG step for every solve in the list; returns their states."""
+    n = len(solves)
+    if n == 0:
+        return []
+    arr = (ctypes.c_void_p * n)(*[s.h.value for s in solves])
+    st = (ctypes.c_int32 * n)()
+    dev = device or solves[0].P.device
+    check(lib().krr_solve_step(ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), n, st,
+                               _stream(dev)))
+    out = [int(st[i]) for i in range(n)]
+    for s_, v in zip(solves, out):
+        s_.state = v
     return out

@@ -42,6 +42,8 @@ static size_t matvec_bytes(krr_kernel_kind kind, krr_precision prec, int64_t nr,
          product_scratch_bytes(prec, nr, nc, m);
 }
 
+const char* last_error() { return g_err; }
+
 }  // namespace krr
 
 using namespace krr;

@@ -365,3 +365,72 @@ extern "C" int krr_krill_export(krr_precond h, int32_t what, void* dst, size_t b
       return KRR_OK;
   }
 }
+
+struct krr_solve_s {
+  Solve S;
+};
+
+extern "C" int krr_solve_begin(krr_precond h, const double* Y, int32_t m, double tol,
+                               int32_t max_iter, krr_solve* out, hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  Precond& P = h->P;
+  if (!out || m < 1 || m > P.m_max || !Y || !(tol > 0.0) || max_iter < 0) {
+    set_error("invalid arguments (m=%d, m_max=%d, tol=%g, max_iter=%d)", m, P.m_max, tol,
+              max_iter);
+    return KRR_EINVAL;
+  }
+  *out = nullptr;
+  krr_solve q = new (std::nothrow) krr_solve_s;
+  if (!q) {
+    set_error("out of host memory");
+    return KRR_EINVAL;
+  }
+  const int rc = solve_begin(q->S, P, Y, m, tol, max_iter, stream);
+  if (rc < 0) {
+    delete q;
+    return rc;
+  }
+  *out = q;
+  return KRR_OK;
+}
+
+extern "C" int krr_solve_step(krr_solve* solves, int32_t n, int32_t* state, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!solves || !state))) {
+    set_error("invalid arguments");
+    return KRR_EINVAL;
+  }
+  std::vector<Solve*> v;
+  v.reserve(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!solves[i]) {
+      set_error("NULL solve at %d", i);
+      return KRR_EINVAL;
+    }
+    v.push_back(&solves[i]->S);
+  }
+  const int rc = solve_step(v.data(), n, stream);
+  for (int32_t i = 0; i < n; ++i)
+    state[i] = v[i]->err < 0 ? v[i]->err : (v[i]->phase == kPhaseDone ? 1 : 0);
+  return rc;
+}
+
+extern "C" int krr_solve_end(krr_solve q, double* beta, krr_solve_info* info, hipStream_t stream) {
+  if (!q) {
+    set_error("NULL solve");
+    return KRR_EINVAL;
+  }
+  int rc = KRR_OK;
+  if (q->S.err >= 0 && q->S.phase != kPhaseDone) {
+    set_error("solve has not finished");
+    rc = KRR_EINVAL;
+  } else if (q->S.err >= 0 && !beta) {
+    set_error("NULL beta");
+    rc = KRR_EINVAL;
+  } else {
+    rc = solve_end(q->S, beta, info, stream);
+  }
+  delete q;
+  return rc;
+}
+
+extern "C" void krr_solve_free(krr_solve q) { delete q; }

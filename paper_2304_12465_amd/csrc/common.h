@@ -12,6 +12,7 @@
 namespace krr {
 
 void set_error(const char* fmt, ...);
+const char* last_error();
 
 // Returns KRR_EHIP (and records the message) when a HIP call failed.
 inline int hip_check(hipError_t e, const char* what) {

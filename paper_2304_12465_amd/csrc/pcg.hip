@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void update_p(double* __restrict__ p,
     p[off + i] = act ? z[off + i] + beta * p[off + i] : 0.0;
 }
 
-enum FinalOp { kFinPW = 0, kFinRR = 1, kFinRZ = 2, kFinInit = 3, kFinSum = 4 };
+enum FinalOp { kFinPW = 0, kFinRR = 1, kFinRZ = 2, kFinInit = 3, kFinSum = 4, kFinActivate = 5 };
 
 // One thread per column: sums the partial slots in a fixed order and applies
 // the scalar step of the recurrence.
@@ -106,7 +106,12 @@ __global__ void finalize(const double* __restrict__ part, int nblk, int m, int m
       break;
     case kFinRR:
       S[kRR * m_max + c] = s;
+      S[kActivePrev * m_max + c] = act ? 1.0 : 0.0;
       S[kActive * m_max + c] = (act && s > tol2 * S[kBB * m_max + c]) ? 1.0 : 0.0;
+      break;
+    case kFinActivate:  // restart from a true residual with ||r||^2 = s
+      S[kRR * m_max + c] = s;
+      S[kActive * m_max + c] = (S[kBB * m_max + c] > 0.0 && s > tol2 * S[kBB * m_max + c]) ? 1.0 : 0.0;
       break;
     case kFinRZ: {
       const bool a2 = act;
@@ -272,143 +277,263 @@ int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s
                  s);
 }
 
-int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
-            krr_solve_info* info, hipStream_t s) {
-  using clk = std::chrono::steady_clock;
-  const auto t0 = clk::now();
+namespace {
+
+int pull_async(Solve& S, hipStream_t s) {
+  PcgState& st = S.P->pcg;
+  return hip_check(hipMemcpyAsync(st.host, st.scal, sizeof(double) * kScalars * st.m_max,
+                                  hipMemcpyDeviceToHost, s),
+                   "scalars D2H");
+}
+
+void fail(Solve& S, int code) {
+  S.err = code;
+  S.phase = kPhaseDone;
+  S.errmsg = last_error();
+}
+
+// z = P^{-1} r; rz = r.z (fresh, no beta); p = z
+int restart_direction(Solve& S, hipStream_t s) {
+  Precond& P = *S.P;
   PcgState& st = P.pcg;
   const int64_t n = st.n;
-  const int mm = st.m_max;
-  const int64_t len = n * m;
-  const double tol2 = tol * tol;
-  VecBlock X{st.x, n}, R{st.r, n}, Z{st.z, n}, Pv{st.p, n}, W{st.w, n}, Bv{st.b, n};
+  VecBlock R{st.r, n}, Z{st.z, n};
+  KRR_TRY(apply_precond(P, R, S.m, Z, s));
+  KRR_TRY(dot_cols(st, st.r, st.z, S.m, kFinSum, 0, kRZ, s));
+  return hip_check(hipMemcpyAsync(st.p, st.z, sizeof(double) * n * S.m, hipMemcpyDeviceToDevice, s),
+                   "p = z");
+}
 
+}  // namespace
+
+int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter,
+                hipStream_t s) {
+  S = Solve();
+  S.P = &P;
+  S.m = m;
+  S.tol = tol;
+  S.max_iter = max_iter;
+  S.t0 = std::chrono::steady_clock::now();
+  S.iters.assign(m, 0);
+  S.active.assign(m, 0);
+  PcgState& st = P.pcg;
+  const int64_t n = st.n;
+  const int64_t len = n * m;
+  VecBlock Bv{st.b, n};
   KRR_TRY(system_rhs(P, Y, m, Bv, s));
   fill<<<(unsigned)ceil_div(len, 256), 256, 0, s>>>(st.x, 0.0, len);
   KRR_LAUNCH_CHECK("fill");
   KRR_TRY(hip_check(hipMemcpyAsync(st.r, st.b, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
                     "r = b"));
   KRR_TRY(dot_cols(st, st.b, st.b, m, kFinInit, 0, 0, s));
-  KRR_TRY(apply_precond(P, R, m, Z, s));
-  KRR_TRY(dot_cols(st, st.r, st.z, m, kFinSum, 0, kRZ, s));
-  KRR_TRY(hip_check(hipMemcpyAsync(st.p, st.z, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
-                    "p = z"));
-
-  std::vector<int32_t> iters(m, 0);
-  std::vector<char> active(m, 0);
-  auto pull = [&]() -> int {
-    KRR_TRY(hip_check(hipMemcpyAsync(st.host, st.scal, sizeof(double) * kScalars * mm,
-                                     hipMemcpyDeviceToHost, s),
-                      "scalars D2H"));
-    return hip_check(hipStreamSynchronize(s), "stream sync");
-  };
-  KRR_TRY(pull());
+  KRR_TRY(restart_direction(S, s));
+  KRR_TRY(pull_async(S, s));
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "stream sync"));
+  const int mm = st.m_max;
+  bool any = false;
   for (int c = 0; c < m; ++c) {
     if (!std::isfinite(st.host[kBB * mm + c]) || !std::isfinite(st.host[kRZ * mm + c])) {
       set_error("NaN/Inf in the right-hand side or its preconditioned residual, column %d", c);
       return KRR_ENAN;
     }
-    active[c] = st.host[kActive * mm + c] != 0.0;
+    S.active[c] = st.host[kActive * mm + c] != 0.0;
+    any = any || S.active[c];
   }
-  if (info && info->history) info->history_len = 0;
+  S.phase = (any && max_iter > 0) ? kPhaseIterate : kPhaseCheck;
+  return KRR_OK;
+}
 
-  const Red rd = red_for(n);
-  int it = 0;
-  int restarts = 0;
-  double worst_true = 0.0;
-  for (;;) {
-    while (it < max_iter && std::any_of(active.begin(), active.end(), [](char a) { return a; })) {
-      KRR_TRY(apply_operator(P, Pv, m, W, false, s));
-      KRR_TRY(dot_cols(st, st.p, st.w, m, kFinPW, 0, 0, s));
-      update_xr<<<dim3((unsigned)rd.nblk, (unsigned)m), kThreads, 0, s>>>(
-          st.x, st.r, st.p, st.w, st.scal, mm, n, rd.chunk, rd.nblk, st.part);
-      KRR_LAUNCH_CHECK("update_xr");
-      finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, m, mm, kFinRR, tol2, 0, st.scal);
-      KRR_LAUNCH_CHECK("finalize rr");
-      KRR_TRY(pull());
-      ++it;
-      double worst = 0.0;
-      for (int c = 0; c < m; ++c) {
-        if (active[c]) iters[c] = it;
-        const double rr = st.host[kRR * mm + c], bb = st.host[kBB * mm + c];
-        if (!std::isfinite(rr)) {
-          set_error("NaN/Inf in the residual of column %d at iteration %d", c, it);
-          return KRR_ENAN;
-        }
-        if (bb > 0) worst = std::max(worst, std::sqrt(rr / bb));
-        active[c] = st.host[kActive * mm + c] != 0.0;
-      }
-      if (info && info->history && info->history_len < info->history_cap)
-        info->history[info->history_len++] = worst;
-      if (!std::any_of(active.begin(), active.end(), [](char a) { return a; })) break;
-      KRR_TRY(apply_precond(P, R, m, Z, s));
-      KRR_TRY(dot_cols(st, st.r, st.z, m, kFinRZ, 0, 0, s));
-      update_p<<<dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096), (unsigned)m), kThreads,
-                 0, s>>>(st.p, st.z, st.scal, mm, n);
-      KRR_LAUNCH_CHECK("update_p");
+int solve_step(Solve* const* solves, int n, hipStream_t s) {
+  // 1. products: direction products of iterating solves (their precision)
+  //    and FP64 true-residual products of checking solves, one group.
+  std::vector<ProductReq> reqs;
+  std::vector<int> owner;
+  for (int q = 0; q < n; ++q) {
+    Solve& S = *solves[q];
+    if (S.phase == kPhaseDone) continue;
+    Precond& P = *S.P;
+    PcgState& st = P.pcg;
+    const bool check = S.phase == kPhaseCheck;
+    VecBlock src{check ? st.x : st.p, st.n}, dst{st.w, st.n};
+    if (P.type == kRPChol) {
+      ProductReq r;
+      r.kind = P.kind;
+      r.sigma = P.sigma;
+      r.prec = check ? KRR_FP64 : P.prec;
+      r.rows = check ? &P.pts64 : &P.pts;
+      r.cols = r.rows;
+      r.V = src.view();
+      r.m = S.m;
+      r.shift = P.mu;
+      r.Vs = src.view();
+      r.W = dst.out();
+      r.scratch = &P.scratch;
+      reqs.push_back(r);
+      owner.push_back(q);
+    } else {
+      const int rc = apply_operator(P, src, S.m, dst, check, s);
+      if (rc < 0) fail(S, rc);
     }
-    // True residual b - M x with an FP64 product.
-    KRR_TRY(apply_operator(P, X, m, W, true, s));
-    axpby<<<(unsigned)ceil_div(len, 256), 256, 0, s>>>(st.w, st.b, 1.0, -1.0, len);  // w = b - w
-    KRR_LAUNCH_CHECK("axpby");
-    KRR_TRY(dot_cols(st, st.w, st.w, m, kFinSum, 0, kTrue, s));
-    KRR_TRY(pull());
-    worst_true = 0.0;
-    bool replace = false;
-    for (int c = 0; c < m; ++c) {
-      const double bb = st.host[kBB * mm + c];
-      if (bb <= 0) continue;
-      const double rt = std::sqrt(st.host[kTrue * mm + c] / bb);
-      worst_true = std::max(worst_true, rt);
-      if (!std::isfinite(rt)) {
-        set_error("NaN/Inf in the true residual of column %d", c);
-        return KRR_ENAN;
-      }
-      // FP64 tiles: replace when the recurrence drifted (> 10 tol).
-      // FP32 / MIXED tiles: iterative refinement with the FP64 residual until
-      // it meets tol (the lower-precision operator limits the recurrence).
-      if (rt > (P.prec == KRR_FP64 ? 10.0 * tol : tol)) replace = true;
-    }
-    const int max_restarts = P.prec == KRR_FP64 ? 1 : kMaxRefine;
-    if (!replace || restarts >= max_restarts || it >= max_iter) break;
-    ++restarts;
-    KRR_TRY(hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
-                      "r = true residual"));
-    KRR_TRY(dot_cols(st, st.r, st.r, m, kFinSum, 0, kRR, s));
-    KRR_TRY(apply_precond(P, R, m, Z, s));
-    KRR_TRY(dot_cols(st, st.r, st.z, m, kFinSum, 0, kRZ, s));
-    KRR_TRY(hip_check(hipMemcpyAsync(st.p, st.z, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
-                      "p = z"));
-    KRR_TRY(pull());
-    for (int c = 0; c < m; ++c) {
-      const double bb = st.host[kBB * mm + c];
-      active[c] = bb > 0 && st.host[kRR * mm + c] > tol2 * bb;
-      st.host[kActive * mm + c] = active[c] ? 1.0 : 0.0;
-    }
-    KRR_TRY(hip_check(hipMemcpyAsync(st.scal + kActive * mm, st.host + kActive * mm,
-                                     sizeof(double) * mm, hipMemcpyHostToDevice, s),
-                      "active H2D"));
   }
-  KRR_TRY(to_rowmajor(st.x, n, m, beta, s));
+  if (!reqs.empty()) {
+    const int rc = product_group(reqs.data(), (int)reqs.size(), s);
+    if (rc < 0) {
+      for (int q : owner) fail(*solves[q], rc);
+    }
+  }
+  // 2. post-product kernels and scalar read-back
+  for (int q = 0; q < n; ++q) {
+    Solve& S = *solves[q];
+    if (S.phase == kPhaseDone) continue;
+    PcgState& st = S.P->pcg;
+    const int64_t nn = st.n;
+    const int mm = st.m_max;
+    int rc = KRR_OK;
+    if (S.phase == kPhaseIterate) {
+      rc = dot_cols(st, st.p, st.w, S.m, kFinPW, 0, 0, s);
+      if (rc == KRR_OK) {
+        const Red rd = red_for(nn);
+        update_xr<<<dim3((unsigned)rd.nblk, (unsigned)S.m), kThreads, 0, s>>>(
+            st.x, st.r, st.p, st.w, st.scal, mm, nn, rd.chunk, rd.nblk, st.part);
+        rc = hip_check(hipGetLastError(), "update_xr");
+        if (rc == KRR_OK) {
+          finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, S.m, mm, kFinRR, S.tol * S.tol, 0, st.scal);
+          rc = hip_check(hipGetLastError(), "finalize rr");
+        }
+      }
+    } else {
+      const int64_t len = nn * S.m;
+      axpby<<<(unsigned)ceil_div(len, 256), 256, 0, s>>>(st.w, st.b, 1.0, -1.0, len);
+      rc = hip_check(hipGetLastError(), "axpby");
+      if (rc == KRR_OK) rc = dot_cols(st, st.w, st.w, S.m, kFinSum, 0, kTrue, s);
+    }
+    if (rc == KRR_OK) rc = pull_async(S, s);
+    if (rc < 0) fail(S, rc);
+  }
   KRR_TRY(hip_check(hipStreamSynchronize(s), "stream sync"));
+  // 3. host decisions, then the next direction
+  for (int q = 0; q < n; ++q) {
+    Solve& S = *solves[q];
+    if (S.phase == kPhaseDone) continue;
+    Precond& P = *S.P;
+    PcgState& st = P.pcg;
+    const int mm = st.m_max;
+    const double* h = st.host;
+    if (S.phase == kPhaseIterate) {
+      ++S.it;
+      double worst = 0.0;
+      bool any = false, bad = false;
+      for (int c = 0; c < S.m; ++c) {
+        if (h[kActivePrev * mm + c] != 0.0) S.iters[c] = S.it;
+        const double rr = h[kRR * mm + c], bb = h[kBB * mm + c];
+        if (!std::isfinite(rr)) bad = true;
+        if (bb > 0) worst = std::max(worst, std::sqrt(rr / bb));
+        S.active[c] = h[kActive * mm + c] != 0.0;
+        any = any || S.active[c];
+      }
+      if (bad) {
+        set_error("NaN/Inf in a residual at iteration %d", S.it);
+        fail(S, KRR_ENAN);
+        continue;
+      }
+      S.history.push_back(worst);
+      if (!any || S.it >= S.max_iter) {
+        S.phase = kPhaseCheck;
+        continue;
+      }
+      VecBlock R{st.r, st.n}, Z{st.z, st.n};
+      int rc = apply_precond(P, R, S.m, Z, s);
+      if (rc == KRR_OK) rc = dot_cols(st, st.r, st.z, S.m, kFinRZ, 0, 0, s);
+      if (rc == KRR_OK) {
+        update_p<<<dim3((unsigned)std::min<int64_t>(ceil_div(st.n, 256), 4096), (unsigned)S.m),
+                   kThreads, 0, s>>>(st.p, st.z, st.scal, mm, st.n);
+        rc = hip_check(hipGetLastError(), "update_p");
+      }
+      if (rc < 0) fail(S, rc);
+    } else {  // check
+      S.worst_true = 0.0;
+      bool replace = false, bad = false;
+      for (int c = 0; c < S.m; ++c) {
+        const double bb = h[kBB * mm + c];
+        if (bb <= 0) continue;
+        const double rt = std::sqrt(h[kTrue * mm + c] / bb);
+        if (!std::isfinite(rt)) bad = true;
+        S.worst_true = std::max(S.worst_true, rt);
+        // FP64 tiles: replace when the recurrence drifted (> 10 tol).
+        // FP32 / MIXED tiles: iterative refinement with the FP64 residual
+        // until it meets tol (the lower-precision operator limits the
+        // recurrence).
+        if (rt > (P.prec == KRR_FP64 ? 10.0 * S.tol : S.tol)) replace = true;
+      }
+      if (bad) {
+        set_error("NaN/Inf in the true residual");
+        fail(S, KRR_ENAN);
+        continue;
+      }
+      const int max_restarts = P.prec == KRR_FP64 ? 1 : kMaxRefine;
+      if (!replace || S.restarts >= max_restarts || S.it >= S.max_iter) {
+        S.phase = kPhaseDone;
+        continue;
+      }
+      ++S.restarts;
+      const int64_t len = st.n * S.m;
+      int rc = hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                         "r = true residual");
+      if (rc == KRR_OK) rc = dot_cols(st, st.r, st.r, S.m, kFinActivate, S.tol * S.tol, 0, s);
+      if (rc == KRR_OK) rc = restart_direction(S, s);
+      if (rc < 0) {
+        fail(S, rc);
+        continue;
+      }
+      S.phase = kPhaseIterate;
+    }
+  }
+  return KRR_OK;
+}
+
+int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
+  Precond& P = *S.P;
+  PcgState& st = P.pcg;
+  if (S.err < 0) {
+    set_error("%s", S.errmsg.c_str());
+    return S.err;
+  }
+  KRR_TRY(to_rowmajor(st.x, st.n, S.m, beta, s));
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "stream sync"));
+  const int mm = st.m_max;
   double worst_rec = 0.0;
   int conv = 0;
-  for (int c = 0; c < m; ++c) {
+  for (int c = 0; c < S.m; ++c) {
     const double bb = st.host[kBB * mm + c];
     const double rr = st.host[kRR * mm + c];
     const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     worst_rec = std::max(worst_rec, rel);
-    if (rel <= tol) ++conv;
+    if (rel <= S.tol) ++conv;
   }
   if (info) {
-    info->iters = *std::max_element(iters.begin(), iters.end());
+    info->iters = S.m > 0 ? *std::max_element(S.iters.begin(), S.iters.end()) : 0;
     info->converged_cols = conv;
     info->relres_recursive = worst_rec;
-    info->relres_true = worst_true;
+    info->relres_true = S.worst_true;
     info->build_seconds = P.build_seconds;
-    info->solve_seconds = std::chrono::duration<double>(clk::now() - t0).count();
+    info->solve_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
+    if (info->history) {
+      info->history_len = 0;
+      for (size_t i = 0; i < S.history.size() && info->history_len < info->history_cap; ++i)
+        info->history[info->history_len++] = S.history[i];
+    }
   }
-  return conv == m ? KRR_OK : KRR_NOT_CONVERGED;
+  return conv == S.m ? KRR_OK : KRR_NOT_CONVERGED;
+}
+
+int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
+            krr_solve_info* info, hipStream_t s) {
+  Solve S;
+  KRR_TRY(solve_begin(S, P, Y, m, tol, max_iter, s));
+  Solve* one = &S;
+  while (S.phase != kPhaseDone) KRR_TRY(solve_step(&one, 1, s));
+  return solve_end(S, beta, info, s);
 }
 
 }  // namespace krr

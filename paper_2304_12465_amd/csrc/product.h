@@ -1,5 +1,6 @@
 // Internal interface of the matrix-free kernel product engine.
 #pragma once
+#include <vector>
 #include "common.h"
 
 namespace krr {
@@ -57,14 +58,51 @@ int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointS
             const PointSet& cols, VecView V, int32_t m, double shift, VecView Vs, VecOut W,
             Arena& scratch, hipStream_t s);
 
+// One product of a group: W = K(rows, cols) V + shift Vs, scratch from the
+// request's own arena.
+struct ProductReq {
+  krr_kernel_kind kind = KRR_GAUSSIAN;
+  double sigma = 1.0;
+  krr_precision prec = KRR_FP64;
+  const PointSet* rows = nullptr;
+  const PointSet* cols = nullptr;
+  VecView V;
+  int32_t m = 1;
+  double shift = 0.0;
+  VecView Vs;
+  VecOut W;
+  Arena* scratch = nullptr;
+};
+// Several products at once: tiles of products that use the same kernel
+// instantiation share launches.  Each product's tile decomposition depends
+// only on its own shapes, so results are bitwise identical to product().
+int product_group(const ProductReq* reqs, int n, hipStream_t s);
+
+// A prepared bf16-split MFMA job (V packed, partial slots carved).
+struct MfmaJob {
+  const uint16_t* xhi;
+  const uint16_t* xlo;
+  const float* xn;
+  const uint16_t* yhi;
+  const uint16_t* ylo;
+  const float* yn;
+  const uint16_t* vh;
+  const uint16_t* vl;
+  double* part;
+  int64_t nr, nc, per, item0;
+  float s;
+  int nsplit, M, kp;
+};
+int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0,
+                 int mc, Arena& scratch, MfmaJob* out, hipStream_t s);
+int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s);
+
 // bf16-split MFMA path for Gaussian tiles (product_mfma.hip).
 int carve_mixed(int64_t n, int32_t d, Arena& arena, PointSet* out);
 int compute_centre(const double* X, int64_t n, int32_t d, double* centre, double* part,
                    hipStream_t s);
 int fill_mixed(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
 size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc);
-int product_mfma(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int32_t m,
-                 double shift, VecView Vs, VecOut W, Arena& scratch, hipStream_t s);
 
 // Tile timer hooks: start returns a token (or null when timing is off).
 void* tile_timer_start(hipStream_t s);

@@ -47,12 +47,21 @@ __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
 __device__ __forceinline__ int slot_col(int g, int v) { return v < 4 ? 4 * g + v : 16 + 4 * g + (v - 4); }
 
 template <int KP>
-__global__ __launch_bounds__(256) void tile_mfma_gauss(
-    const uint16_t* __restrict__ Xhi, const uint16_t* __restrict__ Xlo,
-    const float* __restrict__ Xn, int64_t nr, const uint16_t* __restrict__ Yhi,
-    const uint16_t* __restrict__ Ylo, const float* __restrict__ Yn,
-    const uint16_t* __restrict__ Vhi, const uint16_t* __restrict__ Vlo, int64_t nc, float s,
-    int nsplit, int64_t cols_per_split, int M, double* __restrict__ part) {
+__device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int split) {
+  const uint16_t* __restrict__ Xhi = J.xhi;
+  const uint16_t* __restrict__ Xlo = J.xlo;
+  const float* __restrict__ Xn = J.xn;
+  const int64_t nr = J.nr;
+  const uint16_t* __restrict__ Yhi = J.yhi;
+  const uint16_t* __restrict__ Ylo = J.ylo;
+  const float* __restrict__ Yn = J.yn;
+  const uint16_t* __restrict__ Vhi = J.vh;
+  const uint16_t* __restrict__ Vlo = J.vl;
+  const int64_t nc = J.nc;
+  const float s = J.s;
+  const int64_t cols_per_split = J.per;
+  const int M = J.M;
+  double* __restrict__ part = J.part;
   constexpr int KS = KP / 32;      // MFMA K steps of the distance contraction
   constexpr int YP = KP + 8;       // LDS row pitch (bf16) of the column points
   __shared__ __attribute__((aligned(16))) __bf16 sYh[kCols][YP];
@@ -64,9 +73,6 @@ __global__ __launch_bounds__(256) void tile_mfma_gauss(
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t bid = blockIdx.x;
-  const int split = (int)(bid % nsplit);
-  const int64_t rg = bid / nsplit;
   const int64_t row0 = (rg * 4 + wave) * (16 * kRT);
 
   // row operands (B of the distance MFMA): X[i0 + li][8g .. 8g+8] per K step
@@ -203,6 +209,24 @@ __global__ __launch_bounds__(256) void tile_mfma_gauss(
   }
 }
 
+constexpr int kMaxMJobs = 8;
+struct MJobTable {
+  MfmaJob job[kMaxMJobs];
+  int njobs;
+  int64_t total;
+};
+
+template <int KP>
+__global__ __launch_bounds__(256) void tile_mfma_gauss(const MJobTable tab) {
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const MfmaJob& J = tab.job[jn];
+    const int64_t local = item - J.item0;
+    mfma_item<KP>(J, local / J.nsplit, (int)(local % J.nsplit));
+  }
+}
+
 }  // namespace
 
 }  // namespace krr
@@ -277,18 +301,6 @@ __global__ void pack_vsplit(VecView V, int64_t n, int c0, int mc, uint16_t* __re
   const __bf16 l = (__bf16)(float)(vd - (double)(float)h);
   hi[t] = __builtin_bit_cast(uint16_t, h);
   lo[t] = __builtin_bit_cast(uint16_t, l);
-}
-
-__global__ void reduce_splits16(const double* __restrict__ part, int nsplit, int64_t nr, int mc,
-                                int c0, double shift, VecView Vs, VecOut W) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nr * mc) return;
-  const int64_t i = t / mc;
-  const int c = (int)(t % mc);
-  double s = 0.0;
-  for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * nr + i) * 16 + c];
-  if (shift != 0.0) s += shift * Vs.p[i * Vs.rs + (int64_t)(c0 + c) * Vs.cs];
-  W.p[i * W.rs + (int64_t)(c0 + c) * W.cs] = s;
 }
 
 struct MSplit {
@@ -367,50 +379,71 @@ size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc) {
   return a.used;
 }
 
-int product_mfma(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int32_t m,
-                 double shift, VecView Vs, VecOut W, Arena& scratch, hipStream_t s) {
+int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0,
+                 int mc, Arena& scratch, MfmaJob* out, hipStream_t s) {
   const int64_t nr = rows.n, nc = cols.n;
   if (rows.kpad != cols.kpad || !rows.xhi || !cols.xhi) {
     set_error("MIXED product: point layouts missing or inconsistent");
     return KRR_EINVAL;
   }
-  const int KP = rows.kpad;
-  const float sc = (float)(1.4426950408889634 / (2.0 * sigma * sigma));
-  const size_t mark = scratch.used;
-  for (int c0 = 0; c0 < m; c0 += 16) {
-    const int mc = std::min(16, m - c0);
-    scratch.used = mark;
-    MSplit sp = mfma_split(nr, nc);
-    uint16_t* vh = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
-    uint16_t* vl = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
-    double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
-    if (!scratch.ok()) {
-      set_error("MIXED product scratch too small");
-      return KRR_EWORKSPACE;
-    }
-    if (nc > 0) {
-      pack_vsplit<<<(unsigned)ceil_div(nc * 16, 256), 256, 0, s>>>(V, nc, c0, mc, vh, vl);
-      KRR_LAUNCH_CHECK("pack_vsplit");
-      const int64_t rg = ceil_div(nr, (int64_t)4 * 16 * kRT);
-      const unsigned grid = (unsigned)(rg * sp.nsplit);
+  MSplit sp = mfma_split(nr, nc);
+  uint16_t* vh = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  uint16_t* vl = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
+  if (!scratch.ok()) {
+    set_error("MIXED product scratch too small");
+    return KRR_EWORKSPACE;
+  }
+  if (nc > 0) {
+    pack_vsplit<<<(unsigned)ceil_div(nc * 16, 256), 256, 0, s>>>(V, nc, c0, mc, vh, vl);
+    KRR_LAUNCH_CHECK("pack_vsplit");
+  }
+  MfmaJob& j = *out;
+  j.xhi = rows.xhi;
+  j.xlo = rows.xlo;
+  j.xn = rows.nrm;
+  j.yhi = cols.xhi;
+  j.ylo = cols.xlo;
+  j.yn = cols.nrm;
+  j.vh = vh;
+  j.vl = vl;
+  j.part = part;
+  j.nr = nr;
+  j.nc = nc;
+  j.per = sp.per;
+  j.item0 = 0;
+  j.s = (float)(1.4426950408889634 / (2.0 * sigma * sigma));
+  j.nsplit = sp.nsplit;
+  j.M = mc;
+  j.kp = rows.kpad;
+  return KRR_OK;
+}
+
+int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s) {
+  for (int kp : {32, 64}) {
+    std::vector<MfmaJob> sel;
+    for (const MfmaJob& j : jobs)
+      if (j.kp == kp) sel.push_back(j);
+    for (size_t j0 = 0; j0 < sel.size(); j0 += kMaxMJobs) {
+      MJobTable tab{};
+      int64_t total = 0;
+      int nj = 0;
+      for (size_t j = j0; j < sel.size() && nj < kMaxMJobs; ++j, ++nj) {
+        tab.job[nj] = sel[j];
+        tab.job[nj].item0 = total;
+        total += ceil_div(sel[j].nr, (int64_t)4 * 16 * kRT) * sel[j].nsplit;
+      }
+      tab.njobs = nj;
+      tab.total = total;
+      if (total == 0) continue;
+      const unsigned grid = (unsigned)std::min<int64_t>(total, 8192);
       void* tok = tile_timer_start(s);
-      if (KP == 32)
-        tile_mfma_gauss<32><<<grid, 256, 0, s>>>(rows.xhi, rows.xlo, rows.nrm, nr, cols.xhi,
-                                                 cols.xlo, cols.nrm, vh, vl, nc, sc, sp.nsplit,
-                                                 sp.per, mc, part);
-      else
-        tile_mfma_gauss<64><<<grid, 256, 0, s>>>(rows.xhi, rows.xlo, rows.nrm, nr, cols.xhi,
-                                                 cols.xlo, cols.nrm, vh, vl, nc, sc, sp.nsplit,
-                                                 sp.per, mc, part);
+      if (kp == 32) tile_mfma_gauss<32><<<grid, 256, 0, s>>>(tab);
+      else tile_mfma_gauss<64><<<grid, 256, 0, s>>>(tab);
       KRR_LAUNCH_CHECK("tile_mfma_gauss");
       tile_timer_stop(tok, s);
     }
-    const int ns = nc > 0 ? sp.nsplit : 0;
-    reduce_splits16<<<(unsigned)ceil_div(nr * mc, 256), 256, 0, s>>>(part, ns, nr, mc, c0, shift,
-                                                                     Vs, W);
-    KRR_LAUNCH_CHECK("reduce_splits16");
   }
-  scratch.used = mark;
   return KRR_OK;
 }
 

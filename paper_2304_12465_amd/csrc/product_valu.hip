@@ -31,17 +31,36 @@ __device__ __forceinline__ float abs_t(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ double abs_t(double a) { return __builtin_fabs(a); }
 constexpr int kFold = 256;          // FP32 columns per FP64 fold
 
+// One work item: row group rg (kWaves waves x 64 lanes x R rows) against
+// column split `split` of one product.
+template <typename T>
+struct TileJob {
+  const T* Xr;
+  const T* Xc;
+  const T* Vc;
+  double* part;
+  int64_t nr, nc, per;
+  int64_t item0;  // first work item of this job in the launch
+  T scale;
+  int nsplit;
+};
+
+constexpr int kMaxJobs = 8;  // products per launch (kernel-argument table)
+
+template <typename T>
+struct JobTable {
+  TileJob<T> job[kMaxJobs];
+  int njobs;
+  int64_t total;
+};
+
 template <int KIND, typename T, int D, int M, int R>
-__global__ __launch_bounds__(256) void tile_valu(const T* __restrict__ Xr, int64_t nr,
-                                                 const T* __restrict__ Xc,
-                                                 const T* __restrict__ Vc, int64_t nc,
-                                                 T scale, int nsplit, int64_t cols_per_split,
-                                                 double* __restrict__ part) {
+__device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
+                                          const T* __restrict__ Xc, const T* __restrict__ Vc,
+                                          int64_t nc, T scale, int split, int64_t cols_per_split,
+                                          int64_t rg, double* __restrict__ part, int nsplit) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t bid = blockIdx.x;
-  const int split = (int)(bid % nsplit);
-  const int64_t rg = bid / nsplit;
   const int64_t row0 = (rg * kWaves + wave) * 64 * R;
   if (row0 >= nr) return;  // whole wave idle (wave-uniform)
 
@@ -118,6 +137,20 @@ __global__ __launch_bounds__(256) void tile_valu(const T* __restrict__ Xr, int64
   }
 }
 
+template <int KIND, typename T, int D, int M, int R>
+__global__ __launch_bounds__(256) void tile_valu(const JobTable<T> tab) {
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const TileJob<T>& J = tab.job[jn];
+    const int64_t local = item - J.item0;
+    const int split = (int)(local % J.nsplit);
+    const int64_t rg = local / J.nsplit;
+    tile_item<KIND, T, D, M, R>(J.Xr, J.nr, J.Xc, J.Vc, J.nc, J.scale, split, J.per, rg, J.part,
+                                J.nsplit);
+  }
+}
+
 // W[i, c0+c] = sum_s part[s, i, c] + shift * Vs[i, c0+c], fixed order over s.
 __global__ __launch_bounds__(256) void reduce_splits(const double* __restrict__ part, int nsplit,
                                                      int64_t nr, int M, int mc, int c0,
@@ -154,11 +187,6 @@ __global__ void pack_vec(VecView V, int64_t n, int c0, int mc, int M, T* __restr
   out[t] = (c < mc) ? (T)V.p[j * V.rs + (int64_t)(c0 + c) * V.cs] : T(0);
 }
 
-using TileFn32 = void (*)(const float*, int64_t, const float*, const float*, int64_t, float, int,
-                          int64_t, double*);
-using TileFn64 = void (*)(const double*, int64_t, const double*, const double*, int64_t, double,
-                          int, int64_t, double*);
-
 constexpr int kDims[] = {4, 8, 16, 20, 24, 32, 48, 64};
 constexpr int kMs[] = {1, 2, 4, 8, 16};
 
@@ -169,6 +197,8 @@ template <int KIND, typename T, int D, int M>
 void* tile_ptr() {
   return reinterpret_cast<void*>(&tile_valu<KIND, T, D, M, rows_per_lane<D>()>);
 }
+template <typename T>
+using TileFn = void (*)(const JobTable<T>);
 
 template <int KIND, typename T, int D>
 void* pick_m(int M) {
@@ -371,73 +401,176 @@ size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t
   return a.used;
 }
 
+namespace {
+
+struct Family {
+  bool f64;
+  void* fn;
+  std::vector<TileJob<float>> j32;
+  std::vector<TileJob<double>> j64;
+  int R;
+};
+
+template <typename T>
+int launch_jobs(void* fn, const std::vector<TileJob<T>>& jobs, int R, hipStream_t s) {
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+    JobTable<T> tab{};
+    int64_t total = 0;
+    int nj = 0;
+    for (size_t j = j0; j < jobs.size() && nj < kMaxJobs; ++j, ++nj) {
+      tab.job[nj] = jobs[j];
+      tab.job[nj].item0 = total;
+      total += ceil_div(jobs[j].nr, (int64_t)kWaves * 64 * R) * jobs[j].nsplit;
+    }
+    tab.njobs = nj;
+    tab.total = total;
+    if (total == 0) continue;
+    const unsigned grid = (unsigned)std::min<int64_t>(total, 8192);
+    void* tok = tile_timer_start(s);
+    reinterpret_cast<TileFn<T>>(fn)<<<grid, 256, 0, s>>>(tab);
+    KRR_LAUNCH_CHECK("tile_valu");
+    tile_timer_stop(tok, s);
+  }
+  return KRR_OK;
+}
+
+}  // namespace
+
+int product_group(const ProductReq* reqs, int n, hipStream_t s) {
+  int mmax = 0;
+  for (int q = 0; q < n; ++q) {
+    const ProductReq& r = reqs[q];
+    if (r.rows->dpad != r.cols->dpad) {
+      set_error("row and column point sets differ in dimension");
+      return KRR_EINVAL;
+    }
+    if (r.rows->n > 0) mmax = std::max(mmax, r.m);
+  }
+  std::vector<size_t> marks(n);
+  for (int q = 0; q < n; ++q) marks[q] = reqs[q].scratch->used;
+  const double log2e = 1.4426950408889634;
+  for (int c0 = 0; c0 < mmax; c0 += 16) {
+    std::vector<Family> fams;
+    auto family = [&](bool f64, void* fn, int R) -> Family& {
+      for (auto& f : fams)
+        if (f.fn == fn) return f;
+      fams.push_back(Family{f64, fn, {}, {}, R});
+      return fams.back();
+    };
+    std::vector<MfmaJob> mjobs;
+    std::vector<int> mreq;
+    struct Pending {
+      int q;
+      double* part;
+      int nsplit;
+      int M;
+      int mc;
+      bool mfma;
+    };
+    std::vector<Pending> pend;
+    for (int q = 0; q < n; ++q) {
+      const ProductReq& r = reqs[q];
+      const int64_t nr = r.rows->n, nc = r.cols->n;
+      if (nr == 0 || r.m <= c0) continue;
+      Arena& sc = *r.scratch;
+      sc.used = marks[q];
+      const int mc = std::min(16, r.m - c0);
+      if (r.prec == KRR_MIXED && r.kind == KRR_GAUSSIAN) {
+        MfmaJob mj;
+        KRR_TRY(mfma_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &mj, s));
+        pend.push_back(Pending{q, mj.part, nc > 0 ? mj.nsplit : 0, 16, mc, true});
+        if (nc > 0) {
+          mjobs.push_back(mj);
+          mreq.push_back(q);
+        }
+        continue;
+      }
+      const int D = r.rows->dpad;
+      const bool f64 = r.prec == KRR_FP64;
+      const int R = rows_for_dpad(D);
+      const int M = mpad(mc);
+      Split sp = choose_split(nr, nc, R);
+      void* vp = f64 ? (void*)sc.take<double>((size_t)std::max<int64_t>(nc, 1) * M)
+                     : (void*)sc.take<float>((size_t)std::max<int64_t>(nc, 1) * M);
+      double* part = sc.take<double>((size_t)sp.nsplit * nr * M);
+      if (!sc.ok()) {
+        set_error("product scratch too small");
+        return KRR_EWORKSPACE;
+      }
+      pend.push_back(Pending{q, part, nc > 0 ? sp.nsplit : 0, M, mc, false});
+      if (nc == 0) continue;
+      const int64_t tot = nc * M;
+      if (f64) {
+        pack_vec<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(r.V, nc, c0, mc, M, (double*)vp);
+        KRR_LAUNCH_CHECK("pack_vec");
+        const double sc64 = r.kind == KRR_LAPLACE ? -1.0 / r.sigma : -1.0 / (2.0 * r.sigma * r.sigma);
+        void* fn = r.kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, double>(D, M)
+                                         : pick_d<KRR_GAUSSIAN, double>(D, M);
+        TileJob<double> j{};
+        j.Xr = r.rows->x64;
+        j.Xc = r.cols->x64;
+        j.Vc = (const double*)vp;
+        j.part = part;
+        j.nr = nr;
+        j.nc = nc;
+        j.per = sp.per;
+        j.scale = sc64;
+        j.nsplit = sp.nsplit;
+        family(true, fn, R).j64.push_back(j);
+      } else {
+        pack_vec<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(r.V, nc, c0, mc, M, (float*)vp);
+        KRR_LAUNCH_CHECK("pack_vec");
+        const float sc32 = (float)(r.kind == KRR_LAPLACE ? -log2e / r.sigma
+                                                         : -log2e / (2.0 * r.sigma * r.sigma));
+        void* fn = r.kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, float>(D, M)
+                                         : pick_d<KRR_GAUSSIAN, float>(D, M);
+        TileJob<float> j{};
+        j.Xr = r.rows->x32;
+        j.Xc = r.cols->x32;
+        j.Vc = (const float*)vp;
+        j.part = part;
+        j.nr = nr;
+        j.nc = nc;
+        j.per = sp.per;
+        j.scale = sc32;
+        j.nsplit = sp.nsplit;
+        family(false, fn, R).j32.push_back(j);
+      }
+    }
+    for (auto& f : fams) {
+      if (f.f64) KRR_TRY(launch_jobs<double>(f.fn, f.j64, f.R, s));
+      else KRR_TRY(launch_jobs<float>(f.fn, f.j32, f.R, s));
+    }
+    if (!mjobs.empty()) KRR_TRY(mfma_launch(mjobs, s));
+    for (const Pending& pd : pend) {
+      const ProductReq& r = reqs[pd.q];
+      const int64_t nr = r.rows->n;
+      const int64_t tot = nr * pd.mc;
+      reduce_splits<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(pd.part, pd.nsplit, nr, pd.M,
+                                                                 pd.mc, c0, r.shift, r.Vs, r.W);
+      KRR_LAUNCH_CHECK("reduce_splits");
+    }
+  }
+  for (int q = 0; q < n; ++q) reqs[q].scratch->used = marks[q];
+  return KRR_OK;
+}
+
 int product(krr_kernel_kind kind, double sigma, krr_precision prec, const PointSet& rows,
             const PointSet& cols, VecView V, int32_t m, double shift, VecView Vs, VecOut W,
             Arena& scratch, hipStream_t s) {
-  const int64_t nr = rows.n, nc = cols.n;
-  if (nr == 0 || m == 0) return KRR_OK;
-  if (rows.dpad != cols.dpad) {
-    set_error("row and column point sets differ in dimension");
-    return KRR_EINVAL;
-  }
-  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN)
-    return product_mfma(sigma, rows, cols, V, m, shift, Vs, W, scratch, s);
-  const int D = rows.dpad;
-  const bool f64 = prec == KRR_FP64;
-  const int R = rows_for_dpad(D);
-  const size_t mark = scratch.used;
-  for (int c0 = 0; c0 < m; c0 += 16) {
-    const int mc = std::min(16, m - c0);
-    const int M = mpad(mc);
-    scratch.used = mark;
-    Split sp = choose_split(nr, nc, R);
-    void* vp = f64 ? (void*)scratch.take<double>((size_t)std::max<int64_t>(nc, 1) * M)
-                   : (void*)scratch.take<float>((size_t)std::max<int64_t>(nc, 1) * M);
-    double* part = scratch.take<double>((size_t)sp.nsplit * nr * M);
-    if (!scratch.ok()) {
-      set_error("product scratch too small");
-      return KRR_EWORKSPACE;
-    }
-    if (nc > 0) {
-      const int64_t tot = nc * M;
-      if (f64)
-        pack_vec<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(V, nc, c0, mc, M,
-                                                                        (double*)vp);
-      else
-        pack_vec<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(V, nc, c0, mc, M,
-                                                                       (float*)vp);
-      KRR_LAUNCH_CHECK("pack_vec");
-      const int64_t rg = ceil_div(nr, (int64_t)kWaves * 64 * R);
-      const unsigned grid = (unsigned)(rg * sp.nsplit);
-      void* tok = tile_timer_start(s);
-      const double log2e = 1.4426950408889634;
-      if (f64) {
-        const double sc = kind == KRR_LAPLACE ? -1.0 / sigma : -1.0 / (2.0 * sigma * sigma);
-        void* fn = kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, double>(D, M)
-                                       : pick_d<KRR_GAUSSIAN, double>(D, M);
-        reinterpret_cast<TileFn64>(fn)<<<grid, 256, 0, s>>>(rows.x64, nr, cols.x64,
-                                                            (const double*)vp, nc, sc, sp.nsplit,
-                                                            sp.per, part);
-      } else {
-        const float sc = (float)(kind == KRR_LAPLACE ? -log2e / sigma
-                                                     : -log2e / (2.0 * sigma * sigma));
-        void* fn = kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, float>(D, M)
-                                       : pick_d<KRR_GAUSSIAN, float>(D, M);
-        reinterpret_cast<TileFn32>(fn)<<<grid, 256, 0, s>>>(rows.x32, nr, cols.x32,
-                                                           (const float*)vp, nc, sc, sp.nsplit,
-                                                           sp.per, part);
-      }
-      KRR_LAUNCH_CHECK("tile_valu");
-      tile_timer_stop(tok, s);
-    }
-    const int ns = nc > 0 ? sp.nsplit : 0;
-    const int64_t tot = nr * mc;
-    reduce_splits<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(part, ns, nr, M, mc, c0, shift,
-                                                               Vs, W);
-    KRR_LAUNCH_CHECK("reduce_splits");
-  }
-  scratch.used = mark;
-  return KRR_OK;
+  ProductReq r;
+  r.kind = kind;
+  r.sigma = sigma;
+  r.prec = prec;
+  r.rows = &rows;
+  r.cols = &cols;
+  r.V = V;
+  r.m = m;
+  r.shift = shift;
+  r.Vs = Vs;
+  r.W = W;
+  r.scratch = &scratch;
+  return product_group(&r, 1, s);
 }
 
 }  // namespace krr

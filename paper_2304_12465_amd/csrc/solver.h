@@ -1,5 +1,7 @@
 // Internal: preconditioner objects and the PCG driver.
 #pragma once
+#include <chrono>
+#include <string>
 #include <vector>
 #include "product.h"
 #include "la.h"
@@ -112,7 +114,7 @@ struct Precond {
 
 // Fixed-order reductions and vector updates (pcg.hip).
 constexpr int kScalars = 12;
-enum ScalarSlot { kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp };
+enum ScalarSlot { kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp, kActivePrev };
 
 size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_for_restricted, int32_t rank);
 void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_for_restricted,
@@ -128,6 +130,31 @@ int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s
 
 int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
             krr_solve_info* info, hipStream_t s);
+
+// PCG as a state machine, so that several solves advance together (one
+// host synchronisation per step, direction products grouped into shared
+// launches).
+enum SolvePhase { kPhaseIterate = 0, kPhaseCheck = 1, kPhaseDone = 2 };
+struct Solve {
+  Precond* P = nullptr;
+  int32_t m = 0;
+  double tol = 0.0;
+  int32_t max_iter = 0;
+  int it = 0;
+  int restarts = 0;
+  int phase = kPhaseIterate;
+  int err = 0;
+  std::string errmsg;
+  std::vector<int32_t> iters;
+  std::vector<char> active;
+  std::vector<double> history;
+  double worst_true = 0.0;
+  std::chrono::steady_clock::time_point t0;
+};
+int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter,
+                hipStream_t s);
+int solve_step(Solve* const* solves, int n, hipStream_t s);
+int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s);
 
 // Layout helpers used for both measuring and carving.
 int rpchol_layout(Arena& a, Precond& P);

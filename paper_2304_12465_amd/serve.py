@@ -1,0 +1,211 @@
+"""Continuously batched serving of KRR solves.
+
+Requests (points, targets, kernel, rank, right-hand-side count) arrive over
+time.  The server admits them in arrival order as long as their HBM
+footprint (the library's workspace size plus the request's own arrays) fits
+in the budget, keeps every admitted request's points, Nystrom factor and
+CG state resident on the device, and advances all admitted solves together:
+each tick is one native step (``krr_solve_step``) in which the direction
+products of all active requests share kernel launches.  A request leaves as
+soon as its solve finishes, freeing memory for the next ones.  Latency is
+completion time minus arrival time (queueing included).
+
+The scheduling policy lives here; every numerical step runs in the HIP
+library behind a backend object.  ``GpuBackend`` is the product backend;
+tests may plug in a fake backend with the same four methods.
+"""
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float = 0.0
+    finished: float = 0.0
+    status: str = "pending"   # done | failed | rejected
+    iters: int = 0
+    relres_true: float = float("nan")
+    error: str = ""
+    beta: object = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class GpuBackend:
+    """Runs requests on the GPU through the C ABI (binding module)."""
+
+    def __init__(self, precision, tol=1e-6, max_iter=500, device="cuda:0", keep_beta=False):
+        import torch
+        from . import binding
+        self.b = binding
+        self.torch = torch
+        self.prec = precision
+        self.tol = tol
+        self.max_iter = max_iter
+        self.dev = torch.device(device)
+        self.keep_beta = keep_beta
+
+    def footprint(self, prob):
+        N, d = prob.X.shape
+        m = prob.Y.shape[1]
+        ws = self.b.rpchol_ws(prob.kind, self.prec, N, d, prob.rank, 0, m)
+        return ws + 8 * N * (d + 2 * m) + 4096
+
+    def start(self, prob):
+        t = lambda a: self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
+        X, Y = t(prob.X), t(prob.Y)
+        P = self.b.rpchol_build(prob.kind, prob.sigma, self.prec, X, prob.mu, prob.rank,
+                                seed=prob.algo_seed, m_max=Y.shape[1])
+        S = self.b.Solve(P, Y, self.tol, self.max_iter)
+        return {"P": P, "S": S, "Y": Y}
+
+    def step(self, handles):
+        return self.b.solve_step([h["S"] for h in handles], self.dev)
+
+    def finish(self, h):
+        beta, info = h["S"].end()
+        out = beta.cpu().numpy() if self.keep_beta else None
+        h.clear()
+        return out, info
+
+    def cancel(self, h):
+        h.clear()
+
+
+class Server:
+    def __init__(self, backend, hbm_budget, max_active=64, clock=time.perf_counter,
+                 sleep=time.sleep):
+        self.be = backend
+        self.budget = hbm_budget
+        self.max_active = max_active
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, stream, make_problem):
+        """Serves ``stream`` (objects with .rid and .arrival in seconds);
+        ``make_problem(req)`` gives its arrays.  Returns {rid: Result}."""
+        pending = deque(sorted(stream, key=lambda r: r.arrival))
+        results = {r.rid: Result(r.rid, r.arrival) for r in stream}
+        problems = {}
+        waiting = deque()
+        active = []  # (req, handle, bytes)
+        used = 0
+        t0 = self.clock()
+        while pending or waiting or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                req = pending.popleft()
+                problems[req.rid] = make_problem(req)
+                waiting.append(req)
+            # admission: FIFO by arrival while the footprint fits
+            while waiting and len(active) < self.max_active:
+                req = waiting[0]
+                prob = problems[req.rid]
+                need = self.be.footprint(prob)
+                if need > self.budget:
+                    waiting.popleft()
+                    r = results[req.rid]
+                    r.status, r.error = "rejected", f"footprint {need} exceeds budget {self.budget}"
+                    r.finished = self.clock() - t0
+                    continue
+                if used + need > self.budget:
+                    break
+                waiting.popleft()
+                r = results[req.rid]
+                r.admitted = self.clock() - t0
+                try:
+                    h = self.be.start(prob)
+                except Exception as e:  # a failed build isolates this request only
+                    r.status, r.error = "failed", str(e)
+                    r.finished = self.clock() - t0
+                    continue
+                active.append((req, h, need))
+                used += need
+            if not active:
+                if pending and not waiting:
+                    self.sleep(max(0.0, min(0.05, pending[0].arrival - (self.clock() - t0))))
+                continue
+            states = self.be.step([h for _, h, _ in active])
+            keep = []
+            for (req, h, need), st in zip(active, states):
+                if st == 0:
+                    keep.append((req, h, need))
+                    continue
+                r = results[req.rid]
+                if st < 0:
+                    r.status, r.error = "failed", f"solver error {st}"
+                    try:
+                        self.be.finish(h)
+                    except Exception as e:
+                        r.error += f" ({e})"
+                else:
+                    try:
+                        beta, info = self.be.finish(h)
+                        r.status = "done"
+                        r.iters = info["iters"]
+                        r.relres_true = info["relres_true"]
+                        r.beta = beta
+                    except Exception as e:
+                        r.status, r.error = "failed", str(e)
+                r.finished = self.clock() - t0
+                used -= need
+                problems.pop(req.rid, None)
+            active = keep
+        return results
+
+
+def serve_one_at_a_time(backend, stream, make_problem, clock=time.perf_counter,
+                        sleep=time.sleep):
+    """Baseline: the same arrival trace served one request at a time (FIFO)."""
+    results = {}
+    t0 = clock()
+    for req in sorted(stream, key=lambda r: r.arrival):
+        now = clock() - t0
+        if req.arrival > now:
+            sleep(req.arrival - now)
+        r = Result(req.rid, req.arrival)
+        r.admitted = clock() - t0
+        prob = make_problem(req)
+        try:
+            h = backend.start(prob)
+            while True:
+                st = backend.step([h])[0]
+                if st != 0:
+                    break
+            if st < 0:
+                r.status, r.error = "failed", f"solver error {st}"
+                backend.finish(h)
+            else:
+                beta, info = backend.finish(h)
+                r.status, r.iters, r.relres_true, r.beta = "done", info["iters"], \
+                    info["relres_true"], beta
+        except Exception as e:
+            r.status, r.error = "failed", str(e)
+        r.finished = clock() - t0
+        results[req.rid] = r
+    return results
+
+
+def summarize(results):
+    lat = np.array([r.latency for r in results.values() if r.status == "done"])
+    done = len(lat)
+    span = max((r.finished for r in results.values()), default=0.0)
+    first = min((r.arrival for r in results.values()), default=0.0)
+    return {
+        "requests": len(results),
+        "done": done,
+        "failed": sum(r.status == "failed" for r in results.values()),
+        "rejected": sum(r.status == "rejected" for r in results.values()),
+        "p50_s": float(np.percentile(lat, 50)) if done else None,
+        "p99_s": float(np.percentile(lat, 99)) if done else None,
+        "mean_s": float(lat.mean()) if done else None,
+        "solves_per_s": done / max(span - first, 1e-9),
+        "makespan_s": span,
+    }

@@ -1,0 +1,127 @@
+"""Scheduler tests on the CPU with a fake backend (no numerics): admission by
+HBM footprint, FIFO order, continuous admission as memory frees, isolation
+of failed requests, rejection of requests larger than the budget."""
+from dataclasses import dataclass
+
+from paper_2304_12465_amd.serve import Server, serve_one_at_a_time, summarize
+
+
+@dataclass
+class Req:
+    rid: int
+    arrival: float
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-3)
+
+
+class FakeBackend:
+    """A request needs `steps` ticks of 10 ms; `fail` = 'build' | 'solve'."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.used = 0
+        self.max_used = 0
+        self.started = []
+
+    def footprint(self, prob):
+        return prob["fp"]
+
+    def start(self, prob):
+        if prob.get("fail") == "build":
+            raise RuntimeError("injected build failure")
+        self.used += prob["fp"]
+        self.max_used = max(self.max_used, self.used)
+        self.started.append(prob["rid"])
+        return {"p": prob, "left": prob["steps"]}
+
+    def step(self, handles):
+        self.clock.t += 0.01
+        out = []
+        for h in handles:
+            h["left"] -= 1
+            if h["p"].get("fail") == "solve" and h["left"] <= 1:
+                out.append(-4)
+            else:
+                out.append(1 if h["left"] <= 0 else 0)
+        return out
+
+    def finish(self, h):
+        self.used -= h["p"]["fp"]
+        return None, {"iters": h["p"]["steps"], "relres_true": 1e-7}
+
+    def cancel(self, h):
+        self.used -= h["p"]["fp"]
+
+
+def run(problems, arrivals, budget, max_active=64):
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [Req(i, a) for i, a in enumerate(arrivals)]
+    srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep)
+    res = srv.run(reqs, lambda r: dict(problems[r.rid], rid=r.rid))
+    return res, be
+
+
+def test_budget_is_never_exceeded_and_all_finish():
+    probs = [dict(fp=30, steps=5 + i % 4) for i in range(12)]
+    res, be = run(probs, [0.005 * i for i in range(12)], budget=100)
+    assert be.max_used <= 100
+    assert all(r.status == "done" for r in res.values())
+    assert all(r.latency >= 0 for r in res.values())
+    assert be.started == sorted(be.started)  # FIFO admission
+
+
+def test_continuous_admission_as_memory_frees():
+    # 3 fit at once; later arrivals join while earlier ones are still running
+    probs = [dict(fp=30, steps=20)] * 3 + [dict(fp=30, steps=2)] * 3
+    res, be = run(probs, [0.0, 0.0, 0.0, 0.0, 0.0, 0.001], budget=100)
+    first_done = min(res[i].finished for i in range(3))
+    assert res[3].admitted < 0.05 + first_done
+    assert all(r.status == "done" for r in res.values())
+    # request 3 was admitted while requests 0..2 were on the device
+    assert res[3].admitted >= min(res[i].admitted for i in range(3))
+
+
+def test_oversized_request_rejected_not_oom():
+    probs = [dict(fp=50, steps=3), dict(fp=500, steps=3), dict(fp=50, steps=3)]
+    res, be = run(probs, [0, 0, 0], budget=100)
+    assert res[1].status == "rejected"
+    assert res[0].status == "done" and res[2].status == "done"
+    assert be.max_used <= 100
+
+
+def test_failures_are_isolated():
+    probs = [dict(fp=10, steps=4), dict(fp=10, steps=4, fail="build"),
+             dict(fp=10, steps=6, fail="solve"), dict(fp=10, steps=5)]
+    res, be = run(probs, [0, 0, 0, 0], budget=100)
+    assert res[1].status == "failed" and "build" in res[1].error
+    assert res[2].status == "failed"
+    assert res[0].status == "done" and res[3].status == "done"
+    assert be.used == 0
+
+
+def test_max_active_limit_and_summary():
+    probs = [dict(fp=1, steps=3)] * 10
+    res, be = run(probs, [0] * 10, budget=1000, max_active=2)
+    assert all(r.status == "done" for r in res.values())
+    s = summarize(res)
+    assert s["done"] == 10 and s["p50_s"] <= s["p99_s"]
+
+
+def test_one_at_a_time_baseline():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [Req(i, 0.0) for i in range(4)]
+    res = serve_one_at_a_time(be, reqs, lambda r: dict(fp=1, steps=3, rid=r.rid), clock=clk,
+                              sleep=clk.sleep)
+    lat = sorted(r.latency for r in res.values())
+    assert lat == sorted(lat) and lat[-1] > lat[0]
