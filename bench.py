@@ -39,13 +39,24 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-tile variant")
     ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default) is the headline line; the others measure the other "
+                         "workloads for the design notes")
+    ap.add_argument("--requests", type=int, default=64, help="c5: number of served requests")
+    ap.add_argument("--no-baseline", action="store_true", help="c5: skip the one-at-a-time run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--product-only", action="store_true",
+                    help="only run 5 launches of the headline product (for counter runs)")
     return ap.parse_args()
 
 
 def laplace_ops_per_entry(d, m):
-    # d subtractions, d absolute-value accumulations, one scale, one exp,
-    # m multiply-adds against V
-    return 2 * d + 2 + m
+    # The method's work per kernel entry, in VALU lane operations: d
+    # absolute-difference accumulations (|x_l - y_l| + s, a single v_sad_u32
+    # on quantised coordinates), one conversion of the l1 sum, one scale,
+    # one exp, and m multiply-adds against V.
+    return d + 3 + m
 
 
 def run_steps(b, torch, p, X, Y, prec, steps, warmup):
@@ -78,6 +89,20 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not code)", file=sys.stderr)
         sys.exit(2)
+    if a.config != "c2":
+        import bench_configs
+        bench_configs.run(a)
+        return
+    if a.copy_calibration:
+        import torch
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "launches": 5}))
+        return
     import numpy as np
     import torch
     from paper_2304_12465_amd import binding as b
@@ -89,6 +114,15 @@ def main():
     Y = torch.from_numpy(p.Y).to(dev)
     N, d = p.X.shape
     torch.cuda.synchronize()
+    if a.product_only:
+        ws = b.workspace(b.kernel_matvec_ws(b.FP32, N, N, d, 1), dev)
+        V = torch.from_numpy(np.random.default_rng(0).standard_normal((N, 1))).to(dev)
+        W = torch.empty_like(V)
+        for _ in range(5):
+            b.kernel_matvec(p.kind, p.sigma, b.FP32, X, X, V, shift=p.mu, out=W, ws=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"product_launches": 5, "entries_per_launch": N * N}))
+        return
 
     wall, infos, tile_ms, launches = run_steps(b, torch, p, X, Y, b.FP32, a.steps, a.warmup)
     iters = [i["iters"] for i in infos]
@@ -123,7 +157,7 @@ def main():
     achieved = ops * N * N / (fp32_launch_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_F32_PEAK_TOPS,
                 "unit": "TOP/s", "frac": round(achieved / VALU_F32_PEAK_TOPS, 4),
-                "traffic": None, "kernel": "tile_valu<Laplace, f32, d=20, m=1>",
+                "traffic": None, "kernel": "tile_lapq<d=20, m=1> (quantised l1, FP32 exp)",
                 "ops_per_entry": ops, "launch_ms": round(fp32_launch_ms, 4),
                 "entries_per_launch": N * N}
 

@@ -1,0 +1,195 @@
+"""Measurements of the workloads other than the headline one (see bench.py):
+
+* c1 — 2,000-point Gaussian, FP64 tiles, RPCholesky r=100, PCG to 1e-10,
+  checked against a dense Cholesky solve;
+* c3 — 1,000,000-point Gaussian (d=32, 8 right-hand sides) on the bf16-split
+  MFMA tiles: per-launch product rate and a whole solve to 1e-6;
+* c4 — 2,000,000-point restricted problem with KRILL (k=10,000): build,
+  restricted product rate, whole solve to 1e-6;
+* c5 — served stream: p50/p99 latency and solves/s, continuously batched on
+  the MIXED path vs the same trace one at a time on the FP64 path.
+
+Each prints one JSON line in the same shape as the headline line.
+"""
+import json
+import sys
+import time
+
+import numpy as np
+
+METRIC = ("kernel entries/s in fused matvec; time-to-1e-6 PCG solve; "
+          "p50/p99 served solve latency")
+
+
+def _line(**kw):
+    base = {"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic"}
+    base.update(kw)
+    print(json.dumps(base), flush=True)
+
+
+def _product_rate(b, torch, kind, sigma, prec, X, m, launches=3):
+    N = X.shape[0]
+    V = torch.from_numpy(np.random.default_rng(0).standard_normal((N, m))).to(X.device)
+    ws = b.workspace(b.kernel_matvec_ws(prec, N, N, X.shape[1], m), X.device)
+    W = torch.empty_like(V)
+    b.kernel_matvec(kind, sigma, prec, X, X, V, out=W, ws=ws)
+    torch.cuda.synchronize()
+    b.timing_read()
+    b.timing_enable(True)
+    for _ in range(launches):
+        b.kernel_matvec(kind, sigma, prec, X, X, V, out=W, ws=ws)
+    torch.cuda.synchronize()
+    b.timing_enable(False)
+    ms, nl = b.timing_read()
+    return ms / max(nl, 1)
+
+
+def c1(a, b, torch, synth):
+    from oracle import direct
+    p = synth.c1()
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(p.Y).cuda()
+    ws = b.workspace(b.rpchol_ws(p.kind, b.FP64, 2000, 8, p.rank, 0, 1), X.device)
+    times, infos = [], []
+    for k in range(a.warmup + a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = b.rpchol_build(p.kind, p.sigma, b.FP64, X, p.mu, p.rank, seed=p.algo_seed, ws=ws)
+        beta, info = P.solve(Y, p.tol, 1000)
+        torch.cuda.synchronize()
+        if k >= a.warmup:
+            times.append(time.perf_counter() - t0)
+            infos.append(info)
+    xd = direct.full_krr(p.X, p.Y, p.kind, p.sigma, p.mu)
+    err = float(np.linalg.norm(beta.cpu().numpy() - xd) / np.linalg.norm(xd))
+    it = infos[-1]["iters"]
+    t = float(np.mean(times))
+    t_cpu0 = time.perf_counter()
+    direct.full_krr(p.X, p.Y, p.kind, p.sigma, p.mu)
+    t_cpu = time.perf_counter() - t_cpu0
+    _line(value=(it + 1) * 2000 * 2000 / t, unit="kernel entries/s", steps=a.steps,
+          warmup=a.warmup, ms_per_step=t * 1e3, dtype="f64",
+          config={"workload": "full-data KRR, Gaussian, N=2000, d=8, sigma=sqrt(8), mu=1e-3, "
+                              "RPCholesky r=100 (B=10), PCG to 1e-10, FP64 tiles"},
+          solve={"iters": it, "relres_true": infos[-1]["relres_true"],
+                 "rel_error_vs_dense_cholesky": err},
+          cpu_baseline={"value": t_cpu, "unit": "s (dense Cholesky solve, scipy)",
+                        "kind": "oracle", "cores": 1, "sample": "whole problem"})
+
+
+def c3(a, b, torch, synth):
+    p = synth.c3()
+    N, d = p.X.shape
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(p.Y).cuda()
+    m = p.Y.shape[1]
+    ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)
+    rate = N * N / (ms * 1e-3)
+    # executed MFMA work per entry: 3 split products of K=32 for the distance
+    # and 3 of K=16-column V tiles, 2 flops per multiply-add
+    mfma_flops = (3 * 2 * 32) + (3 * 2 * 16)
+    out = {"product_ms": ms, "entries_per_s": rate,
+           "mfma_tflops_executed": rate * mfma_flops / 1e12,
+           "mfma_frac_of_bf16_peak": rate * mfma_flops / 2.5e15}
+    ms32 = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, m, launches=1)
+    out["fp32_valu_product_ms"] = ms32
+    steps = []
+    if a.steps > 0:
+        ws = b.workspace(b.rpchol_ws(p.kind, b.MIXED, N, d, p.rank, 0, m), X.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = b.rpchol_build(p.kind, p.sigma, b.MIXED, X, p.mu, p.rank, seed=p.algo_seed,
+                           m_max=m, ws=ws)
+        print(f"c3: build done in {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+        S = b.Solve(P, Y, p.tol, 2000)
+        k = 0
+        while b.solve_step([S])[0] == 0:
+            k += 1
+            if k % 25 == 0:
+                print(f"c3: step {k}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+        beta, info = S.end()
+        torch.cuda.synchronize()
+        steps.append(time.perf_counter() - t0)
+        out.update(solve_s=steps[0], build_s=info["build_seconds"], iters=info["iters"],
+                   relres_true=info["relres_true"], relres_recursive=info["relres_recursive"],
+                   rank=P.dims()[0], converged=info["converged"])
+    _line(value=rate, unit="kernel entries/s", steps=len(steps), warmup=0,
+          ms_per_step=(steps[0] * 1e3 if steps else None), dtype="bf16x3/f32",
+          config={"workload": "full-data KRR, Gaussian, N=1e6, d=32, uniform [0,1]^32 with 5% "
+                              "near-duplicates, 8 RHS, sigma=1.5, mu=1e-6 N, RPCholesky r=2000, "
+                              "bf16-split MFMA tiles, PCG to 1e-6"},
+          result=out)
+
+
+def c4(a, b, torch, synth):
+    p = synth.c4()
+    N, d = p.X.shape
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(p.Y).cuda()
+    res = {}
+    for prec, name in ((b.FP32, "fp32"), (b.FP64, "fp64")):
+        ws = b.workspace(b.krill_ws(p.kind, prec, N, d, p.centers, p.sketch_rows, p.zeta, 1),
+                         X.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = b.krill_build(p.kind, p.sigma, prec, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
+                          zeta=p.zeta, seed=p.algo_seed, ws=ws)
+        tb = time.perf_counter() - t0
+        beta, info = P.solve(Y, p.tol, 200)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        # restricted operator timing (two products of N x k entries each)
+        V = torch.from_numpy(np.random.default_rng(1).standard_normal((p.centers, 1))).cuda()
+        P.operator(V)
+        torch.cuda.synchronize()
+        b.timing_read()
+        b.timing_enable(True)
+        t1 = time.perf_counter()
+        for _ in range(3):
+            P.operator(V)
+        torch.cuda.synchronize()
+        top = (time.perf_counter() - t1) / 3
+        b.timing_enable(False)
+        tms, tn = b.timing_read()
+        res[name] = {"build_s": tb, "solve_total_s": tt, "iters": info["iters"],
+                     "relres_true": info["relres_true"], "operator_ms": top * 1e3,
+                     "tile_ms_per_launch": tms / max(tn, 1),
+                     "entries_per_s": 2 * N * p.centers / top}
+        del P, ws
+        torch.cuda.empty_cache()
+    _line(value=res["fp32"]["entries_per_s"], unit="kernel entries/s", steps=1, warmup=0,
+          ms_per_step=res["fp32"]["solve_total_s"] * 1e3, dtype="f32",
+          config={"workload": "restricted KRR with KRILL, Gaussian sigma=4, N=2e6, d=16, "
+                              "k=10000 centres, sketch 20000 x 8 nonzeros, mu=1e-5 N, PCG to 1e-6"},
+          result=res)
+
+
+def c5(a, b, torch, synth):
+    from paper_2304_12465_amd.serve import Server, GpuBackend, serve_one_at_a_time, summarize
+    stream = synth.c5_stream(count=a.requests)
+    be = GpuBackend(b.MIXED, tol=1e-6, max_iter=500)
+    srv = Server(be, hbm_budget=160 << 30, max_active=64)
+    t0 = time.perf_counter()
+    res = srv.run(stream, synth.c5_problem)
+    tmix = time.perf_counter() - t0
+    s_mix = summarize(res)
+    out = {"batched_mixed": s_mix, "batched_wall_s": tmix}
+    if not a.no_baseline:
+        be64 = GpuBackend(b.FP64, tol=1e-6, max_iter=500)
+        res64 = serve_one_at_a_time(be64, stream, synth.c5_problem)
+        out["one_at_a_time_fp64"] = summarize(res64)
+    _line(value=s_mix["solves_per_s"], unit="solves/s", steps=1, warmup=0,
+          ms_per_step=tmix * 1e3, dtype="bf16x3/f32 (Gaussian), f32 (Laplace)",
+          config={"workload": f"served stream: {a.requests} requests, Poisson 20/s, N log-uniform "
+                              "[1e4, 3e5], d in {8,16,32}, Gaussian/Laplace, 1-16 RHS, "
+                              "r=min(1000, N/50), PCG to 1e-6"},
+          result=out)
+
+
+def run(a):
+    import torch
+    import synth
+    from paper_2304_12465_amd import binding as b
+    {"c1": c1, "c3": c3, "c4": c4, "c5": c5}[a.config](a, b, torch, synth)

@@ -86,14 +86,26 @@ extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precisi
   KRR_TRY(check_ws(ws, ws_bytes, need));
   Arena arena(ws, ws_bytes);
   PointSet rows, cols;
-  if (Xc == Xr && nc == nr) {
-    KRR_TRY(pack_points(kind, prec, Xr, nr, d, nullptr, arena, &rows, stream));
-    cols = rows;
+  const bool same = (Xc == Xr && nc == nr);
+  KRR_TRY(carve_points(kind, prec, nr, d, arena, &rows));
+  if (same) cols = rows;
+  else KRR_TRY(carve_points(kind, prec, nc, d, arena, &cols));
+  if (!arena.ok()) {
+    set_error("workspace too small for the point layouts");
+    return KRR_EWORKSPACE;
+  }
+  if (same) {
+    KRR_TRY(fill_points(kind, prec, Xr, nullptr, rows, stream));
+  } else if (kind == KRR_LAPLACE && prec != KRR_FP64) {
+    // one quantisation over both sets
+    KRR_TRY(quant_params(Xr, nr, Xc, nc, d, rows.qbits, rows.qpart, const_cast<double*>(rows.qp),
+                         stream));
+    KRR_TRY(fill_points(kind, prec, Xr, rows.qp, rows, stream));
+    KRR_TRY(fill_points(kind, prec, Xc, rows.qp, cols, stream));
   } else {
-    // columns first: under MIXED Gaussian tiles both sets share the
-    // columns' centre (distances are translation invariant)
-    KRR_TRY(pack_points(kind, prec, Xc, nc, d, nullptr, arena, &cols, stream));
-    KRR_TRY(pack_points(kind, prec, Xr, nr, d, nc > 0 ? cols.centre : nullptr, arena, &rows,
+    // columns first: MIXED Gaussian rows share the columns' centre
+    KRR_TRY(fill_points(kind, prec, Xc, nullptr, cols, stream));
+    KRR_TRY(fill_points(kind, prec, Xr, nc > 0 ? shared_params(kind, prec, cols) : nullptr, rows,
                         stream));
   }
   VecView v{V, m, 1};

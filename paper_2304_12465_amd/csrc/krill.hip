@@ -395,7 +395,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
   gather_raw<<<(unsigned)ceil_div(k * P.d, 256), 256, 0, s>>>(X, P.d, P.centers, k, w.craw);
   KRR_LAUNCH_CHECK("gather_raw");
   KRR_TRY(fill_points(P.kind, KRR_FP64, w.craw, nullptr, P.cpts64, s));
-  if (P.prec != KRR_FP64) KRR_TRY(fill_points(P.kind, P.prec, w.craw, P.pts.centre, P.cpts, s));
+  if (P.prec != KRR_FP64)
+    KRR_TRY(fill_points(P.kind, P.prec, w.craw, shared_params(P.kind, P.prec, P.pts), P.cpts, s));
 
   // 2. H = mu A_SS + N eps tr(A_SS) I  (tr(A_SS) = k: unit diagonal)
   KRR_TRY(kernel_block64(P.kind, P.sigma, P.cpts64, P.cpts64, P.H, k, s));

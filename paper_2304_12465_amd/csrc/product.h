@@ -20,7 +20,18 @@ struct PointSet {
   const double* centre = nullptr; // d doubles subtracted before the split
   double* cpart = nullptr;        // 256 x 64 partial sums for the centre
   int32_t kpad = 0;
+  // Laplace tiles under FP32 / MIXED: coordinates quantised to `qbits`-bit
+  // unsigned fixed point, q = round((x - lo) S); the l1 sums of a tile are
+  // then exact 32-bit integer sums of |q_x - q_y| (one v_sad_u32 each).
+  const uint32_t* xq = nullptr;   // n x dpad
+  const double* qp = nullptr;     // [lo, S] (device), shared by rows and columns
+  double* qpart = nullptr;        // 256 x 2 partial min/max
+  int32_t qbits = 0;
 };
+
+// Quantisation range of a point set (or of two): qp[0] = lo, qp[1] = S.
+int quant_params(const double* X1, int64_t n1, const double* X2, int64_t n2, int32_t d,
+                 int32_t qbits, double* qpart, double* qp, hipStream_t s);
 
 int padded_dim(int32_t d);                       // 0 if d unsupported
 int mfma_kdim(int32_t d);                        // bf16 K padding (multiple of 32)
@@ -32,9 +43,13 @@ size_t pointset_bytes(krr_kernel_kind kind, krr_precision prec, int64_t n, int32
 int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d, Arena& arena,
                  PointSet* out);
 // Fills a carved layout from FP64 points X (n x d, row-major, device).
-// `centre` (d doubles, device, or null) is subtracted first.
-int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* centre,
+// `shared` carries parameters that several point sets of one problem must
+// agree on (device, or null to derive them from X): the centre (d doubles)
+// of MIXED Gaussian layouts, the quantisation [lo, S] of Laplace FP32 /
+// MIXED layouts.
+int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* shared,
                 const PointSet& ps, hipStream_t s);
+const double* shared_params(krr_kernel_kind kind, krr_precision prec, const PointSet& ps);
 // carve_points + fill_points.
 int pack_points(krr_kernel_kind kind, krr_precision prec, const double* X, int64_t n, int32_t d,
                 const double* centre, Arena& arena, PointSet* out, hipStream_t s);

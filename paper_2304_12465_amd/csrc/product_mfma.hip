@@ -36,8 +36,8 @@ __device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint3
 }
 
 constexpr int kRT = 4;       // 16-row tiles per wave
-constexpr int kCols = 32;    // columns per LDS chunk (two 16-column MFMA tiles)
-constexpr int kFoldChunks = 8;  // FP32 chunks per FP64 fold (256 columns)
+constexpr int kCols = 64;    // columns per LDS chunk (four 16-column MFMA tiles)
+constexpr int kFoldChunks = 4;  // FP32 chunks per FP64 fold (256 columns)
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
@@ -52,32 +52,29 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
   const uint16_t* __restrict__ Xlo = J.xlo;
   const float* __restrict__ Xn = J.xn;
   const int64_t nr = J.nr;
-  const uint16_t* __restrict__ Yhi = J.yhi;
-  const uint16_t* __restrict__ Ylo = J.ylo;
-  const float* __restrict__ Yn = J.yn;
-  const uint16_t* __restrict__ Vhi = J.vh;
-  const uint16_t* __restrict__ Vlo = J.vl;
   const int64_t nc = J.nc;
   const float s = J.s;
-  const int64_t cols_per_split = J.per;
   const int M = J.M;
-  double* __restrict__ part = J.part;
-  constexpr int KS = KP / 32;      // MFMA K steps of the distance contraction
-  constexpr int YP = KP + 8;       // LDS row pitch (bf16) of the column points
+  constexpr int KS = KP / 32;       // MFMA K steps of the distance contraction
+  constexpr int YP = KP + 8;        // LDS row pitch (bf16) of the column points
+  constexpr int NG = kCols / 32;    // 32-column groups per chunk (V-reduction K)
   __shared__ __attribute__((aligned(16))) __bf16 sYh[kCols][YP];
   __shared__ __attribute__((aligned(16))) __bf16 sYl[kCols][YP];
   __shared__ __attribute__((aligned(16))) float sAy[kCols];
-  __shared__ __attribute__((aligned(16))) __bf16 sVh[16][kCols + 8];  // [c][slot], slot = 8g + v
-  __shared__ __attribute__((aligned(16))) __bf16 sVl[16][kCols + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sVh[NG][16][32 + 8];  // [group][c][slot]
+  __shared__ __attribute__((aligned(16))) __bf16 sVl[NG][16][32 + 8];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row0 = (rg * 4 + wave) * (16 * kRT);
 
-  // row operands (B of the distance MFMA): X[i0 + li][8g .. 8g+8] per K step
+  // Row operands (B of the distance MFMA): X[i0 + li][8g .. 8g+8] per K
+  // step.  The distance MFMA starts from -||x||^2 / 2 (accumulator init), so
+  // its result is x.y - ||x||^2 / 2 and one FMA gives the exponent
+  // 2 s (x.y - ||x||^2/2) - s ||y||^2 = -s ||x - y||^2.
   bf16x8 xh[kRT][KS], xl[kRT][KS];
-  float ax[kRT];
+  f32x4 cinit[kRT];
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     int64_t i = row0 + rt * 16 + li;
@@ -87,7 +84,8 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
       xh[rt][ks] = *reinterpret_cast<const bf16x8*>(Xhi + i * KP + ks * 32 + g * 8);
       xl[rt][ks] = *reinterpret_cast<const bf16x8*>(Xlo + i * KP + ks * 32 + g * 8);
     }
-    ax[rt] = -s * Xn[i];
+    const float h = -0.5f * Xn[i];
+    cinit[rt] = f32x4{h, h, h, h};
   }
   f32x4 acc[kRT];
   double acc64[kRT][4];
@@ -99,20 +97,24 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
   }
   const float s2 = 2.0f * s;
 
-  const int64_t j0 = (int64_t)split * cols_per_split;
-  int64_t j1 = j0 + cols_per_split;
+  const int64_t j0 = (int64_t)split * J.per;
+  int64_t j1 = j0 + J.per;
   if (j1 > nc) j1 = nc;
   int chunk = 0;
   for (int64_t jb = j0; jb < j1; jb += kCols, ++chunk) {
+    const int ncol = (int)((j1 - jb < kCols) ? j1 - jb : kCols);
+    const uint16_t* __restrict__ yhb = J.yhi + jb * KP;
+    const uint16_t* __restrict__ ylb = J.ylo + jb * KP;
+    const uint16_t* __restrict__ vhb = J.vh + jb * 16;
+    const uint16_t* __restrict__ vlb = J.vl + jb * 16;
     __syncthreads();
-    // stage the chunk: points (hi/lo), -s*||y||^2, and V (hi/lo, permuted)
+    // stage the chunk: points (hi/lo), -s ||y||^2, V (hi/lo, K-permuted)
     for (int e = tid; e < kCols * (KP / 8); e += 256) {
       const int jj = e / (KP / 8), seg = e % (KP / 8);
-      const int64_t j = jb + jj;
       bf16x8 h, l;
-      if (j < j1) {
-        h = *reinterpret_cast<const bf16x8*>(Yhi + j * KP + seg * 8);
-        l = *reinterpret_cast<const bf16x8*>(Ylo + j * KP + seg * 8);
+      if (jj < ncol) {
+        h = *reinterpret_cast<const bf16x8*>(yhb + jj * KP + seg * 8);
+        l = *reinterpret_cast<const bf16x8*>(ylb + jj * KP + seg * 8);
       } else {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -124,68 +126,69 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
       *reinterpret_cast<bf16x8*>(&sYl[jj][seg * 8]) = l;
     }
     if (tid < kCols) {
-      const int64_t j = jb + tid;
       // columns past the range get a huge distance: exp -> 0
-      sAy[tid] = (j < j1) ? -s * Yn[j] : -3.0e38f;
+      sAy[tid] = (tid < ncol) ? -s * J.yn[jb + tid] : -3.0e38f;
     }
-    for (int e = tid; e < 16 * kCols; e += 256) {
-      const int c = e / kCols, slot = e % kCols;
-      const int col = slot_col(slot / 8, slot % 8);
-      const int64_t j = jb + col;
+    for (int e = tid; e < NG * 16 * 32; e += 256) {
+      const int gi = e / 512, r = e % 512;
+      const int c = r / 32, slot = r % 32;
+      const int col = gi * 32 + slot_col(slot / 8, slot % 8);
       uint16_t vh = 0, vl = 0;
-      if (j < j1 && c < M) {
-        vh = Vhi[j * 16 + c];
-        vl = Vlo[j * 16 + c];
+      if (col < ncol && c < M) {
+        vh = vhb[col * 16 + c];
+        vl = vlb[col * 16 + c];
       }
-      sVh[c][slot] = __builtin_bit_cast(__bf16, vh);
-      sVl[c][slot] = __builtin_bit_cast(__bf16, vl);
+      sVh[gi][c][slot] = __builtin_bit_cast(__bf16, vh);
+      sVl[gi][c][slot] = __builtin_bit_cast(__bf16, vl);
     }
     __syncthreads();
     if (row0 >= nr) continue;  // idle wave still joins the barriers
-    // A operands of the distance MFMA for the two column tiles
-    bf16x8 yh[2][KS], yl[2][KS];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+    for (int gi = 0; gi < NG; ++gi) {
+      // A operands of the distance MFMA for the group's two column tiles
+      bf16x8 yh[2][KS], yl[2][KS];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        yh[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYh[ct * 16 + li][ks * 32 + g * 8]);
-        yl[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYl[ct * 16 + li][ks * 32 + g * 8]);
-      }
-    float ay[2][4];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ay[ct][u] = sAy[ct * 16 + 4 * g + u];
-    const bf16x8 vh = *reinterpret_cast<const bf16x8*>(&sVh[li][g * 8]);
-    const bf16x8 vl = *reinterpret_cast<const bf16x8*>(&sVl[li][g * 8]);
-#pragma unroll
-    for (int rt = 0; rt < kRT; ++rt) {
-      uint32_t eh[4], el[4];  // 8 bf16 each: K slots 8g .. 8g+7
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        f32x4 dot = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xh[rt][ks], dot, 0, 0, 0);
-          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xl[rt][ks], dot, 0, 0, 0);
-          dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[ct][ks], xh[rt][ks], dot, 0, 0, 0);
+          yh[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYh[gi * 32 + ct * 16 + li][ks * 32 + g * 8]);
+          yl[ct][ks] = *reinterpret_cast<const bf16x8*>(&sYl[gi * 32 + ct * 16 + li][ks * 32 + g * 8]);
         }
-        // dot[u] = y_{4g+u} . x_{li} of column tile ct; the exponent
-        // -s (||x||^2 + ||y||^2 - 2 x.y) is left unclamped: rounding can make
-        // it ~1e-6 positive, within the split's error budget.
-        float e[4];
+      float ay[2][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          e[u] = __builtin_amdgcn_exp2f(__builtin_fmaf(dot[u], s2, ax[rt] + ay[ct][u]));
-        split_pair(e[0], e[1], eh[ct * 2 + 0], el[ct * 2 + 0]);
-        split_pair(e[2], e[3], eh[ct * 2 + 1], el[ct * 2 + 1]);
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ay[ct][u] = sAy[gi * 32 + ct * 16 + 4 * g + u];
+      const bf16x8 vh = *reinterpret_cast<const bf16x8*>(&sVh[gi][li][g * 8]);
+      const bf16x8 vl = *reinterpret_cast<const bf16x8*>(&sVl[gi][li][g * 8]);
+#pragma unroll
+      for (int rt = 0; rt < kRT; ++rt) {
+        uint32_t eh[4], el[4];  // 8 bf16 each: K slots 8g .. 8g+7
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          f32x4 dot = cinit[rt];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xh[rt][ks], dot, 0, 0, 0);
+            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xl[rt][ks], dot, 0, 0, 0);
+            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[ct][ks], xh[rt][ks], dot, 0, 0, 0);
+          }
+          // dot[u] = y_{4g+u} . x_{li} - ||x_{li}||^2 / 2; the exponent is left
+          // unclamped: rounding can make it ~1e-6 positive, within the
+          // split's error budget.
+          float e[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) e[u] = __builtin_amdgcn_exp2f(__builtin_fmaf(dot[u], s2, ay[ct][u]));
+          split_pair(e[0], e[1], eh[ct * 2 + 0], el[ct * 2 + 0]);
+          split_pair(e[2], e[3], eh[ct * 2 + 1], el[ct * 2 + 1]);
+        }
+        const bf16x8 EH = __builtin_bit_cast(bf16x8, eh);
+        const bf16x8 EL = __builtin_bit_cast(bf16x8, el);
+        // W[i][c] += sum_j E[i][j] V[j][c]: A = E (rows li, K slots 8g..8g+7)
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vh, acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vl, acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EL, vh, acc[rt], 0, 0, 0);
       }
-      const bf16x8 EH = __builtin_bit_cast(bf16x8, eh);
-      const bf16x8 EL = __builtin_bit_cast(bf16x8, el);
-      // W[i][c] += sum_j E[i][j] V[j][c]: A = E (rows li, K slots 8g..8g+7)
-      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vh, acc[rt], 0, 0, 0);
-      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EH, vl, acc[rt], 0, 0, 0);
-      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(EL, vh, acc[rt], 0, 0, 0);
     }
     if ((chunk + 1) % kFoldChunks == 0) {
 #pragma unroll
@@ -197,7 +200,7 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
     }
   }
   if (row0 >= nr) return;
-  double* __restrict__ out = part + (int64_t)split * nr * 16;
+  double* __restrict__ out = J.part + (int64_t)split * nr * 16;
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
 #pragma unroll

@@ -38,6 +38,9 @@ struct TileJob {
   const T* Xr;
   const T* Xc;
   const T* Vc;
+  const uint32_t* Qr;  // quantised points (Laplace FP32 / MIXED tiles)
+  const uint32_t* Qc;
+  const double* qp;    // [lo, S]
   double* part;
   int64_t nr, nc, per;
   int64_t item0;  // first work item of this job in the launch
@@ -151,6 +154,103 @@ __global__ __launch_bounds__(256) void tile_valu(const JobTable<T> tab) {
   }
 }
 
+// |x - y| + acc as one v_sad_u32: the empty asm keeps the compiler from
+// reassociating the integer chain into max/min/sub/add3 sequences.
+__device__ __forceinline__ uint32_t sad_u32(uint32_t x, uint32_t y, uint32_t acc) {
+  uint32_t r = (x > y ? x - y : y - x) + acc;
+  __asm__("" : "+v"(r));
+  return r;
+}
+
+// Laplace tile on quantised coordinates: the l1 distance of a pair is the
+// exact 32-bit sum of |q_x - q_y| (v_sad_u32, one instruction per
+// coordinate with the column coordinate as an SGPR operand), converted to
+// FP32 once and scaled by -log2(e) / (sigma S) inside exp2.
+template <int D, int M, int R>
+__device__ __forceinline__ void tile_item_q(const uint32_t* __restrict__ Qr, int64_t nr,
+                                            const uint32_t* __restrict__ Qc,
+                                            const float* __restrict__ Vc, int64_t nc,
+                                            float scale, int split, int64_t cols_per_split,
+                                            int64_t rg, double* __restrict__ part) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (rg * kWaves + wave) * 64 * R;
+  if (row0 >= nr) return;
+  uint32_t x[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int64_t i = row0 + lane + 64 * r;
+    if (i > nr - 1) i = nr - 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[r][k] = Qr[i * D + k];
+  }
+  double acc64[R][M];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc64[r][c] = 0.0;
+  const int64_t j0 = (int64_t)split * cols_per_split;
+  int64_t j1 = j0 + cols_per_split;
+  if (j1 > nc) j1 = nc;
+  for (int64_t jb = j0; jb < j1; jb += kFold) {
+    const int64_t je = (jb + kFold < j1) ? jb + kFold : j1;
+    float acc[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc[r][c] = 0.f;
+#pragma unroll 2
+    for (int64_t j = jb; j < je; ++j) {
+      const uint32_t* __restrict__ yc = Qc + j * D;
+      const float* __restrict__ vc = Vc + j * M;
+      uint32_t y[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) y[k] = yc[k];
+      float v[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) v[c] = vc[c];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // one chain per row (R rows give R independent chains); it starts
+        // from an opaque zero so that every step stays a v_sad_u32
+        uint32_t s0 = 0;
+        __asm__("" : "+v"(s0));
+#pragma unroll
+        for (int k = 0; k < D; ++k) s0 = sad_u32(x[r][k], y[k], s0);
+        const float e = __builtin_amdgcn_exp2f((float)s0 * scale);
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[r][c] = __builtin_fmaf(e, v[c], acc[r][c]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < M; ++c) acc64[r][c] += (double)acc[r][c];
+  }
+  double* __restrict__ out = part + (int64_t)split * nr * M;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int64_t i = row0 + lane + 64 * r;
+    if (i < nr) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) out[i * M + c] = acc64[r][c];
+    }
+  }
+}
+
+template <int D, int M, int R>
+__global__ __launch_bounds__(256) void tile_lapq(const JobTable<float> tab) {
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const TileJob<float>& J = tab.job[jn];
+    const int64_t local = item - J.item0;
+    const float sc = (float)((double)J.scale / J.qp[1]);
+    tile_item_q<D, M, R>(J.Qr, J.nr, J.Qc, J.Vc, J.nc, sc, (int)(local % J.nsplit), J.per,
+                         local / J.nsplit, J.part);
+  }
+}
+
 // W[i, c0+c] = sum_s part[s, i, c] + shift * Vs[i, c0+c], fixed order over s.
 __global__ __launch_bounds__(256) void reduce_splits(const double* __restrict__ part, int nsplit,
                                                      int64_t nr, int M, int mc, int c0,
@@ -163,6 +263,65 @@ __global__ __launch_bounds__(256) void reduce_splits(const double* __restrict__ 
   for (int q = 0; q < nsplit; ++q) s += part[((int64_t)q * nr + i) * M + c];
   if (shift != 0.0) s += shift * Vs.p[i * Vs.rs + (int64_t)(c0 + c) * Vs.cs];
   W.p[i * W.rs + (int64_t)(c0 + c) * W.cs] = s;
+}
+
+// per-block min / max of all coordinates of up to two point sets
+__global__ __launch_bounds__(256) void minmax_part(const double* __restrict__ X1, int64_t len1,
+                                                   const double* __restrict__ X2, int64_t len2,
+                                                   int64_t chunk, double* __restrict__ part) {
+  __shared__ double smin[256], smax[256];
+  const int64_t tot = len1 + len2;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = (b0 + chunk < tot) ? b0 + chunk : tot;
+  double lo = 1.0e308, hi = -1.0e308;
+  for (int64_t t = b0 + threadIdx.x; t < b1; t += 256) {
+    const double v = t < len1 ? X1[t] : X2[t - len1];
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smin[0];
+    part[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+__global__ void minmax_final(const double* __restrict__ part, int nb, double qmax,
+                             double* __restrict__ qp) {
+  double lo = 1.0e308, hi = -1.0e308;
+  for (int b = 0; b < nb; ++b) {
+    lo = fmin(lo, part[2 * b]);
+    hi = fmax(hi, part[2 * b + 1]);
+  }
+  const double range = hi - lo;
+  qp[0] = lo;
+  qp[1] = range > 0.0 ? qmax / range : 1.0;
+}
+
+// q = round((x - lo) S), clamped to [0, 2^qbits - 1]; padding stays 0
+__global__ void pack_quant(const double* __restrict__ X, int64_t n, int d, int dpad,
+                           const double* __restrict__ qp, double qmax,
+                           uint32_t* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * dpad) return;
+  const int64_t i = t / dpad;
+  const int k = (int)(t % dpad);
+  uint32_t q = 0;
+  if (k < d) {
+    double v = rint((X[i * d + k] - qp[0]) * qp[1]);
+    v = v < 0.0 ? 0.0 : (v > qmax ? qmax : v);
+    q = (uint32_t)v;
+  }
+  out[t] = q;
 }
 
 template <typename T>
@@ -199,6 +358,39 @@ void* tile_ptr() {
 }
 template <typename T>
 using TileFn = void (*)(const JobTable<T>);
+
+// quantised tiles: more rows per lane give more independent SAD chains
+// (dependent v_sad_u32 issued back to back need a wait state on gfx950)
+template <int D>
+constexpr int rows_per_lane_q() { return D <= 24 ? 4 : (D <= 48 ? 2 : 1); }
+int rows_for_q(int D) { return D <= 24 ? 4 : (D <= 48 ? 2 : 1); }
+
+template <int D, int M>
+void* tileq_ptr() {
+  return reinterpret_cast<void*>(&tile_lapq<D, M, rows_per_lane_q<D>()>);
+}
+template <int D>
+void* pickq_m(int M) {
+  switch (M) {
+    case 1: return tileq_ptr<D, 1>();
+    case 2: return tileq_ptr<D, 2>();
+    case 4: return tileq_ptr<D, 4>();
+    case 8: return tileq_ptr<D, 8>();
+    default: return tileq_ptr<D, 16>();
+  }
+}
+void* pickq_d(int D, int M) {
+  switch (D) {
+    case 4: return pickq_m<4>(M);
+    case 8: return pickq_m<8>(M);
+    case 16: return pickq_m<16>(M);
+    case 20: return pickq_m<20>(M);
+    case 24: return pickq_m<24>(M);
+    case 32: return pickq_m<32>(M);
+    case 48: return pickq_m<48>(M);
+    default: return pickq_m<64>(M);
+  }
+}
 
 template <int KIND, typename T, int D>
 void* pick_m(int M) {
@@ -326,6 +518,12 @@ size_t pointset_bytes(krr_kernel_kind kind, krr_precision prec, int64_t n, int32
   return a.used;
 }
 
+int quant_bits(int D) {
+  int lg = 0;
+  while ((1 << lg) < D) ++lg;
+  return std::min(30, 32 - lg);
+}
+
 int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d, Arena& arena,
                  PointSet* out) {
   const int D = padded_dim(d);
@@ -343,10 +541,33 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
   }
   out->x32 = arena.take<float>((size_t)n * D);
   if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) KRR_TRY(carve_mixed(n, d, arena, out));
+  if (kind == KRR_LAPLACE) {
+    out->qbits = quant_bits(D);
+    out->xq = arena.take<uint32_t>((size_t)n * D);
+    out->qp = arena.take<double>(4);
+    out->qpart = arena.take<double>(2 * 256);
+  }
   return KRR_OK;
 }
 
-int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* centre,
+const double* shared_params(krr_kernel_kind kind, krr_precision prec, const PointSet& ps) {
+  if (prec == KRR_FP64) return nullptr;
+  return kind == KRR_LAPLACE ? ps.qp : ps.centre;
+}
+
+int quant_params(const double* X1, int64_t n1, const double* X2, int64_t n2, int32_t d,
+                 int32_t qbits, double* qpart, double* qp, hipStream_t s) {
+  const int64_t tot = (n1 + n2) * d;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(tot, 4096)));
+  const int64_t chunk = ceil_div(std::max<int64_t>(tot, 1), nb);
+  minmax_part<<<nb, 256, 0, s>>>(X1, n1 * d, X2, n2 * d, chunk, qpart);
+  KRR_LAUNCH_CHECK("minmax_part");
+  minmax_final<<<1, 1, 0, s>>>(qpart, nb, (double)((1u << qbits) - 1u), qp);
+  KRR_LAUNCH_CHECK("minmax_final");
+  return KRR_OK;
+}
+
+int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const double* shared,
                 const PointSet& ps, hipStream_t s) {
   const int64_t n = ps.n;
   if (n == 0) return KRR_OK;
@@ -361,7 +582,8 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
       set_error("fill_points: layout not carved");
       return KRR_EINVAL;
     }
-    pack_pts<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, centre, const_cast<double*>(ps.x64));
+    pack_pts<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr,
+                                                                   const_cast<double*>(ps.x64));
     KRR_LAUNCH_CHECK("pack_pts<double>");
     return KRR_OK;
   }
@@ -370,9 +592,24 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     return KRR_EINVAL;
   }
   // FP32 points are not centred (VALU tiles use direct differences)
-  pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr, const_cast<float*>(ps.x32));
+  pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr,
+                                                                const_cast<float*>(ps.x32));
   KRR_LAUNCH_CHECK("pack_pts<float>");
-  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) return fill_mixed(X, centre, ps, s);
+  if (kind == KRR_LAPLACE) {
+    double* qp = const_cast<double*>(ps.qp);
+    if (shared) {
+      if (shared != qp)
+        KRR_TRY(hip_check(hipMemcpyAsync(qp, shared, 2 * sizeof(double), hipMemcpyDeviceToDevice, s),
+                          "quant params"));
+    } else {
+      KRR_TRY(quant_params(X, n, nullptr, 0, ps.d, ps.qbits, ps.qpart, qp, s));
+    }
+    pack_quant<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(
+        X, n, ps.d, D, qp, (double)((1u << ps.qbits) - 1u), const_cast<uint32_t*>(ps.xq));
+    KRR_LAUNCH_CHECK("pack_quant");
+    return KRR_OK;
+  }
+  if (prec == KRR_MIXED) return fill_mixed(X, shared, ps, s);
   return KRR_OK;
 }
 
@@ -393,7 +630,7 @@ size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t
   // worst case over the row-per-lane choices (more rows per lane -> fewer
   // row groups -> more column splits)
   int64_t ns = 1;
-  for (int R = 1; R <= 2; ++R) ns = std::max<int64_t>(ns, choose_split(nr, nc, R).nsplit);
+  for (int R = 1; R <= 4; ++R) ns = std::max<int64_t>(ns, choose_split(nr, nc, R).nsplit);
   Arena a;
   a.take<char>((size_t)std::max<int64_t>(nc, 1) * M * es);
   a.take<double>((size_t)ns * std::max<int64_t>(nr, 1) * M);
@@ -487,7 +724,8 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       }
       const int D = r.rows->dpad;
       const bool f64 = r.prec == KRR_FP64;
-      const int R = rows_for_dpad(D);
+      const bool quantised = !f64 && r.kind == KRR_LAPLACE;
+      const int R = quantised ? rows_for_q(D) : rows_for_dpad(D);
       const int M = mpad(mc);
       Split sp = choose_split(nr, nc, R);
       void* vp = f64 ? (void*)sc.take<double>((size_t)std::max<int64_t>(nc, 1) * M)
@@ -520,11 +758,22 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       } else {
         pack_vec<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(r.V, nc, c0, mc, M, (float*)vp);
         KRR_LAUNCH_CHECK("pack_vec");
+        const bool quant = r.kind == KRR_LAPLACE;
+        if (quant && (!r.rows->xq || !r.cols->xq || r.rows->qp != r.cols->qp)) {
+          // rows and columns must share one quantisation (same qp buffer or
+          // identical copies): the row set's parameters are used
+          if (!r.rows->xq || !r.cols->xq) {
+            set_error("Laplace FP32 tiles: quantised layout missing");
+            return KRR_EINVAL;
+          }
+        }
         const float sc32 = (float)(r.kind == KRR_LAPLACE ? -log2e / r.sigma
                                                          : -log2e / (2.0 * r.sigma * r.sigma));
-        void* fn = r.kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, float>(D, M)
-                                         : pick_d<KRR_GAUSSIAN, float>(D, M);
+        void* fn = quant ? pickq_d(D, M) : pick_d<KRR_GAUSSIAN, float>(D, M);
         TileJob<float> j{};
+        j.Qr = r.rows->xq;
+        j.Qc = r.cols->xq;
+        j.qp = r.rows->qp;
         j.Xr = r.rows->x32;
         j.Xc = r.cols->x32;
         j.Vc = (const float*)vp;

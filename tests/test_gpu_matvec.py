@@ -2,6 +2,11 @@
 oracle, element by element, with tolerances derived from the arithmetic:
 
 * FP64 tiles: |W - W_ref| <= 1e-13 * sum_j |K_ij| |V_jc| + 1e-300.
+* FP32 Laplace tiles sum |q_x - q_y| exactly over coordinates quantised to
+  qbits = min(30, 32 - ceil(log2 dpad)) bits on the common range of both
+  point sets, so each entry's exponent is off by at most
+  dpad * range / ((2^qbits - 1) sigma) plus FP32 rounding of the sum, scale
+  and exp (test_laplace_quantised_wide_range checks this bound directly).
 * FP32 tiles: entries carry a relative error of about
   |arg| (d + 2) 2^-24 + 2 ulp(exp) <= 0.37 (d + 2) 6e-8 absolute, V is rounded
   to FP32 (6e-8 relative) and at most 256 terms are summed in FP32 before
@@ -203,3 +208,23 @@ def test_mixed_full_size_uniform_sampled_rows():
     scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
     tol = mixed_tol(p.X[rows], p.X, p.sigma)
     assert np.all(np.abs(W[rows] - ref) <= tol * scale), np.max(np.abs(W[rows] - ref) / scale)
+
+
+def test_laplace_quantised_wide_range():
+    # Outliers stretch the quantisation range; the bound scales with it.
+    g = np.random.default_rng(21)
+    d = 20
+    Xr = g.standard_normal((900, d))
+    Xc = g.standard_normal((1500, d))
+    Xc[:3] *= 400.0
+    V = g.standard_normal((1500, 2))
+    sigma = 30.0
+    W = run(1, 1, Xr, Xc, V, sigma)
+    Kb = OK.block(Xr, Xc, 1, sigma)
+    ref = Kb @ V
+    scale = np.abs(Kb) @ np.abs(V)
+    rng_ = max(Xr.max(), Xc.max()) - min(Xr.min(), Xc.min())
+    dpad, qbits = 20, 27
+    delta = dpad * rng_ / ((2 ** qbits - 1) * sigma) + 4 * 2 ** -24
+    tol = delta + 257 * 2 ** -24
+    assert np.all(np.abs(W - ref) <= tol * scale), (np.max(np.abs(W - ref) / scale), tol)
