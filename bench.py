@@ -52,11 +52,12 @@ def parse():
 
 
 def laplace_ops_per_entry(d, m):
-    # The method's work per kernel entry, in VALU lane operations: d
-    # absolute-difference accumulations (|x_l - y_l| + s, a single v_sad_u32
-    # on quantised coordinates), one conversion of the l1 sum, one scale,
-    # one exp, and m multiply-adds against V.
-    return d + 3 + m
+    # The method's VALU work per kernel entry, in FP32 lane-operation slots:
+    # d coordinate differences, d absolute-value accumulations, one scale,
+    # one exp (a quarter-rate transcendental: 4 slots) and m multiply-adds
+    # against V.  The tile may realise a difference plus accumulation in one
+    # integer instruction; the count of the method's work does not change.
+    return 2 * d + 5 + m
 
 
 def run_steps(b, torch, p, X, Y, prec, steps, warmup):

@@ -170,7 +170,13 @@ def c5(a, b, torch, synth):
     from paper_2304_12465_amd.serve import Server, GpuBackend, serve_one_at_a_time, summarize
     stream = synth.c5_stream(count=a.requests)
     be = GpuBackend(b.MIXED, tol=1e-6, max_iter=500)
-    srv = Server(be, hbm_budget=160 << 30, max_active=64)
+
+    def progress(tag):
+        def f(r):
+            print(f"c5 {tag}: request {r.rid} {r.status} latency {r.latency:.2f} s",
+                  file=sys.stderr, flush=True)
+        return f
+    srv = Server(be, hbm_budget=160 << 30, max_active=64, on_finish=progress("batched"))
     t0 = time.perf_counter()
     res = srv.run(stream, synth.c5_problem)
     tmix = time.perf_counter() - t0
@@ -178,7 +184,7 @@ def c5(a, b, torch, synth):
     out = {"batched_mixed": s_mix, "batched_wall_s": tmix}
     if not a.no_baseline:
         be64 = GpuBackend(b.FP64, tol=1e-6, max_iter=500)
-        res64 = serve_one_at_a_time(be64, stream, synth.c5_problem)
+        res64 = serve_one_at_a_time(be64, stream, synth.c5_problem, on_finish=progress("fp64"))
         out["one_at_a_time_fp64"] = summarize(res64)
     _line(value=s_mix["solves_per_s"], unit="solves/s", steps=1, warmup=0,
           ms_per_step=tmix * 1e3, dtype="bf16x3/f32 (Gaussian), f32 (Laplace)",

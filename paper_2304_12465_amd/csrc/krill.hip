@@ -394,7 +394,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     }
   gather_raw<<<(unsigned)ceil_div(k * P.d, 256), 256, 0, s>>>(X, P.d, P.centers, k, w.craw);
   KRR_LAUNCH_CHECK("gather_raw");
-  KRR_TRY(fill_points(P.kind, KRR_FP64, w.craw, nullptr, P.cpts64, s));
+  KRR_TRY(fill_points(P.kind, KRR_FP64, w.craw, shared_params(P.kind, KRR_FP64, P.pts64),
+                      P.cpts64, s));
   if (P.prec != KRR_FP64)
     KRR_TRY(fill_points(P.kind, P.prec, w.craw, shared_params(P.kind, P.prec, P.pts), P.cpts, s));
 

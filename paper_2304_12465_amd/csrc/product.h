@@ -23,6 +23,8 @@ struct PointSet {
   // Laplace tiles under FP32 / MIXED: coordinates quantised to `qbits`-bit
   // unsigned fixed point, q = round((x - lo) S); the l1 sums of a tile are
   // then exact 32-bit integer sums of |q_x - q_y| (one v_sad_u32 each).
+  const double* xc64 = nullptr;   // FP64 Gaussian: centred points n x dpad
+  const double* xn64 = nullptr;   // FP64 Gaussian: ||x - centre||^2
   const uint32_t* xq = nullptr;   // n x dpad
   const double* qp = nullptr;     // [lo, S] (device), shared by rows and columns
   double* qpart = nullptr;        // 256 x 2 partial min/max
@@ -111,6 +113,25 @@ struct MfmaJob {
 int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0,
                  int mc, Arena& scratch, MfmaJob* out, hipStream_t s);
 int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s);
+
+// A prepared FP64 MFMA Gaussian job (product_f64mfma.hip).
+struct F64Job {
+  const double* xc;
+  const double* xn;
+  const double* yc;
+  const double* yn;
+  const double* v;
+  double* part;
+  int64_t nr, nc, per, item0;
+  double s;
+  int nsplit, M, dpad;
+};
+int carve_f64c(int64_t n, int32_t dpad, Arena& arena, PointSet* out);
+int fill_f64c(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
+size_t product_f64mfma_scratch_bytes(int64_t nr, int64_t nc);
+int f64_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
+                Arena& scratch, F64Job* out, hipStream_t s);
+int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s);
 
 // bf16-split MFMA path for Gaussian tiles (product_mfma.hip).
 int carve_mixed(int64_t n, int32_t d, Arena& arena, PointSet* out);

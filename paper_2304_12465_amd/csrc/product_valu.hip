@@ -537,6 +537,7 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
   out->dpad = D;
   if (prec == KRR_FP64) {
     out->x64 = arena.take<double>((size_t)n * D);
+    if (kind == KRR_GAUSSIAN) KRR_TRY(carve_f64c(n, D, arena, out));
     return KRR_OK;
   }
   out->x32 = arena.take<float>((size_t)n * D);
@@ -551,8 +552,8 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
 }
 
 const double* shared_params(krr_kernel_kind kind, krr_precision prec, const PointSet& ps) {
-  if (prec == KRR_FP64) return nullptr;
-  return kind == KRR_LAPLACE ? ps.qp : ps.centre;
+  if (kind == KRR_LAPLACE) return prec == KRR_FP64 ? nullptr : ps.qp;
+  return ps.centre;  // Gaussian FP64 (centred MFMA layout) and MIXED
 }
 
 int quant_params(const double* X1, int64_t n1, const double* X2, int64_t n2, int32_t d,
@@ -585,6 +586,7 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     pack_pts<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr,
                                                                    const_cast<double*>(ps.x64));
     KRR_LAUNCH_CHECK("pack_pts<double>");
+    if (kind == KRR_GAUSSIAN) return fill_f64c(X, shared, ps, s);
     return KRR_OK;
   }
   if (!ps.x32) {
@@ -635,6 +637,7 @@ size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t
   a.take<char>((size_t)std::max<int64_t>(nc, 1) * M * es);
   a.take<double>((size_t)ns * std::max<int64_t>(nr, 1) * M);
   if (prec == KRR_MIXED) return std::max(a.used, product_mfma_scratch_bytes(nr, nc));
+  if (prec == KRR_FP64) return std::max(a.used, product_f64mfma_scratch_bytes(nr, nc));
   return a.used;
 }
 
@@ -695,6 +698,7 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       return fams.back();
     };
     std::vector<MfmaJob> mjobs;
+    std::vector<F64Job> fjobs;
     std::vector<int> mreq;
     struct Pending {
       int q;
@@ -712,6 +716,13 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       Arena& sc = *r.scratch;
       sc.used = marks[q];
       const int mc = std::min(16, r.m - c0);
+      if (r.prec == KRR_FP64 && r.kind == KRR_GAUSSIAN) {
+        F64Job fj;
+        KRR_TRY(f64_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &fj, s));
+        pend.push_back(Pending{q, fj.part, nc > 0 ? fj.nsplit : 0, 16, mc, true});
+        if (nc > 0) fjobs.push_back(fj);
+        continue;
+      }
       if (r.prec == KRR_MIXED && r.kind == KRR_GAUSSIAN) {
         MfmaJob mj;
         KRR_TRY(mfma_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &mj, s));
@@ -791,6 +802,7 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       else KRR_TRY(launch_jobs<float>(f.fn, f.j32, f.R, s));
     }
     if (!mjobs.empty()) KRR_TRY(mfma_launch(mjobs, s));
+    if (!fjobs.empty()) KRR_TRY(f64_launch(fjobs, s));
     for (const Pending& pd : pend) {
       const ProductReq& r = reqs[pd.q];
       const int64_t nr = r.rows->n;

@@ -58,6 +58,11 @@ class GpuBackend:
         ws = self.b.rpchol_ws(prob.kind, self.prec, N, d, prob.rank, 0, m)
         return ws + 8 * N * (d + 2 * m) + 4096
 
+    def cost(self, prob):
+        """Work estimate for shortest-first admission: one product."""
+        N, d = prob.X.shape
+        return float(N) * N * (d + prob.Y.shape[1])
+
     def start(self, prob):
         t = lambda a: self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
         X, Y = t(prob.X), t(prob.Y)
@@ -81,12 +86,16 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, hbm_budget, max_active=64, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 sleep=time.sleep, on_finish=None, order="fifo"):
+        """order: "fifo" admits in arrival order; "sjf" admits the waiting
+        request with the smallest estimated work (backend.cost) first."""
         self.be = backend
         self.budget = hbm_budget
         self.max_active = max_active
+        self.order = order
         self.clock = clock
         self.sleep = sleep
+        self.on_finish = on_finish  # called with each finished Result
 
     def run(self, stream, make_problem):
         """Serves ``stream`` (objects with .rid and .arrival in seconds);
@@ -104,7 +113,10 @@ class Server:
                 req = pending.popleft()
                 problems[req.rid] = make_problem(req)
                 waiting.append(req)
-            # admission: FIFO by arrival while the footprint fits
+            # admission while the footprint fits: arrival order, or smallest
+            # estimated work first
+            if self.order == "sjf" and len(waiting) > 1:
+                waiting = deque(sorted(waiting, key=lambda q: self.be.cost(problems[q.rid])))
             while waiting and len(active) < self.max_active:
                 req = waiting[0]
                 prob = problems[req.rid]
@@ -157,12 +169,14 @@ class Server:
                 r.finished = self.clock() - t0
                 used -= need
                 problems.pop(req.rid, None)
+                if self.on_finish:
+                    self.on_finish(r)
             active = keep
         return results
 
 
 def serve_one_at_a_time(backend, stream, make_problem, clock=time.perf_counter,
-                        sleep=time.sleep):
+                        sleep=time.sleep, on_finish=None):
     """Baseline: the same arrival trace served one request at a time (FIFO)."""
     results = {}
     t0 = clock()
@@ -190,6 +204,8 @@ def serve_one_at_a_time(backend, stream, make_problem, clock=time.perf_counter,
             r.status, r.error = "failed", str(e)
         r.finished = clock() - t0
         results[req.rid] = r
+        if on_finish:
+            on_finish(r)
     return results
 
 

@@ -1,0 +1,105 @@
+"""The oracle's pins catch plausible mistakes: each test plants one mistake
+in the oracle (a dropped term, a wrong sign or index, a transposed operand,
+a wrong constant) and checks that the pin it should trip fails."""
+import numpy as np
+import pytest
+
+import oracle.kernels as K
+import oracle.rpcholesky as RP
+import oracle.pcg as PCG
+import oracle.krill as KR
+from oracle import direct
+import tests.test_oracle_kernels as TK
+import tests.test_oracle_rpcholesky as TR
+import tests.test_oracle_pcg as TP
+import tests.test_oracle_krill as TKR
+
+
+def must_fail(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_gaussian_bandwidth_mistake_is_caught(monkeypatch):
+    orig = K.block
+
+    def bad(Xr, Xc, kind, sigma):  # sigma^2 instead of 2 sigma^2
+        if kind == K.GAUSSIAN:
+            return orig(Xr, Xc, kind, sigma / np.sqrt(2.0))
+        return orig(Xr, Xc, kind, sigma)
+    monkeypatch.setattr(K, "block", bad)
+    must_fail(TK.test_block_matches_brute_force, K.GAUSSIAN)
+
+
+def test_laplace_squared_distance_mistake_is_caught(monkeypatch):
+    orig = K.block
+
+    def bad(Xr, Xc, kind, sigma):  # l2 instead of l1
+        if kind == K.LAPLACE:
+            d2 = -2 * sigma * sigma * np.log(orig(Xr, Xc, K.GAUSSIAN, sigma))
+            return np.exp(-np.sqrt(np.maximum(d2, 0)) / sigma)
+        return orig(Xr, Xc, kind, sigma)
+    monkeypatch.setattr(K, "block", bad)
+    must_fail(TK.test_separable_product_form, K.LAPLACE)
+
+
+def test_wrong_factor_update_is_caught(monkeypatch):
+    orig = RP.rpcholesky
+
+    def bad_rpchol(X, kind, sigma, r, B=None, seed=0, record=None):
+        F, piv = orig(X, kind, sigma, r, B, seed, record)
+        F[:, 1:] *= 1.01  # later columns updated wrongly
+        return F, piv
+    monkeypatch.setattr(RP, "rpcholesky", bad_rpchol)
+    must_fail(TR.test_nystrom_identity_psd_residual_and_monotone_trace, K.GAUSSIAN)
+
+
+def test_off_by_one_sampler_is_caught(monkeypatch):
+    orig = RP.sample_index
+
+    def bad(d, O, u):  # returns the neighbour of the correct index
+        i = orig(d, O, u)
+        return min(i + 1, len(d) - 1)
+    monkeypatch.setattr(RP, "sample_index", bad)
+    must_fail(TR.test_sampler_distribution_is_proportional_to_d)
+
+
+def test_transposed_triangular_solve_is_caught(monkeypatch):
+    def bad_apply(self, Z):
+        Z = np.asarray(Z, dtype=np.float64)
+        squeeze = Z.ndim == 1
+        Z2 = Z[:, None] if squeeze else Z
+        coef = 1.0 / (self.s2 + self.mu) + 1.0 / self.mu  # wrong sign
+        out = self.U @ (coef[:, None] * (self.U.T @ Z2)) + Z2 / self.mu
+        return out[:, 0] if squeeze else out
+    monkeypatch.setattr(RP.NystromPreconditioner, "apply", bad_apply)
+    must_fail(TR.test_preconditioner_forms_agree_and_bounds_hold)
+
+
+def test_wrong_pcg_sign_is_caught(monkeypatch):
+    orig = PCG.pcg
+
+    def bad(product, precond, b, tol, max_iter, history=None):
+        x, info = orig(product, precond, b, tol, max_iter, history)
+        return -x, info
+    monkeypatch.setattr(PCG, "pcg", bad)
+    must_fail(TP.test_rpcholesky_pcg_matches_dense_cholesky_solve)
+
+
+def test_missing_krill_shift_or_transposed_sketch_is_caught(monkeypatch):
+    orig_init = KR.Krill.__init__
+
+    def bad_init(self, *a, **kw):
+        orig_init(self, *a, **kw)
+        self.AnS = self.AnS + 1e-3  # a wrong A(:,S) in the product
+    monkeypatch.setattr(KR.Krill, "__init__", bad_init)
+    must_fail(TKR.test_all_points_as_centres_reduce_to_full_data_krr)
+
+
+def test_wrong_sketch_scale_is_caught(monkeypatch):
+    orig = KR.sketch_matrix
+
+    def bad(N, d_rows, zeta, seed):
+        return orig(N, d_rows, zeta, seed) * np.sqrt(zeta)  # forgot zeta^{-1/2}
+    monkeypatch.setattr(KR, "sketch_matrix", bad)
+    must_fail(TKR.test_sketch_structure)

@@ -35,6 +35,9 @@ class FakeBackend:
     def footprint(self, prob):
         return prob["fp"]
 
+    def cost(self, prob):
+        return prob["steps"]
+
     def start(self, prob):
         if prob.get("fail") == "build":
             raise RuntimeError("injected build failure")
@@ -62,11 +65,11 @@ class FakeBackend:
         self.used -= h["p"]["fp"]
 
 
-def run(problems, arrivals, budget, max_active=64):
+def run(problems, arrivals, budget, max_active=64, order="fifo"):
     clk = FakeClock()
     be = FakeBackend(clk)
     reqs = [Req(i, a) for i, a in enumerate(arrivals)]
-    srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep)
+    srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep, order=order)
     res = srv.run(reqs, lambda r: dict(problems[r.rid], rid=r.rid))
     return res, be
 
@@ -125,3 +128,12 @@ def test_one_at_a_time_baseline():
                               sleep=clk.sleep)
     lat = sorted(r.latency for r in res.values())
     assert lat == sorted(lat) and lat[-1] > lat[0]
+
+
+def test_shortest_first_admission_lowers_mean_latency():
+    probs = [dict(fp=10, steps=s) for s in (40, 30, 2, 3, 1, 2)]
+    fifo, _ = run(probs, [0.0] * 6, budget=1000, max_active=1)
+    sjf, be = run(probs, [0.0] * 6, budget=1000, max_active=1, order="sjf")
+    mean = lambda res: sum(r.latency for r in res.values()) / len(res)
+    assert mean(sjf) < mean(fifo)
+    assert be.started[:2] == [4, 2]  # smallest work first
