@@ -17,6 +17,7 @@ on a row sample on the host.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +30,26 @@ METRIC = ("kernel entries/s in fused matvec; time-to-1e-6 PCG solve; "
 # i.e. 78.6e12 lane operations per second (256 CUs x 2.4 GHz x 128).
 VALU_F32_PEAK_TOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 FETCH_SIZE / WRITE_SIZE readings of the headline tile, scaled by
+# the readings for a plain device copy of known size.  They describe the tile
+# built from the source whose SHA-256 the file records; for any other source
+# the traffic is reported as null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_lapq_n100k_d20_hbm_traffic.md")
+TILE_SOURCE = os.path.join(ROOT, "paper_2304_12465_amd", "csrc", "product_valu.hip")
+
+
+def measured_traffic():
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^- (\w+): (\S+)$", text, re.M))
+    with open(TILE_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -158,7 +179,8 @@ def main():
     achieved = ops * N * N / (fp32_launch_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_F32_PEAK_TOPS,
                 "unit": "TOP/s", "frac": round(achieved / VALU_F32_PEAK_TOPS, 4),
-                "traffic": None, "kernel": "tile_lapq<d=20, m=1> (quantised l1, FP32 exp)",
+                "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                "kernel": "tile_lapq<d=20, m=1> (quantised l1, FP32 exp)",
                 "ops_per_entry": ops, "launch_ms": round(fp32_launch_ms, 4),
                 "entries_per_launch": N * N}
 
@@ -198,7 +220,7 @@ def main():
 
     if not a.no_cpu:
         from oracle import kernels as OK
-        rows = 1024
+        rows = 3072  # about 12 s of one host core
         cores = 1  # numpy elementwise kernels of the oracle run on one thread
         Vh = np.random.default_rng(0).standard_normal((N, 1))
         t0 = time.perf_counter()

@@ -84,6 +84,10 @@ def c3(a, b, torch, synth):
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
     m = p.Y.shape[1]
+    if a.product_only:
+        ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)
+        print(json.dumps({"product_ms": ms, "entries_per_launch": N * N}), flush=True)
+        return
     ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)
     rate = N * N / (ms * 1e-3)
     # executed MFMA work per entry: 3 split products of K=32 for the distance
