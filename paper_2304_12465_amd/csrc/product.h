@@ -1,9 +1,28 @@
 // Internal interface of the matrix-free kernel product engine.
 #pragma once
+#include <algorithm>
 #include <vector>
 #include "common.h"
 
 namespace krr {
+
+// Work items of a product are (row group, column split) pairs of equal
+// size, dealt to the resident workgroups of 256 CUs.  About 10,240 items
+// (some 40 per CU) keep the imbalance of the last round within a few
+// percent.  A split count of 8 or more is a multiple of 8, so the items of
+// one split share an XCD (workgroup id mod 8) when the grid covers them.
+inline int64_t split_count(int64_t nr, int64_t nc, int64_t rows_per_wg, int64_t min_cols) {
+  constexpr int64_t kTargetItems = 10240;
+  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
+  int64_t ns = (kTargetItems + rg / 2) / rg;
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / min_cols));
+  if (ns >= 8) ns = ns / 8 * 8;
+  return std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+}
+
+// Largest grid of a product launch (items beyond it are taken by a
+// grid-stride loop).
+constexpr int64_t kGridCap = 65536;
 
 // A point set in the compute layout of one precision: n x dpad, zero padded
 // from d to dpad (zero coordinates add nothing to either distance).

@@ -169,12 +169,7 @@ struct FSplit {
 };
 
 FSplit f64_split(int64_t nr, int64_t nc) {
-  const int64_t rows_per_wg = 4 * 16 * kRT64;
-  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
-  int64_t ns = ceil_div(2048, rg);
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / 256));
-  if (ns >= 8) ns = ns / 8 * 8;
-  ns = std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+  const int64_t ns = split_count(nr, nc, 4 * 16 * kRT64, 256);
   int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
   per = ceil_div(per, kCols64) * kCols64;
   return {(int)ns, per};
@@ -271,7 +266,7 @@ int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s) {
       tab.njobs = nj;
       tab.total = total;
       if (total == 0) continue;
-      const unsigned grid = (unsigned)std::min<int64_t>(total, 8192);
+      const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
       void* tok = tile_timer_start(s);
       switch (D) {
         case 4: tile_f64_gauss<4><<<grid, 256, 0, s>>>(tab); break;

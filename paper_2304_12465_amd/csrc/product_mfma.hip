@@ -46,6 +46,62 @@ __device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
 // lane group g holds column (v < 4 ? 4g + v : 16 + 4g + v - 4) of the chunk.
 __device__ __forceinline__ int slot_col(int g, int v) { return v < 4 ? 4 * g + v : 16 + 4 * g + (v - 4); }
 
+// Per-thread staging of one 64-column chunk: the next chunk's points, its
+// -s ||y||^2 and its V tile are loaded into registers while the current
+// chunk is computed, and written to LDS after the next barrier.
+template <int KP>
+struct Stage {
+  static constexpr int kSeg = KP / 32;  // 16-byte point segments per thread and array
+  bf16x8 yh[kSeg], yl[kSeg];
+  bf16x8 v;    // one 16-byte V segment (hi for threads 0..127, lo for 128..255)
+  float ay;    // threads 0..63
+};
+
+template <int KP>
+__device__ __forceinline__ void stage_fetch(const MfmaJob& J, int64_t jb, int64_t j1, int tid,
+                                            Stage<KP>& st) {
+  constexpr int SPR = KP / 8;  // segments per column
+#pragma unroll
+  for (int q = 0; q < Stage<KP>::kSeg; ++q) {
+    const int e = tid + q * 256;
+    const int jj = e / SPR, seg = e % SPR;
+    if (jb + jj < j1) {
+      st.yh[q] = *reinterpret_cast<const bf16x8*>(J.yhi + (jb + jj) * KP + seg * 8);
+      st.yl[q] = *reinterpret_cast<const bf16x8*>(J.ylo + (jb + jj) * KP + seg * 8);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        st.yh[q][k] = to_bf16(0.f);
+        st.yl[q][k] = to_bf16(0.f);
+      }
+    }
+  }
+  // V is stored pre-permuted in 32-column groups of 16 x 32 slots, zero
+  // padded to whole 64-column chunks: a chunk is 2 x 512 contiguous values
+  const uint16_t* vsrc = tid < 128 ? J.vh : J.vl;
+  st.v = *reinterpret_cast<const bf16x8*>(vsrc + jb * 16 + (tid & 127) * 8);
+  // columns past the range get a huge distance: exp -> 0
+  if (tid < kCols) st.ay = (jb + tid < j1) ? -J.s * J.yn[jb + tid] : -3.0e38f;
+}
+
+template <int KP>
+__device__ __forceinline__ void stage_store(const Stage<KP>& st, int tid, __bf16 (*sYh)[KP + 8],
+                                            __bf16 (*sYl)[KP + 8], float* sAy,
+                                            __bf16 (*sVh)[16][40], __bf16 (*sVl)[16][40]) {
+  constexpr int SPR = KP / 8;
+#pragma unroll
+  for (int q = 0; q < Stage<KP>::kSeg; ++q) {
+    const int e = tid + q * 256;
+    const int jj = e / SPR, seg = e % SPR;
+    *reinterpret_cast<bf16x8*>(&sYh[jj][seg * 8]) = st.yh[q];
+    *reinterpret_cast<bf16x8*>(&sYl[jj][seg * 8]) = st.yl[q];
+  }
+  const int vs = tid & 127;  // (group, rhs, 8-slot segment)
+  __bf16(*dst)[16][40] = tid < 128 ? sVh : sVl;
+  *reinterpret_cast<bf16x8*>(&dst[vs >> 6][(vs >> 2) & 15][(vs & 3) * 8]) = st.v;
+  if (tid < kCols) sAy[tid] = st.ay;
+}
+
 template <int KP>
 __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int split) {
   const uint16_t* __restrict__ Xhi = J.xhi;
@@ -54,7 +110,6 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
   const int64_t nr = J.nr;
   const int64_t nc = J.nc;
   const float s = J.s;
-  const int M = J.M;
   constexpr int KS = KP / 32;       // MFMA K steps of the distance contraction
   constexpr int YP = KP + 8;        // LDS row pitch (bf16) of the column points
   constexpr int NG = kCols / 32;    // 32-column groups per chunk (V-reduction K)
@@ -63,6 +118,9 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
   __shared__ __attribute__((aligned(16))) float sAy[kCols];
   __shared__ __attribute__((aligned(16))) __bf16 sVh[NG][16][32 + 8];  // [group][c][slot]
   __shared__ __attribute__((aligned(16))) __bf16 sVl[NG][16][32 + 8];
+  // FP64 running sums of each lane's outputs (each lane touches only its own
+  // entries, so no barrier is involved)
+  __shared__ double sAcc[4][kRT * 4][64];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -88,60 +146,25 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
     cinit[rt] = f32x4{h, h, h, h};
   }
   f32x4 acc[kRT];
-  double acc64[kRT][4];
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
     acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc64[rt][u] = 0.0;
+    for (int u = 0; u < 4; ++u) sAcc[wave][rt * 4 + u][lane] = 0.0;
   }
   const float s2 = 2.0f * s;
 
   const int64_t j0 = (int64_t)split * J.per;
   int64_t j1 = j0 + J.per;
   if (j1 > nc) j1 = nc;
+  Stage<KP> st;
+  if (j0 < j1) stage_fetch<KP>(J, j0, j1, tid, st);
   int chunk = 0;
   for (int64_t jb = j0; jb < j1; jb += kCols, ++chunk) {
-    const int ncol = (int)((j1 - jb < kCols) ? j1 - jb : kCols);
-    const uint16_t* __restrict__ yhb = J.yhi + jb * KP;
-    const uint16_t* __restrict__ ylb = J.ylo + jb * KP;
-    const uint16_t* __restrict__ vhb = J.vh + jb * 16;
-    const uint16_t* __restrict__ vlb = J.vl + jb * 16;
+    __syncthreads();  // the previous chunk's LDS reads are done
+    stage_store<KP>(st, tid, sYh, sYl, sAy, sVh, sVl);
     __syncthreads();
-    // stage the chunk: points (hi/lo), -s ||y||^2, V (hi/lo, K-permuted)
-    for (int e = tid; e < kCols * (KP / 8); e += 256) {
-      const int jj = e / (KP / 8), seg = e % (KP / 8);
-      bf16x8 h, l;
-      if (jj < ncol) {
-        h = *reinterpret_cast<const bf16x8*>(yhb + jj * KP + seg * 8);
-        l = *reinterpret_cast<const bf16x8*>(ylb + jj * KP + seg * 8);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          h[q] = to_bf16(0.f);
-          l[q] = to_bf16(0.f);
-        }
-      }
-      *reinterpret_cast<bf16x8*>(&sYh[jj][seg * 8]) = h;
-      *reinterpret_cast<bf16x8*>(&sYl[jj][seg * 8]) = l;
-    }
-    if (tid < kCols) {
-      // columns past the range get a huge distance: exp -> 0
-      sAy[tid] = (tid < ncol) ? -s * J.yn[jb + tid] : -3.0e38f;
-    }
-    for (int e = tid; e < NG * 16 * 32; e += 256) {
-      const int gi = e / 512, r = e % 512;
-      const int c = r / 32, slot = r % 32;
-      const int col = gi * 32 + slot_col(slot / 8, slot % 8);
-      uint16_t vh = 0, vl = 0;
-      if (col < ncol && c < M) {
-        vh = vhb[col * 16 + c];
-        vl = vlb[col * 16 + c];
-      }
-      sVh[gi][c][slot] = __builtin_bit_cast(__bf16, vh);
-      sVl[gi][c][slot] = __builtin_bit_cast(__bf16, vl);
-    }
-    __syncthreads();
+    if (jb + kCols < j1) stage_fetch<KP>(J, jb + kCols, j1, tid, st);
     if (row0 >= nr) continue;  // idle wave still joins the barriers
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
@@ -161,24 +184,37 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
         for (int u = 0; u < 4; ++u) ay[ct][u] = sAy[gi * 32 + ct * 16 + 4 * g + u];
       const bf16x8 vh = *reinterpret_cast<const bf16x8*>(&sVh[gi][li][g * 8]);
       const bf16x8 vl = *reinterpret_cast<const bf16x8*>(&sVl[gi][li][g * 8]);
+      // Software pipeline over the row tiles: the distance MFMAs of tile
+      // rt + 1 are independent of the exp / split VALU work of tile rt, so
+      // the two overlap.
+      f32x4 dot[2][2];  // [row tile parity][column tile]
+      auto distance = [&](int rt, f32x4* d) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          f32x4 t = cinit[rt];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xh[rt][ks], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xl[rt][ks], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[ct][ks], xh[rt][ks], t, 0, 0, 0);
+          }
+          d[ct] = t;
+        }
+      };
+      distance(0, dot[0]);
 #pragma unroll
       for (int rt = 0; rt < kRT; ++rt) {
+        if (rt + 1 < kRT) distance(rt + 1, dot[(rt + 1) & 1]);
         uint32_t eh[4], el[4];  // 8 bf16 each: K slots 8g .. 8g+7
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          f32x4 dot = cinit[rt];
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xh[rt][ks], dot, 0, 0, 0);
-            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[ct][ks], xl[rt][ks], dot, 0, 0, 0);
-            dot = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[ct][ks], xh[rt][ks], dot, 0, 0, 0);
-          }
           // dot[u] = y_{4g+u} . x_{li} - ||x_{li}||^2 / 2; the exponent is left
           // unclamped: rounding can make it ~1e-6 positive, within the
           // split's error budget.
+          const f32x4 dd = dot[rt & 1][ct];
           float e[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) e[u] = __builtin_amdgcn_exp2f(__builtin_fmaf(dot[u], s2, ay[ct][u]));
+          for (int u = 0; u < 4; ++u) e[u] = __builtin_amdgcn_exp2f(__builtin_fmaf(dd[u], s2, ay[ct][u]));
           split_pair(e[0], e[1], eh[ct * 2 + 0], el[ct * 2 + 0]);
           split_pair(e[2], e[3], eh[ct * 2 + 1], el[ct * 2 + 1]);
         }
@@ -194,7 +230,7 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
 #pragma unroll
       for (int rt = 0; rt < kRT; ++rt) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc64[rt][u] += (double)acc[rt][u];
+        for (int u = 0; u < 4; ++u) sAcc[wave][rt * 4 + u][lane] += (double)acc[rt][u];
         acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
     }
@@ -207,7 +243,8 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
     for (int u = 0; u < 4; ++u) {
       // E.V output: lane l holds W[i0 + 4g + u][c = li]
       const int64_t i = row0 + rt * 16 + 4 * g + u;
-      if (i < nr && li < M) out[i * 16 + li] = acc64[rt][u] + (double)acc[rt][u];
+      if (i < nr && li < J.M)
+        out[i * 16 + li] = sAcc[wave][rt * 4 + u][lane] + (double)acc[rt][u];
     }
   }
 }
@@ -220,7 +257,8 @@ struct MJobTable {
 };
 
 template <int KP>
-__global__ __launch_bounds__(256) void tile_mfma_gauss(const MJobTable tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 32 ? 3 : 2)))
+void tile_mfma_gauss(const MJobTable tab) {
   for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
@@ -287,16 +325,21 @@ __global__ void pack_norms(const double* __restrict__ X, int64_t n, int d,
   nrm[i] = (float)s;
 }
 
-// V (n x m, strided) -> hi/lo bf16, n x 16, columns c0 .. c0+mc, zero padded
-__global__ void pack_vsplit(VecView V, int64_t n, int c0, int mc, uint16_t* __restrict__ hi,
-                            uint16_t* __restrict__ lo) {
+// V (n x m, strided) -> hi/lo bf16 in the V-reduction MFMA's operand order:
+// 32-column groups of 16 rhs x 32 K slots, slot (8g + v) holding column
+// slot_col(g, v) of the group; columns c0 .. c0+mc, zero padded to 16 rhs
+// and to whole 64-column chunks (npad = 64 ceil(n / 64)).
+__global__ void pack_vsplit(VecView V, int64_t n, int64_t npad, int c0, int mc,
+                            uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * 16) return;
-  const int64_t j = t / 16;
-  const int c = (int)(t % 16);
+  if (t >= npad * 16) return;
+  const int64_t q = t / 512;
+  const int r = (int)(t % 512);
+  const int c = r / 32, slot = r % 32;
+  const int64_t j = q * 32 + slot_col(slot / 8, slot % 8);
   float v = 0.f;
   double vd = 0.0;
-  if (c < mc) {
+  if (j < n && c < mc) {
     vd = V.p[j * V.rs + (int64_t)(c0 + c) * V.cs];
     v = (float)vd;
   }
@@ -312,12 +355,7 @@ struct MSplit {
 };
 
 MSplit mfma_split(int64_t nr, int64_t nc) {
-  const int64_t rows_per_wg = 4 * 16 * kRT;
-  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
-  int64_t ns = ceil_div(2048, rg);
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / 256));
-  if (ns >= 8) ns = ns / 8 * 8;
-  ns = std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+  const int64_t ns = split_count(nr, nc, 4 * 16 * kRT, 256);
   int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
   per = ceil_div(per, kCols) * kCols;  // whole chunks per split
   return {(int)ns, per};
@@ -376,8 +414,9 @@ int fill_mixed(const double* X, const double* centre, const PointSet& ps, hipStr
 size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc) {
   MSplit sp = mfma_split(nr, nc);
   Arena a;
-  a.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
-  a.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  const int64_t npad = ceil_div(std::max<int64_t>(nc, 1), kCols) * kCols;
+  a.take<uint16_t>((size_t)npad * 16);
+  a.take<uint16_t>((size_t)npad * 16);
   a.take<double>((size_t)sp.nsplit * std::max<int64_t>(nr, 1) * 16);
   return a.used;
 }
@@ -390,15 +429,16 @@ int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVi
     return KRR_EINVAL;
   }
   MSplit sp = mfma_split(nr, nc);
-  uint16_t* vh = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
-  uint16_t* vl = scratch.take<uint16_t>((size_t)std::max<int64_t>(nc, 1) * 16);
+  const int64_t npad = ceil_div(std::max<int64_t>(nc, 1), kCols) * kCols;
+  uint16_t* vh = scratch.take<uint16_t>((size_t)npad * 16);
+  uint16_t* vl = scratch.take<uint16_t>((size_t)npad * 16);
   double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
   if (!scratch.ok()) {
     set_error("MIXED product scratch too small");
     return KRR_EWORKSPACE;
   }
   if (nc > 0) {
-    pack_vsplit<<<(unsigned)ceil_div(nc * 16, 256), 256, 0, s>>>(V, nc, c0, mc, vh, vl);
+    pack_vsplit<<<(unsigned)ceil_div(npad * 16, 256), 256, 0, s>>>(V, nc, npad, c0, mc, vh, vl);
     KRR_LAUNCH_CHECK("pack_vsplit");
   }
   MfmaJob& j = *out;
@@ -439,7 +479,7 @@ int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s) {
       tab.njobs = nj;
       tab.total = total;
       if (total == 0) continue;
-      const unsigned grid = (unsigned)std::min<int64_t>(total, 8192);
+      const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
       void* tok = tile_timer_start(s);
       if (kp == 32) tile_mfma_gauss<32><<<grid, 256, 0, s>>>(tab);
       else tile_mfma_gauss<64><<<grid, 256, 0, s>>>(tab);

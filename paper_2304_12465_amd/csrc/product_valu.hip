@@ -425,12 +425,7 @@ struct Split {
 };
 
 Split choose_split(int64_t nr, int64_t nc, int R) {
-  const int64_t rows_per_wg = (int64_t)kWaves * 64 * R;
-  const int64_t rg = std::max<int64_t>(1, ceil_div(nr, rows_per_wg));
-  int64_t ns = ceil_div(2048, rg);
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nc / 128));
-  if (ns >= 8) ns = ns / 8 * 8;  // keep a split on one XCD: wg id % 8 == split % 8
-  ns = std::max<int64_t>(1, std::min<int64_t>(ns, 4096));
+  const int64_t ns = split_count(nr, nc, (int64_t)kWaves * 64 * R, 128);
   return {(int)ns, ceil_div(std::max<int64_t>(nc, 1), ns)};
 }
 
@@ -665,7 +660,7 @@ int launch_jobs(void* fn, const std::vector<TileJob<T>>& jobs, int R, hipStream_
     tab.njobs = nj;
     tab.total = total;
     if (total == 0) continue;
-    const unsigned grid = (unsigned)std::min<int64_t>(total, 8192);
+    const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
     void* tok = tile_timer_start(s);
     reinterpret_cast<TileFn<T>>(fn)<<<grid, 256, 0, s>>>(tab);
     KRR_LAUNCH_CHECK("tile_valu");
