@@ -1,0 +1,42 @@
+// FP64 exp for the kernel tiles: table-driven argument reduction after
+// P. T. P. Tang, "Table-driven implementation of the exponential function in
+// IEEE floating-point arithmetic", ACM TOMS 15(2), 1989.
+//
+// x = (64 m + j) ln2/64 + r with |r| <= ln2/128, so exp(x) = 2^m 2^(j/64) e^r.
+// ln2/64 is split in two doubles (the FMA form of the reduction keeps r to a
+// few ulps of r); e^r - 1 is its degree-5 Taylor polynomial, whose truncation
+// error on |r| <= ln2/128 is below 3.6e-17.  2^(j/64) comes from a 64-entry
+// table the calling kernel keeps in LDS (exp64_table_fill).  The result is
+// within about one ulp; x below -745.2 (and -inf) gives 0, NaN gives NaN.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace krr {
+
+constexpr int kExpTable = 64;
+
+// Threads 0..63 of the block fill the table; the caller synchronises.
+__device__ __forceinline__ void exp64_table_fill(double* tab) {
+  if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp2((double)threadIdx.x / kExpTable);
+}
+
+__device__ __forceinline__ double exp64(double x, const double* __restrict__ tab) {
+  constexpr double kInvL = 92.33248261689366;                  // 64 / ln 2
+  constexpr double kL1 = 0x1.62e42fefa39efp-7;                 // ln2/64, leading part
+  constexpr double kL2 = 0x1.abc9e3b39803fp-62;                // ln2/64 - kL1
+  // below -1e4 the result is 0; the clamp keeps the reduction exact for
+  // arbitrarily negative (and -inf) arguments, and passes NaN through
+  x = x < -1.0e4 ? -1.0e4 : x;
+  const double n = __builtin_rint(x * kInvL);
+  double r = __builtin_fma(-n, kL1, x);
+  r = __builtin_fma(-n, kL2, r);
+  const int k = (int)n;
+  const double t = tab[k & (kExpTable - 1)];
+  double p = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = __builtin_fma(r, p, 1.0 / 6.0);
+  p = __builtin_fma(r, p, 0.5);
+  p = __builtin_fma(r * r, p, r);  // e^r - 1
+  return ldexp(__builtin_fma(t, p, t), k >> 6);
+}
+
+}  // namespace krr

@@ -15,6 +15,7 @@
 // into per-row lists sorted by point index, and each B row is a fixed-order
 // signed sum of kernel rows, so the build is bitwise reproducible.
 #include "solver.h"
+#include "exp64.h"
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -211,6 +212,11 @@ __global__ __launch_bounds__(256) void sketch_apply(const T* __restrict__ C, int
                                                     int64_t d_rows, int rows_per_wg, T scale,
                                                     double inv_sqrt_zeta,
                                                     double* __restrict__ Bout) {
+  __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 sketches)
+  if constexpr (sizeof(T) == 8) {
+    exp64_table_fill(etab);
+    __syncthreads();
+  }
   const int lane = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * 256 * R;
   T x[R][D];
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(256) void sketch_apply(const T* __restrict__ C, int
           }
           T ev;
           if constexpr (sizeof(T) == 4) ev = __builtin_amdgcn_exp2f(s0 * scale);
-          else ev = exp(s0 * scale);
+          else ev = exp64(s0 * scale, etab);
           acc[q] += sgn * ev;
         }
       }

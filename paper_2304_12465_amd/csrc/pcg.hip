@@ -18,7 +18,7 @@ namespace krr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxRefine = 4;  // refinement rounds for FP32 / MIXED tiles
+constexpr int kMaxRefine = 6;  // refinement rounds for FP32 / MIXED tiles
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -312,6 +312,7 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
   S.P = &P;
   S.m = m;
   S.tol = tol;
+  S.tol_inner = tol;
   S.max_iter = max_iter;
   S.t0 = std::chrono::steady_clock::now();
   S.iters.assign(m, 0);
@@ -397,7 +398,8 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
             st.x, st.r, st.p, st.w, st.scal, mm, nn, rd.chunk, rd.nblk, st.part);
         rc = hip_check(hipGetLastError(), "update_xr");
         if (rc == KRR_OK) {
-          finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, S.m, mm, kFinRR, S.tol * S.tol, 0, st.scal);
+          finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, S.m, mm, kFinRR, S.tol_inner * S.tol_inner, 0,
+                                    st.scal);
           rc = hip_check(hipGetLastError(), "finalize rr");
         }
       }
@@ -476,10 +478,14 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
         continue;
       }
       ++S.restarts;
+      // a refinement round aims below tol: the lower-precision operator
+      // leaves part of each round's correction in the true residual
+      if (P.prec != KRR_FP64) S.tol_inner = 0.1 * S.tol;
       const int64_t len = st.n * S.m;
       int rc = hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
                          "r = true residual");
-      if (rc == KRR_OK) rc = dot_cols(st, st.r, st.r, S.m, kFinActivate, S.tol * S.tol, 0, s);
+      if (rc == KRR_OK)
+        rc = dot_cols(st, st.r, st.r, S.m, kFinActivate, S.tol_inner * S.tol_inner, 0, s);
       if (rc == KRR_OK) rc = restart_direction(S, s);
       if (rc < 0) {
         fail(S, rc);

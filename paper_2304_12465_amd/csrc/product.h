@@ -44,6 +44,7 @@ struct PointSet {
   // then exact 32-bit integer sums of |q_x - q_y| (one v_sad_u32 each).
   const double* xc64 = nullptr;   // FP64 Gaussian: centred points n x dpad
   const double* xn64 = nullptr;   // FP64 Gaussian: ||x - centre||^2
+  const double* xmax64 = nullptr; // FP64 Gaussian: max ||x - centre||^2 (one device double)
   const uint32_t* xq = nullptr;   // n x dpad
   const double* qp = nullptr;     // [lo, S] (device), shared by rows and columns
   double* qpart = nullptr;        // 256 x 2 partial min/max
@@ -137,6 +138,8 @@ int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s);
 struct F64Job {
   const double* xc;
   const double* xn;
+  const double* xmax;  // max ||x||^2 of the rows / columns (device)
+  const double* ymax;
   const double* yc;
   const double* yn;
   const double* v;

@@ -15,6 +15,7 @@
 //    kernel adds them in a fixed order, so results are bitwise reproducible
 //    and independent of scheduling.
 #include "product.h"
+#include "exp64.h"
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -61,7 +62,8 @@ template <int KIND, typename T, int D, int M, int R>
 __device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
                                           const T* __restrict__ Xc, const T* __restrict__ Vc,
                                           int64_t nc, T scale, int split, int64_t cols_per_split,
-                                          int64_t rg, double* __restrict__ part, int nsplit) {
+                                          int64_t rg, double* __restrict__ part, int nsplit,
+                                          const double* __restrict__ etab) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t row0 = (rg * kWaves + wave) * 64 * R;
@@ -119,7 +121,7 @@ __device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
         }
         T e;
         if constexpr (sizeof(T) == 4) e = __builtin_amdgcn_exp2f((s0 + s1) * scale);
-        else e = exp((s0 + s1) * scale);
+        else e = exp64((s0 + s1) * scale, etab);
 #pragma unroll
         for (int c = 0; c < M; ++c) acc[r][c] = fma_t(e, v[c], acc[r][c]);
       }
@@ -142,6 +144,11 @@ __device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
 
 template <int KIND, typename T, int D, int M, int R>
 __global__ __launch_bounds__(256) void tile_valu(const JobTable<T> tab) {
+  __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 tiles)
+  if constexpr (sizeof(T) == 8) {
+    exp64_table_fill(etab);
+    __syncthreads();
+  }
   for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(256) void tile_valu(const JobTable<T> tab) {
     const int split = (int)(local % J.nsplit);
     const int64_t rg = local / J.nsplit;
     tile_item<KIND, T, D, M, R>(J.Xr, J.nr, J.Xc, J.Vc, J.nc, J.scale, split, J.per, rg, J.part,
-                                J.nsplit);
+                                J.nsplit, etab);
   }
 }
 

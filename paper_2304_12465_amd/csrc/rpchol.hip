@@ -16,6 +16,7 @@
 //    zero and the diagonal is clamped at zero;
 //  * the loop stops early once the residual trace is <= eps * tr(A).
 #include "solver.h"
+#include "exp64.h"
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -101,6 +102,9 @@ __global__ __launch_bounds__(256) void kblock64(const double* __restrict__ A, in
                                                 const double* __restrict__ B, int64_t nb,
                                                 double scale, double* __restrict__ out,
                                                 int64_t ld) {
+  __shared__ double etab[kExpTable];
+  exp64_table_fill(etab);
+  __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t jj = j < nb ? j : nb - 1;
   double y[D];
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void kblock64(const double* __restrict__ A, in
       if (KIND == KRR_LAPLACE) s += __builtin_fabs(t);
       else s = __builtin_fma(t, t, s);
     }
-    if (j < nb) out[q * ld + j] = exp(s * scale);
+    if (j < nb) out[q * ld + j] = exp64(s * scale, etab);
   }
 }
 

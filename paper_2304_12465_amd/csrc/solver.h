@@ -139,6 +139,7 @@ struct Solve {
   Precond* P = nullptr;
   int32_t m = 0;
   double tol = 0.0;
+  double tol_inner = 0.0;  // recursive-residual target of the current PCG run
   int32_t max_iter = 0;
   int it = 0;
   int restarts = 0;

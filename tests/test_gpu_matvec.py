@@ -65,7 +65,7 @@ def test_square_with_shift(kind, prec, d):
     check(kind, prec, X, X, V, sigma=np.sqrt(d) * (1.0 if kind == 0 else 1.5), shift=0.37)
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 8, 16, 17, 40])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 8, 16, 17, 40])
 def test_multiple_rhs(m):
     g = np.random.default_rng(7 + m)
     Xr = g.standard_normal((700, 16))
@@ -74,6 +74,18 @@ def test_multiple_rhs(m):
     for kind in (0, 1):
         for prec in (0, 1):
             check(kind, prec, Xr, Xc, V, sigma=3.0)
+
+
+@pytest.mark.parametrize("sigma", [1e-8, 0.05, 0.4, 3.0, 1e3])
+def test_fp64_gaussian_exponent_range(sigma):
+    # exponents from 0 (coincident points) down past the FP64 underflow
+    # threshold (exp(-745) = 0): covers the table-driven exp's whole range
+    g = np.random.default_rng(11)
+    X = g.standard_normal((900, 6))
+    X[100:150] = X[0]  # duplicates: exponent exactly 0 after centring
+    V = g.standard_normal((900, 3))
+    check(0, 0, X, X, V, sigma=sigma)
+    check(0, 0, X, X, V[:, :1], sigma=sigma, shift=0.5)
 
 
 def test_rectangular_shapes_and_edges():
