@@ -288,6 +288,11 @@ void* sketch_pick(int D) {
 }
 int sketch_rpl(int D) { return D <= 20 ? 2 : 1; }
 
+__global__ void set_identity(double* __restrict__ A, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * n) A[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
 __global__ void scale_add_diag(double* __restrict__ A, int64_t n, double a, double diag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * n) return;
@@ -309,6 +314,7 @@ int krill_layout(Arena& a, Precond& P) {
   P.centers = a.take<int64_t>(k);
   P.H = a.take<double>((size_t)k * k);
   P.C = a.take<double>((size_t)k * k);
+  P.Linv = a.take<double>((size_t)k * k);
   pcg_carve(a, P.pcg, k, P.m_max, N, 0);
   KrillWork& w = P.kw;
   const int64_t nblk = ceil_div(N, kBlk);
@@ -475,6 +481,13 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     set_error("Cholesky of the KRILL matrix failed at column %d", info);
     return KRR_ENOTSPD;
   }
+  // 7. L^{-1} by a blocked forward solve on the identity: each apply of
+  // P^{-1} = L^{-T} L^{-1} is then two dense k x k products streamed from
+  // HBM instead of two sequential triangular solves
+  set_identity<<<(unsigned)ceil_div(k * k, 256), 256, 0, s>>>(P.Linv, k);
+  KRR_LAUNCH_CHECK("set_identity");
+  KRR_TRY(trsm_lower_left(k, k, P.C, k, P.Linv, k, s));
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
   P.build_seconds = std::chrono::duration<double>(clk::now() - t0).count();
   return KRR_OK;
 }

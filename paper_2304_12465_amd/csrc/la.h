@@ -19,13 +19,6 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, hipStream_t s, Arena* scratch = nullptr);
 
-// Triangular solves with a few right-hand sides (B: n x m row-major, ld m),
-// blocked: a small diagonal solve per 64-row block and a right-looking
-// update of the remaining rows spread over many workgroups.
-int trsv_lower(int64_t n, int32_t m, const double* L, int64_t lda, double* B, hipStream_t s);
-int trsv_lower_trans(int64_t n, int32_t m, const double* L, int64_t lda, double* B,
-                     hipStream_t s);
-
 // In-place lower Cholesky of the n x n SPD matrix A (row-major, lda):
 // A = L L^T, L in the lower triangle (the strict upper triangle is left
 // holding values of no meaning).  `info` (device int) receives 0 or the
@@ -36,8 +29,5 @@ int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s);
 // (n x ncols, ldb): B <- L^{-1} B.
 int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
                     int64_t ldb, hipStream_t s);
-// B <- L^{-T} B  (backward substitution with the transpose of L).
-int trsm_lower_left_trans(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
-                          int64_t ldb, hipStream_t s);
 
 }  // namespace krr

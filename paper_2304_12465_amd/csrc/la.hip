@@ -195,9 +195,7 @@ __global__ __launch_bounds__(256) void potrf_panel(double* __restrict__ A, int64
 }
 
 // One block of a lower-triangular solve with many right-hand sides:
-// B_blk <- L_blk^{-1} B_blk (forward) or L_blk^{-T} B_blk (backward),
-// one thread per right-hand-side column.
-template <bool TRANS>
+// B_blk <- L_blk^{-1} B_blk, one thread per right-hand-side column.
 __global__ __launch_bounds__(256) void trsm_diag(const double* __restrict__ L, int64_t lda, int nb,
                                                  double* __restrict__ B, int64_t ldb,
                                                  int64_t ncols) {
@@ -209,74 +207,12 @@ __global__ __launch_bounds__(256) void trsm_diag(const double* __restrict__ L, i
   if (c >= ncols) return;
   double x[kNb];
   for (int q = 0; q < nb; ++q) x[q] = B[q * ldb + c];
-  if (!TRANS) {
-    for (int q = 0; q < nb; ++q) {
-      double s = x[q];
-      for (int p = 0; p < q; ++p) s -= T[q][p] * x[p];
-      x[q] = s / T[q][q];
-    }
-  } else {
-    for (int q = nb - 1; q >= 0; --q) {
-      double s = x[q];
-      for (int p = q + 1; p < nb; ++p) s -= T[p][q] * x[p];
-      x[q] = s / T[q][q];
-    }
+  for (int q = 0; q < nb; ++q) {
+    double s = x[q];
+    for (int p = 0; p < q; ++p) s -= T[q][p] * x[p];
+    x[q] = s / T[q][q];
   }
   for (int q = 0; q < nb; ++q) B[q * ldb + c] = x[q];
-}
-
-// C[M x N] -= A^T-block product for the transposed backward solve:
-// C = C - Lsub^T * X where Lsub is K x M (row-major, lda) and X is K x N.
-__global__ __launch_bounds__(256) void gemm_tn_sub(int64_t M, int64_t N, int64_t K,
-                                                   const double* __restrict__ Lsub, int64_t lda,
-                                                   const double* __restrict__ X, int64_t ldx,
-                                                   double* __restrict__ C, int64_t ldc) {
-  // small-M path used by the backward solve: thread per (m, n)
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M * N) return;
-  const int64_t m = t / N, n = t % N;
-  double s = 0.0;
-  for (int64_t k = 0; k < K; ++k) s += Lsub[k * lda + m] * X[k * ldx + n];
-  C[m * ldc + n] -= s;
-}
-
-
-// Right-looking updates of the blocked triangular solves with m <= 64
-// right-hand sides (B row-major n x m).
-// Forward: rows i >= r0 get B_i -= L[i, k0:k0+nb] Y_blk.
-__global__ __launch_bounds__(256) void trsv_update_below(const double* __restrict__ L, int64_t lda,
-                                                         int64_t k0, int nb, int64_t r0,
-                                                         int64_t n, int m,
-                                                         double* __restrict__ B) {
-  __shared__ double Y[kNb][64];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * m; e += blockDim.x) Y[e / m][e % m] = B[(k0 + e / m) * m + e % m];
-  __syncthreads();
-  const int64_t i = r0 + (int64_t)blockIdx.x * blockDim.x + tid;
-  if (i >= n) return;
-  const double* Li = L + i * lda + k0;
-  for (int c = 0; c < m; ++c) {
-    double s = 0.0;
-    for (int q = 0; q < nb; ++q) s += Li[q] * Y[q][c];
-    B[i * m + c] -= s;
-  }
-}
-
-// Backward (L^T): rows i < k0 get B_i -= sum_q L[k0+q, i] Z_q.
-__global__ __launch_bounds__(256) void trsv_update_above(const double* __restrict__ L, int64_t lda,
-                                                         int64_t k0, int nb, int m,
-                                                         double* __restrict__ B) {
-  __shared__ double Z[kNb][64];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * m; e += blockDim.x) Z[e / m][e % m] = B[(k0 + e / m) * m + e % m];
-  __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
-  if (i >= k0) return;
-  for (int c = 0; c < m; ++c) {
-    double s = 0.0;
-    for (int q = 0; q < nb; ++q) s += L[(k0 + q) * lda + i] * Z[q][c];
-    B[i * m + c] -= s;
-  }
 }
 
 }  // namespace
@@ -373,74 +309,9 @@ int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, doub
       KRR_TRY(gemm_f64(false, nb, ncols, k, -1.0, L + k * lda, lda, B, ldb, 1.0, B + k * ldb, ldb,
                        s));
     }
-    trsm_diag<false><<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
+    trsm_diag<<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
                                                                     B + k * ldb, ldb, ncols);
     KRR_LAUNCH_CHECK("trsm_diag");
-  }
-  return KRR_OK;
-}
-
-int trsm_lower_left_trans(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
-                          int64_t ldb, hipStream_t s) {
-  if (ncols <= 0 || n <= 0) return KRR_OK;
-  const int64_t nblk = ceil_div(n, kNb);
-  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
-    const int64_t k = bk * kNb;
-    const int nb = (int)std::min<int64_t>(kNb, n - k);
-    const int64_t below = n - k - nb;
-    if (below > 0) {
-      // B_k -= L[k+nb:, k:k+nb]^T B[k+nb:]
-      const int64_t tot = (int64_t)nb * ncols;
-      gemm_tn_sub<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(nb, ncols, below,
-                                                              L + (k + nb) * lda + k, lda,
-                                                              B + (k + nb) * ldb, ldb,
-                                                              B + k * ldb, ldb);
-      KRR_LAUNCH_CHECK("gemm_tn_sub");
-    }
-    trsm_diag<true><<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
-                                                                   B + k * ldb, ldb, ncols);
-    KRR_LAUNCH_CHECK("trsm_diag<T>");
-  }
-  return KRR_OK;
-}
-
-
-int trsv_lower(int64_t n, int32_t m, const double* L, int64_t lda, double* B, hipStream_t s) {
-  if (n <= 0 || m <= 0) return KRR_OK;
-  if (m > 64) {
-    set_error("trsv_lower: at most 64 right-hand sides");
-    return KRR_EINVAL;
-  }
-  for (int64_t k = 0; k < n; k += kNb) {
-    const int nb = (int)std::min<int64_t>(kNb, n - k);
-    trsm_diag<false><<<1, 64, 0, s>>>(L + k * lda + k, lda, nb, B + k * m, m, m);
-    KRR_LAUNCH_CHECK("trsv diag");
-    const int64_t rest = n - k - nb;
-    if (rest > 0) {
-      trsv_update_below<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(L, lda, k, nb, k + nb, n, m, B);
-      KRR_LAUNCH_CHECK("trsv_update_below");
-    }
-  }
-  return KRR_OK;
-}
-
-int trsv_lower_trans(int64_t n, int32_t m, const double* L, int64_t lda, double* B,
-                     hipStream_t s) {
-  if (n <= 0 || m <= 0) return KRR_OK;
-  if (m > 64) {
-    set_error("trsv_lower_trans: at most 64 right-hand sides");
-    return KRR_EINVAL;
-  }
-  const int64_t nblk = ceil_div(n, kNb);
-  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
-    const int64_t k = bk * kNb;
-    const int nb = (int)std::min<int64_t>(kNb, n - k);
-    trsm_diag<true><<<1, 64, 0, s>>>(L + k * lda + k, lda, nb, B + k * m, m, m);
-    KRR_LAUNCH_CHECK("trsv diag T");
-    if (k > 0) {
-      trsv_update_above<<<(unsigned)ceil_div(k, 256), 256, 0, s>>>(L, lda, k, nb, m, B);
-      KRR_LAUNCH_CHECK("trsv_update_above");
-    }
   }
   return KRR_OK;
 }

@@ -260,13 +260,12 @@ int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) 
     // Z^T = R^T / mu - (1/mu) T^T Q^T
     return gemm_f64(false, m, N, rk, -imu, TT, rk, P.QT, N, imu, Z.p, N, s, &P.scratch);
   }
-  // KRILL: z = C^{-1} C^{-T} r with P = C^T C, C = L^T (lower L stored).
+  // KRILL: z = C^{-1} C^{-T} r with P = C^T C, C = L^T, i.e. z = L^{-T} (L^{-1} r),
+  // as two products with the stored L^{-1} (vectors column-major: r^T is m x k).
   const int64_t k = P.k;
-  double* tmp = P.pcg.tmpN;  // k x m row-major staging (tmpN holds N >= k rows x m)
-  KRR_TRY(to_rowmajor(R.p, k, m, tmp, s));
-  KRR_TRY(trsv_lower(k, m, P.C, k, tmp, s));        // L^{-1} r
-  KRR_TRY(trsv_lower_trans(k, m, P.C, k, tmp, s));  // L^{-T} (L^{-1} r)
-  return to_colmajor(tmp, k, m, Z.p, s);
+  double* tmp = P.pcg.tmpN;  // m x k (tmpN holds N >= k rows x m)
+  KRR_TRY(gemm_f64(true, m, k, k, 1.0, R.p, k, P.Linv, k, 0.0, tmp, k, s, &P.scratch));  // (L^{-1} r)^T
+  return gemm_f64(false, m, k, k, 1.0, tmp, k, P.Linv, k, 0.0, Z.p, k, s, &P.scratch);
 }
 
 int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s) {

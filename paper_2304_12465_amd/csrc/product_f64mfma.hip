@@ -54,14 +54,15 @@ __device__ __forceinline__ void stage64_fetch(const F64Job& J, int64_t jb, int64
   if (tid < kCols64) st.ay = (jb + tid < j1) ? -J.s * J.yn[jb + tid] : -1.0e300;
 }
 
-// The expansion ||x||^2 + ||y||^2 - 2 x.y carries an absolute error of about
-// (d + 3) eps s (||x||^2 + ||y||^2) into the exponent.  Jobs whose bandwidth
-// is small against the spread of the centred points (s (max ||x||^2 +
-// max ||y||^2) above kDirectBound, i.e. an exponent error that could exceed
-// ~1e-13) take direct differences instead (tile_f64_direct).
-constexpr double kDirectBound = 8.0;
+// The expansion ||x||^2 + ||y||^2 - 2 x.y carries an absolute error of at
+// most about (d + 3) eps s (||x||^2 + ||y||^2) into the exponent, i.e. into
+// the relative error of each entry.  Jobs where that bound (with the largest
+// centred norms of rows and columns) could exceed ~9e-14 -- a bandwidth
+// small against the spread of the points -- take direct differences instead
+// (tile_f64_direct).
+constexpr double kDirectBound = 400.0;  // x eps = 8.9e-14
 __device__ __forceinline__ bool needs_direct(const F64Job& J) {
-  return J.s * (*J.xmax + *J.ymax) > kDirectBound;
+  return J.s * (*J.xmax + *J.ymax) * (J.dpad + 3) > kDirectBound;
 }
 
 template <int D, int MV>

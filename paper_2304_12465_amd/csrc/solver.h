@@ -103,6 +103,7 @@ struct Precond {
   PointSet cpts64, cpts;          // centres in both layouts
   double* H = nullptr;            // k x k: mu A_SS + shift I
   double* C = nullptr;            // k x k: lower Cholesky factor of P = B^T B + H
+  double* Linv = nullptr;         // k x k: L^{-1} (the apply is two dense products)
   std::vector<int64_t> centers_host;
   KrillWork kw;
   // PCG state and scratch
