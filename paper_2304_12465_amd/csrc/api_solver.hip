@@ -50,9 +50,12 @@ int rp_params(Precond& P, krr_kernel_kind kind, krr_precision prec, int64_t N, i
 int finish_carve(Precond& P, void* ws, size_t ws_bytes, size_t need) {
   KRR_TRY(check_ws(ws, ws_bytes, need));
   P.ws_used = need;
-  return hip_check(hipHostMalloc((void**)&P.pcg.host, sizeof(double) * kScalars * P.m_max,
-                                 hipHostMallocDefault),
-                   "pinned host scalars");
+  // one pinned block: the PCG scalar mirror, then the build's staging bytes
+  const size_t scal = align_up(sizeof(double) * kScalars * P.m_max);
+  KRR_TRY(hip_check(hipHostMalloc((void**)&P.pcg.host, scal + kHostStage, hipHostMallocDefault),
+                    "pinned host scalars"));
+  P.rp.hstage = reinterpret_cast<char*>(P.pcg.host) + scal;
+  return KRR_OK;
 }
 
 int valid_precond(krr_precond P) {

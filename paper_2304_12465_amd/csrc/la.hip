@@ -171,27 +171,74 @@ __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ A, int64_
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
-// Rows below the diagonal block: L_i = A_i L_kk^{-T}, one thread per row.
+// A lower-triangular nb x nb block (nb <= kNb) staged in LDS, padded to
+// kNb x kNb with the identity, plus the reciprocals of its diagonal.
+__device__ __forceinline__ void stage_tri(const double* __restrict__ L, int64_t lda, int nb,
+                                          double (*T)[kNb + 1], double* tinv) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kNb * kNb; e += blockDim.x) {
+    const int q = e / kNb, p = e % kNb;
+    T[q][p] = (q < nb && p < nb) ? L[q * lda + p] : (q == p ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tid < kNb) tinv[tid] = 1.0 / T[tid][tid];
+  __syncthreads();
+}
+
+// x <- T^{-1} x by forward substitution, fully unrolled so that x stays in
+// registers; two partial sums per row halve the dependent FMA chain.  The
+// scheduling barriers keep the compiler from hoisting the whole triangle's
+// LDS reads into registers at once.
+__device__ __forceinline__ void tri_forward(const double (*T)[kNb + 1], const double* tinv,
+                                            double (&x)[kNb]) {
+#pragma unroll
+  for (int q = 0; q < kNb; ++q) {
+    double s0 = x[q], s1 = 0.0;
+#pragma unroll
+    for (int p = 0; p + 1 < q; p += 2) {
+      s0 = __builtin_fma(-T[q][p], x[p], s0);
+      s1 = __builtin_fma(-T[q][p + 1], x[p + 1], s1);
+      if ((p & 15) == 14) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (q & 1) s0 = __builtin_fma(-T[q][q - 1], x[q - 1], s0);
+    x[q] = (s0 + s1) * tinv[q];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Branch-free strided access to the nb <= kNb entries of one column: entries
+// q >= nb alias entry nb - 1 (they are loaded, solved against the identity
+// padding and never affect entries < nb).  The store runs from q = kNb - 1
+// down, so entry nb - 1 is written last with its solved value.
+__device__ __forceinline__ void load_col(const double* __restrict__ base, int64_t stride, int nb,
+                                         double (&x)[kNb]) {
+#pragma unroll
+  for (int q = 0; q < kNb; ++q) x[q] = base[(int64_t)(q < nb ? q : nb - 1) * stride];
+}
+__device__ __forceinline__ void store_col(double* __restrict__ base, int64_t stride, int nb,
+                                          const double (&x)[kNb]) {
+  // a fresh copy of the stride: the store addresses are recomputed rather
+  // than kept live across the solve
+  __asm__ volatile("" : "+s"(stride));
+#pragma unroll
+  for (int q = kNb - 1; q >= 0; --q) base[(int64_t)(q < nb ? q : nb - 1) * stride] = x[q];
+}
+
+// Rows below the diagonal block: L_i = A_i L_kk^{-T}, one thread per row
+// (the row solve is a forward substitution with L_kk).
 __global__ __launch_bounds__(256) void potrf_panel(double* __restrict__ A, int64_t lda, int nb,
                                                    int64_t nrows) {
-  __shared__ double L[kNb][kNb + 1];
-  const int tid = threadIdx.x;
+  __shared__ double T[kNb][kNb + 1];
+  __shared__ double tinv[kNb];
   // A points at the diagonal block; panel rows start nb rows below
-  for (int e = tid; e < nb * nb; e += blockDim.x) L[e / nb][e % nb] = A[(e / nb) * lda + e % nb];
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + tid;
+  stage_tri(A, lda, nb, T, tinv);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   double* row = A + (nb + r) * lda;
   double x[kNb];
-#pragma unroll 8
-  for (int q = 0; q < nb; ++q) x[q] = row[q];
-  for (int q = 0; q < nb; ++q) {
-    double s = x[q];
-    for (int p = 0; p < q; ++p) s -= x[p] * L[q][p];
-    x[q] = s / L[q][q];
-  }
-#pragma unroll 8
-  for (int q = 0; q < nb; ++q) row[q] = x[q];
+  load_col(row, 1, nb, x);
+  tri_forward(T, tinv, x);
+  store_col(row, 1, nb, x);
 }
 
 // One block of a lower-triangular solve with many right-hand sides:
@@ -200,19 +247,14 @@ __global__ __launch_bounds__(256) void trsm_diag(const double* __restrict__ L, i
                                                  double* __restrict__ B, int64_t ldb,
                                                  int64_t ncols) {
   __shared__ double T[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = L[(e / nb) * lda + e % nb];
-  __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+  __shared__ double tinv[kNb];
+  stage_tri(L, lda, nb, T, tinv);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
   double x[kNb];
-  for (int q = 0; q < nb; ++q) x[q] = B[q * ldb + c];
-  for (int q = 0; q < nb; ++q) {
-    double s = x[q];
-    for (int p = 0; p < q; ++p) s -= T[q][p] * x[p];
-    x[q] = s / T[q][q];
-  }
-  for (int q = 0; q < nb; ++q) B[q * ldb + c] = x[q];
+  load_col(B + c, ldb, nb, x);
+  tri_forward(T, tinv, x);
+  store_col(B + c, ldb, nb, x);
 }
 
 }  // namespace

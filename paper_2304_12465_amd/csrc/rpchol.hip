@@ -314,30 +314,37 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   P.pivots.clear();
   int64_t i = 0;
   int64_t b = 0;
-  std::vector<int64_t> draws(kBmax), sp;
-  std::vector<int> acc(kBmax);
-  int hbuf[2];
-  double T = 0.0;
+  std::vector<int64_t> sp;
+  // pinned staging: [0, 64) total T, [64, 64 + 8 kBmax) draws, then the
+  // accepted count and list, then the distinct draws for the upload
+  double* hT = reinterpret_cast<double*>(w.hstage);
+  int64_t* hdraws = reinterpret_cast<int64_t*>(w.hstage + 64);
+  int* hints = reinterpret_cast<int*>(w.hstage + 64 + 8 * kBmax);
+  int* hacc = hints + 16;
+  int64_t* hsp = reinterpret_cast<int64_t*>(w.hstage + 128 + 8 * kBmax + 4 * kBmax);
+  static_assert(128 + 8 * kBmax + 4 * kBmax + 8 * kBmax <= kHostStage, "staging bytes");
   while (i < P.r_req && b <= N) {
+    // prefix tables, then the block's draws (they read the total on the
+    // device); one readback of the total and the draws
     chunk_sums<<<(unsigned)ceil_div(nch, 256), 256, 0, s>>>(w.d, N, nch, w.S);
     KRR_LAUNCH_CHECK("chunk_sums");
     chunk_offsets<<<1, 1, 0, s>>>(w.S, nch, w.O);
     KRR_LAUNCH_CHECK("chunk_offsets");
-    KRR_TRY(hip_check(hipMemcpyAsync(&T, w.O + nch, sizeof(double), hipMemcpyDeviceToHost, s), "T"));
-    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
-    if (!(T > thresh)) break;  // residual exhausted (exact recovery)
     const int cnt = (int)std::min<int64_t>(P.B, P.r_req - i);
     draw_pivots<<<(unsigned)ceil_div(cnt, 64), 64, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
                                                            cnt, w.draws);
     KRR_LAUNCH_CHECK("draw_pivots");
-    KRR_TRY(hip_check(hipMemcpyAsync(draws.data(), w.draws, sizeof(int64_t) * cnt,
-                                     hipMemcpyDeviceToHost, s), "draws"));
+    KRR_TRY(hip_check(hipMemcpyAsync(hT, w.O + nch, sizeof(double), hipMemcpyDeviceToHost, s), "T"));
+    KRR_TRY(hip_check(hipMemcpyAsync(hdraws, w.draws, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s),
+                      "draws"));
     KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
-    sp.assign(draws.begin(), draws.begin() + cnt);
+    if (!(*hT > thresh)) break;  // residual exhausted (exact recovery): the draws are unused
+    sp.assign(hdraws, hdraws + cnt);
     std::sort(sp.begin(), sp.end());
     sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
     const int bp = (int)sp.size();
-    KRR_TRY(hip_check(hipMemcpyAsync(w.sp, sp.data(), sizeof(int64_t) * bp, hipMemcpyHostToDevice, s),
+    std::copy(sp.begin(), sp.end(), hsp);
+    KRR_TRY(hip_check(hipMemcpyAsync(w.sp, hsp, sizeof(int64_t) * bp, hipMemcpyHostToDevice, s),
                       "S'"));
     // G^T = A(S', :) - F(S', 1:i) F(:, 1:i)^T
     gather_points<<<(unsigned)ceil_div((int64_t)bp * D, 256), 256, 0, s>>>(P.pts64.x64, D, w.sp, bp,
@@ -357,11 +364,11 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
     }
     chol_drop<<<1, 256, 0, s>>>(w.GT, N, w.sp, bp, thresh, w.Lacc, kBmax, w.acc, w.ints);
     KRR_LAUNCH_CHECK("chol_drop");
-    KRR_TRY(hip_check(hipMemcpyAsync(hbuf, w.ints, sizeof(int), hipMemcpyDeviceToHost, s), "acc"));
-    KRR_TRY(hip_check(hipMemcpyAsync(acc.data(), w.acc, sizeof(int) * bp, hipMemcpyDeviceToHost, s),
+    KRR_TRY(hip_check(hipMemcpyAsync(hints, w.ints, sizeof(int), hipMemcpyDeviceToHost, s), "acc"));
+    KRR_TRY(hip_check(hipMemcpyAsync(hacc, w.acc, sizeof(int) * bp, hipMemcpyDeviceToHost, s),
                       "acc list"));
     KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
-    const int na = hbuf[0];
+    const int na = hints[0];
     if (na > 0) {
       double* Fnew = P.QT + i * N;
       copy_rows<<<(unsigned)ceil_div((int64_t)na * N, 256), 256, 0, s>>>(w.GT, N, w.acc, na, N, Fnew);
@@ -373,7 +380,7 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
     }
     zero_at<<<1, kBmax, 0, s>>>(w.d, w.sp, bp);
     KRR_LAUNCH_CHECK("zero_at");
-    for (int a2 = 0; a2 < na; ++a2) P.pivots.push_back(sp[acc[a2]]);
+    for (int a2 = 0; a2 < na; ++a2) P.pivots.push_back(sp[hacc[a2]]);
     i += na;
     ++b;
   }

@@ -47,6 +47,9 @@ struct PcgState {
 };
 
 // Build-time buffers of RPCholesky (part of the workspace footprint).
+// Pinned host bytes for the build's small readbacks (totals, draws, accepted lists).
+constexpr size_t kHostStage = 4096;
+
 struct RPWork {
   double* d = nullptr;      // residual diagonal, N
   double* S = nullptr;      // chunk totals
@@ -59,6 +62,7 @@ struct RPWork {
   int* acc = nullptr;       // accepted positions
   int* ints = nullptr;      // [0] accepted count, [1] Cholesky info
   double* spx = nullptr;    // pivot points, kBmax x dpad
+  char* hstage = nullptr;   // pinned host staging of the per-block readbacks (kHostStage bytes)
 };
 
 // Build-time buffers of KRILL.
