@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-tile variant")
+    ap.add_argument("--no-predict", action="store_true", help="skip the held-out prediction")
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c2 (default) is the headline line; the others measure the other "
@@ -79,6 +80,14 @@ def laplace_ops_per_entry(d, m):
     # against V.  The tile may realise a difference plus accumulation in one
     # integer instruction; the count of the method's work does not change.
     return 2 * d + 5 + m
+
+
+def smape(yhat, y):
+    """Symmetric mean absolute percentage error of the HOMO task (Sec. 4.1)."""
+    import numpy as np
+    yhat, y = np.ravel(yhat), np.ravel(y)
+    den = (np.abs(yhat) + np.abs(y)) / 2.0
+    return float(np.mean(np.divide(np.abs(yhat - y), den, out=np.zeros_like(den), where=den > 0)))
 
 
 def run_steps(b, torch, p, X, Y, prec, steps, warmup):
@@ -209,6 +218,25 @@ def main():
         "roofline": roofline,
     }
 
+    if not a.no_predict:
+        # out-of-sample prediction on 3 x 10^4 held-out points (the train/test
+        # split of Sec. 4.1), outside the timed solves
+        Xte_h, Yte = synth.c2_test(30_000)
+        Xte = torch.from_numpy(Xte_h).to(dev)
+        P = b.rpchol_build(p.kind, p.sigma, b.FP32, X, p.mu, p.rank, seed=p.algo_seed)
+        beta, _ = P.solve(Y, p.tol, max_iter=1000)
+        pred = {"test_points": int(Xte.shape[0])}
+        for name, prec in (("fp32", b.FP32), ("fp64", b.FP64)):
+            P.predict(Xte, beta, prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = P.predict(Xte, beta, prec=prec)
+            torch.cuda.synchronize()
+            pred[f"{name}_ms"] = (time.perf_counter() - t0) * 1e3
+            pred[f"smape_{name}"] = smape(f.cpu().numpy(), Yte)
+        out["prediction"] = pred
+        del P
+
     if not a.no_fp64:
         wall64, infos64, _, _ = run_steps(b, torch, p, X, Y, b.FP64, 1, 0)
         it64 = infos64[0]["iters"]
@@ -221,11 +249,13 @@ def main():
     if not a.no_cpu:
         from oracle import kernels as OK
         rows = 3072  # about 12 s of one host core
-        cores = 1  # numpy elementwise kernels of the oracle run on one thread
+        from threadpoolctl import threadpool_limits
+        cores = 1  # BLAS limited to one thread; numpy's elementwise kernels use one
         Vh = np.random.default_rng(0).standard_normal((N, 1))
-        t0 = time.perf_counter()
-        OK.matvec(p.X[:rows], p.X, Vh, p.kind, p.sigma)
-        tc = time.perf_counter() - t0
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            OK.matvec(p.X[:rows], p.X, Vh, p.kind, p.sigma)
+            tc = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": rows * N / tc, "unit": "kernel entries/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"FP64 oracle product, rows 0..{rows - 1} x all {N} "

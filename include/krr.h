@@ -173,8 +173,9 @@ void krr_precond_free(krr_precond P);
  * (targets, row-major, device); beta receives n x m (N for full-data, k for
  * restricted).  At exit the true residual is evaluated with an FP64 product.
  * FP64 tiles: one residual-replacement restart if it exceeds 10 tol.
- * FP32 / MIXED tiles: up to 4 rounds of iterative refinement (CG restarted
- * from the FP64 true residual) until it meets tol; relres_true reports the
+ * FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG restarted
+ * from the FP64 true residual, each round run to tol/10 on its recursive
+ * residual) until it meets tol; relres_true reports the
  * final FP64 value.  Synchronises `stream` once per iteration.  Returns
  * KRR_NOT_CONVERGED (beta = last iterate) if a column did not converge and
  * KRR_ENAN on a NaN/Inf residual.                                          */
@@ -199,6 +200,25 @@ int krr_solve_begin(krr_precond P, const double* Y, int32_t m, double tol, int32
 int krr_solve_step(krr_solve* solves, int32_t n, int32_t* state, hipStream_t stream);
 int krr_solve_end(krr_solve S, double* beta, krr_solve_info* info, hipStream_t stream);
 void krr_solve_free(krr_solve S);
+
+/* Out-of-sample prediction with a solved model: the prediction function of
+ * full-data KRR (Sec. 2), f(x) = sum_i beta_i K(x_i, x) over the N training
+ * points, or of restricted KRR (Sec. 2.2), f(x) = sum_i beta_i K(x_{s_i}, x)
+ * over the k centres, in the object's kernel and bandwidth.
+ *   X      device, N x d row-major: the training points the object was built
+ *          on (the object keeps only packed copies, not X itself)
+ *   Xtest  device, ntest x d row-major
+ *   beta   device, n x m row-major (n = N full-data, k restricted), e.g. the
+ *          output of krr_pcg_solve
+ *   out    device, ntest x m row-major: f(Xtest) per right-hand side
+ *   prec   precision of the kernel tiles (any of the three, independent of
+ *          the build precision); 1 <= m <= 64
+ * Workspace: krr_predict_ws; asynchronous on `stream`.  Errors: KRR_EINVAL
+ * (shapes, NULL arrays), KRR_EWORKSPACE.                                    */
+int krr_predict_ws(krr_precond P, krr_precision prec, int64_t ntest, int32_t m, size_t* bytes);
+int krr_predict(krr_precond P, krr_precision prec, const double* X, const double* Xtest,
+                int64_t ntest, const double* beta, int32_t m, double* out, void* ws,
+                size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,8 @@ Modules (each function cites the passage of the paper it follows):
 * ``pcg``        -- textbook preconditioned CG with zero start and a
                     relative-residual stop (Sec. 3, eq. psd_system).
 * ``direct``     -- dense Cholesky solves used as pins (Sec. 2.1.1).
+* ``predict``    -- prediction functions of full-data and restricted KRR
+                    (Sec. 2, Sec. 2.2) and SMAPE (Sec. 4.1).
 
 Parity status: every function here is pinned by tests under ``tests/``
 (``test_oracle_*``) against closed forms, brute force or invariants; none is

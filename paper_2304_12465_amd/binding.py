@@ -57,6 +57,8 @@ _SIGS = {
     "krr_solve_end": ([_vp, _vp, ctypes.POINTER(SolveInfo), _vp], _i32),
     "krr_solve_free": ([_vp], None),
     "krr_pcg_solve": ([_vp, _vp, _i32, _dbl, _i32, _vp, ctypes.POINTER(SolveInfo), _vp], _i32),
+    "krr_predict_ws": ([_vp, _i32, _i64, _i32, _szp], _i32),
+    "krr_predict": ([_vp, _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _sz, _vp], _i32),
     "krr_kernel_matvec_ws": ([_i32, _i64, _i64, _i32, _i32, _szp], _i32),
     "krr_kernel_matvec": ([_i32, _dbl, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _i32, _dbl, _vp,
                            _vp, _sz, _vp], _i32),
@@ -196,6 +198,26 @@ class Precond:
         FT = torch.empty((r, self.X.shape[0]), dtype=torch.float64, device=self.device)
         check(lib().krr_rpchol_factor(self.h, _ptr(FT), _stream(self.device)))
         return FT
+
+    def predict(self, Xtest, beta, prec=0, ws=None):
+        """f(Xtest) of the solved model: K(Xtest, X) beta (full data) or
+        K(Xtest, X(S,:)) beta (restricted), ntest x m."""
+        _f64(Xtest)
+        B2 = self._block(beta)
+        nt, m = Xtest.shape[0], B2.shape[1]
+        # the C call reads ntest x d and n x m: check the tensors hold that
+        if Xtest.dim() != 2 or Xtest.shape[1] != self.X.shape[1]:
+            raise ValueError(f"Xtest must be ntest x {self.X.shape[1]}")
+        if B2.shape[0] != self.dims()[1]:
+            raise ValueError(f"beta must have {self.dims()[1]} rows")
+        if ws is None:
+            b = ctypes.c_size_t(0)
+            check(lib().krr_predict_ws(self.h, int(prec), nt, m, ctypes.byref(b)))
+            ws = workspace(b.value, self.device)
+        out = torch.empty((nt, m), dtype=torch.float64, device=self.device)
+        check(lib().krr_predict(self.h, int(prec), _ptr(self.X), _ptr(Xtest), nt, _ptr(B2), m,
+                                _ptr(out), _ptr(ws), ws.numel(), _stream(self.device)))
+        return out.reshape(-1) if beta.dim() == 1 else out
 
     def solve(self, Y, tol, max_iter=1000, history=0):
         """PCG; returns (beta, info dict).  Y: N x m targets."""

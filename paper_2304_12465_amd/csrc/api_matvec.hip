@@ -14,7 +14,7 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
-static int validate_matvec(int kind, double sigma, int prec, int64_t nr, int64_t nc, int32_t d,
+int validate_matvec(int kind, double sigma, int prec, int64_t nr, int64_t nc, int32_t d,
                            int32_t m) {
   if (kind != KRR_GAUSSIAN && kind != KRR_LAPLACE) {
     set_error("unknown kernel kind %d", kind);
@@ -36,10 +36,10 @@ static int validate_matvec(int kind, double sigma, int prec, int64_t nr, int64_t
   return KRR_OK;
 }
 
-static size_t matvec_bytes(krr_kernel_kind kind, krr_precision prec, int64_t nr, int64_t nc,
-                           int32_t d, int32_t m) {
-  return pointset_bytes(kind, prec, nr, d) + pointset_bytes(kind, prec, nc, d) +
-         product_scratch_bytes(prec, nr, nc, m);
+size_t matvec_bytes(int kind, int prec, int64_t nr, int64_t nc, int32_t d, int32_t m) {
+  return pointset_bytes((krr_kernel_kind)kind, (krr_precision)prec, nr, d) +
+         pointset_bytes((krr_kernel_kind)kind, (krr_precision)prec, nc, d) +
+         product_scratch_bytes((krr_precision)prec, nr, nc, m);
 }
 
 const char* last_error() { return g_err; }
@@ -64,10 +64,14 @@ extern "C" int krr_kernel_matvec_ws(krr_precision prec, int64_t nr, int64_t nc, 
   return KRR_OK;
 }
 
-extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precision prec,
-                                 const double* Xr, int64_t nr, const double* Xc, int64_t nc,
-                                 int32_t d, const double* V, int32_t m, double shift, double* W,
-                                 void* ws, size_t ws_bytes, hipStream_t stream) {
+namespace krr {
+
+int matvec_impl(int kind, double sigma, int prec,
+                const double* Xr, int64_t nr, const double* Xc, int64_t nc, int32_t d,
+                const double* V, int32_t m, double shift, double* W, void* ws, size_t ws_bytes,
+                hipStream_t stream) {
+  const krr_kernel_kind kk = (krr_kernel_kind)kind;
+  const krr_precision pp = (krr_precision)prec;
   KRR_TRY(validate_matvec(kind, sigma, prec, nr, nc, d, m));
   if (shift != 0.0 && nr != nc) {
     set_error("shift != 0 needs a square product (nr == nc)");
@@ -87,30 +91,40 @@ extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precisi
   Arena arena(ws, ws_bytes);
   PointSet rows, cols;
   const bool same = (Xc == Xr && nc == nr);
-  KRR_TRY(carve_points(kind, prec, nr, d, arena, &rows));
+  KRR_TRY(carve_points(kk, pp, nr, d, arena, &rows));
   if (same) cols = rows;
-  else KRR_TRY(carve_points(kind, prec, nc, d, arena, &cols));
+  else KRR_TRY(carve_points(kk, pp, nc, d, arena, &cols));
   if (!arena.ok()) {
     set_error("workspace too small for the point layouts");
     return KRR_EWORKSPACE;
   }
   if (same) {
-    KRR_TRY(fill_points(kind, prec, Xr, nullptr, rows, stream));
-  } else if (kind == KRR_LAPLACE && prec != KRR_FP64) {
+    KRR_TRY(fill_points(kk, pp, Xr, nullptr, rows, stream));
+  } else if (kk == KRR_LAPLACE && pp != KRR_FP64) {
     // one quantisation over both sets
     KRR_TRY(quant_params(Xr, nr, Xc, nc, d, rows.qbits, rows.qpart, const_cast<double*>(rows.qp),
                          stream));
-    KRR_TRY(fill_points(kind, prec, Xr, rows.qp, rows, stream));
-    KRR_TRY(fill_points(kind, prec, Xc, rows.qp, cols, stream));
+    KRR_TRY(fill_points(kk, pp, Xr, rows.qp, rows, stream));
+    KRR_TRY(fill_points(kk, pp, Xc, rows.qp, cols, stream));
   } else {
     // columns first: MIXED Gaussian rows share the columns' centre
-    KRR_TRY(fill_points(kind, prec, Xc, nullptr, cols, stream));
-    KRR_TRY(fill_points(kind, prec, Xr, nc > 0 ? shared_params(kind, prec, cols) : nullptr, rows,
+    KRR_TRY(fill_points(kk, pp, Xc, nullptr, cols, stream));
+    KRR_TRY(fill_points(kk, pp, Xr, nc > 0 ? shared_params(kk, pp, cols) : nullptr, rows,
                         stream));
   }
   VecView v{V, m, 1};
   VecOut w{W, m, 1};
-  return product(kind, sigma, prec, rows, cols, v, m, shift, v, w, arena, stream);
+  return product(kk, sigma, pp, rows, cols, v, m, shift, v, w, arena, stream);
+}
+
+}  // namespace krr
+
+
+extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                 const double* Xr, int64_t nr, const double* Xc, int64_t nc,
+                                 int32_t d, const double* V, int32_t m, double shift, double* W,
+                                 void* ws, size_t ws_bytes, hipStream_t stream) {
+  return matvec_impl(kind, sigma, prec, Xr, nr, Xc, nc, d, V, m, shift, W, ws, ws_bytes, stream);
 }
 
 extern "C" int krr_timing_enable(int on) {

@@ -437,3 +437,58 @@ extern "C" int krr_solve_end(krr_solve q, double* beta, krr_solve_info* info, hi
 }
 
 extern "C" void krr_solve_free(krr_solve q) { delete q; }
+
+// ---- out-of-sample prediction -------------------------------------------
+
+namespace {
+__global__ void gather_rows(const double* __restrict__ X, int d, const int64_t* __restrict__ idx,
+                            int64_t k, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < k * d) out[t] = X[idx[t / d] * d + t % d];
+}
+
+// bytes of the centre copy ahead of the product's own workspace
+size_t predict_prefix(const Precond& P) {
+  return P.type == kRPChol ? 0 : align_up(sizeof(double) * (size_t)P.k * P.d);
+}
+}  // namespace
+
+extern "C" int krr_predict_ws(krr_precond h, krr_precision prec, int64_t ntest, int32_t m,
+                              size_t* bytes) {
+  KRR_TRY(valid_precond(h));
+  const Precond& P = h->P;
+  const int64_t nc = P.type == kRPChol ? P.N : P.k;
+  KRR_TRY(validate_matvec(P.kind, P.sigma, prec, ntest, nc, P.d, m));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return KRR_EINVAL;
+  }
+  *bytes = predict_prefix(P) + matvec_bytes(P.kind, prec, ntest, nc, P.d, m);
+  return KRR_OK;
+}
+
+extern "C" int krr_predict(krr_precond h, krr_precision prec, const double* X,
+                           const double* Xtest, int64_t ntest, const double* beta, int32_t m,
+                           double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  KRR_TRY(valid_precond(h));
+  const Precond& P = h->P;
+  const int64_t nc = P.type == kRPChol ? P.N : P.k;
+  KRR_TRY(validate_matvec(P.kind, P.sigma, prec, ntest, nc, P.d, m));
+  if (ntest == 0) return KRR_OK;
+  if (!X || !Xtest || !beta || !out) {
+    set_error("NULL array argument");
+    return KRR_EINVAL;
+  }
+  const size_t pre = predict_prefix(P);
+  KRR_TRY(check_ws(ws, ws_bytes, pre + matvec_bytes(P.kind, prec, ntest, nc, P.d, m)));
+  const double* Xc = X;
+  if (P.type != kRPChol) {
+    // restricted KRR predicts from the centres x^(s_1) .. x^(s_k)
+    double* C = static_cast<double*>(ws);
+    gather_rows<<<(unsigned)ceil_div(P.k * P.d, 256), 256, 0, stream>>>(X, P.d, P.centers, P.k, C);
+    KRR_LAUNCH_CHECK("gather_rows");
+    Xc = C;
+  }
+  return matvec_impl(P.kind, P.sigma, prec, Xtest, ntest, Xc, nc, P.d, beta, m, 0.0, out,
+                     static_cast<char*>(ws) + pre, ws_bytes - pre, stream);
+}

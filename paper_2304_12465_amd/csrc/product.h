@@ -162,6 +162,15 @@ int compute_centre(const double* X, int64_t n, int32_t d, double* centre, double
 int fill_mixed(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
 size_t product_mfma_scratch_bytes(int64_t nr, int64_t nc);
 
+// The standalone product W = K(Xr, Xc) V + shift V with its own point layouts
+// carved from a caller workspace (api_matvec.hip); also serves predictions.
+int validate_matvec(int kind, double sigma, int prec, int64_t nr, int64_t nc, int32_t d,
+                    int32_t m);
+size_t matvec_bytes(int kind, int prec, int64_t nr, int64_t nc, int32_t d, int32_t m);
+int matvec_impl(int kind, double sigma, int prec, const double* Xr, int64_t nr, const double* Xc,
+                int64_t nc, int32_t d, const double* V, int32_t m, double shift, double* W,
+                void* ws, size_t ws_bytes, hipStream_t stream);
+
 // Tile timer hooks: start returns a token (or null when timing is off).
 void* tile_timer_start(hipStream_t s);
 void tile_timer_stop(void* token, hipStream_t s);

@@ -67,6 +67,18 @@ def c2(n=100_000, seed=1002):
                    rank=min(1000, n), tol=1e-6, algo_seed=2002)
 
 
+def c2_test(m=30_000, seed=1002, test_seed=3002):
+    """Held-out points of the c2 distribution (the same mixture means, drawn
+    from `seed` as c2 does, then m fresh points and targets from
+    `test_seed`): the 10^5 / 3 x 10^4 train / test split of Sec. 4.1."""
+    means = 2.0 * np.random.default_rng(seed).standard_normal((10, 20))
+    g = np.random.default_rng(test_seed)
+    comp = g.integers(0, 10, size=m)
+    X = means[comp] + g.standard_normal((m, 20))
+    y = np.mod(np.abs(X).sum(axis=1), 3.0) + 0.05 * g.standard_normal(m)
+    return X, y[:, None]
+
+
 def c3(n=1_000_000, seed=1003, m=8):
     """Uniform [0,1]^32 with 5% near-duplicates (copies of uniformly chosen
     points plus N(0, 1e-12 I) jitter); m smooth targets

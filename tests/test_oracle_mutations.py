@@ -103,3 +103,28 @@ def test_wrong_sketch_scale_is_caught(monkeypatch):
         return orig(N, d_rows, zeta, seed) * np.sqrt(zeta)  # forgot zeta^{-1/2}
     monkeypatch.setattr(KR, "sketch_matrix", bad)
     must_fail(TKR.test_sketch_structure)
+
+
+def test_wrong_centre_indexing_in_prediction_is_caught(monkeypatch):
+    import oracle.predict as PR
+    import tests.test_oracle_predict as TPR
+
+    def bad(X, S, beta_hat, Xtest, kind, sigma, row_block=2048):  # off-by-one centres
+        C = np.asarray(X)[(np.asarray(S) + 1) % len(X)]
+        return K.matvec(Xtest, C, beta_hat, kind, sigma, row_block=row_block)
+    monkeypatch.setattr(PR, "predict_restricted", bad)
+    must_fail(TPR.test_restricted_fit_satisfies_the_normal_equations)
+
+
+def test_smape_without_halving_is_caught(monkeypatch):
+    import oracle.predict as PR
+    import tests.test_oracle_predict as TPR
+
+    def bad(yhat, y):  # denominator |yhat| + |y| (no halving)
+        yhat = np.asarray(yhat, float)
+        y = np.asarray(y, float)
+        den = np.abs(yhat) + np.abs(y)
+        return float(np.mean(np.divide(np.abs(yhat - y), den, out=np.zeros_like(den),
+                                       where=den > 0)))
+    monkeypatch.setattr(PR, "smape", bad)
+    must_fail(TPR.test_smape_definition_values)
