@@ -257,6 +257,48 @@ __global__ __launch_bounds__(256) void trsm_diag(const double* __restrict__ L, i
   store_col(B + c, ldb, nb, x);
 }
 
+// C[M x N] = alpha A B^T + beta C for M <= MM rows of A (row-major M x K)
+// and B given as N x K rows: each output is a dot product of two contiguous
+// rows.  One workgroup per output column streams row j of B (coalesced)
+// against the M rows of A (L2-resident); lanes, then the four waves, are
+// added in a fixed order, so the result is reproducible.  Used by the
+// preconditioner applies, whose first product has one row per right-hand
+// side.
+template <int MM>
+__global__ __launch_bounds__(256) void gemm_rowdot(int64_t M, int64_t N, int64_t K, double alpha,
+                                                   const double* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ B, int64_t ldb,
+                                                   double beta, double* __restrict__ C,
+                                                   int64_t ldc) {
+  __shared__ double red[4][MM];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t j = blockIdx.x;
+  double acc[MM];
+#pragma unroll
+  for (int c = 0; c < MM; ++c) acc[c] = 0.0;
+  const double* __restrict__ b = B + j * ldb;
+  for (int64_t k = tid; k < K; k += 256) {
+    const double bv = b[k];
+#pragma unroll
+    for (int c = 0; c < MM; ++c)
+      if (c < M) acc[c] = __builtin_fma(A[c * lda + k], bv, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < MM; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wave][c] = v;
+  }
+  __syncthreads();
+  if (tid < MM && tid < M) {
+    const int c = tid;
+    const double v = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    const double old = beta != 0.0 ? beta * C[c * ldc + j] : 0.0;
+    C[c * ldc + j] = alpha * v + old;
+  }
+}
+
 }  // namespace
 
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
@@ -274,6 +316,19 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, hipStream_t s, Arena* scratch) {
   if (M <= 0 || N <= 0) return KRR_OK;
+  if (!a_trans && b_trans && M <= 8) {
+    const unsigned g = (unsigned)N;
+    if (M == 1)
+      gemm_rowdot<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (M <= 2)
+      gemm_rowdot<2><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (M <= 4)
+      gemm_rowdot<4><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+      gemm_rowdot<8><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    KRR_LAUNCH_CHECK("gemm_rowdot");
+    return KRR_OK;
+  }
   const int64_t gx = ceil_div(N, kTile), gy = ceil_div(M, kTile);
   if (gy > 65535) {
     set_error("gemm_f64: M=%lld too large for the grid", (long long)M);
