@@ -32,15 +32,19 @@ __global__ void fill_d(double* __restrict__ d, double v, int64_t n) {
   if (t < n) d[t] = v;
 }
 
-// S[c] = ((0 + d[c*1024]) + d[c*1024+1]) + ... , one thread per chunk.
-__global__ void chunk_sums(const double* __restrict__ d, int64_t n, int64_t nch,
-                           double* __restrict__ S) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nch) return;
+// S[c] = ((0 + d[c*1024]) + d[c*1024+1]) + ... : one workgroup per chunk
+// stages it in LDS (coalesced), then one thread adds it in index order.
+__global__ __launch_bounds__(256) void chunk_sums(const double* __restrict__ d, int64_t n,
+                                                  int64_t nch, double* __restrict__ S) {
+  __shared__ double v[kChunk];
+  const int64_t c = blockIdx.x;
   const int64_t i0 = c * kChunk;
-  const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+  const int len = (int)((i0 + kChunk < n) ? kChunk : n - i0);
+  for (int e = threadIdx.x; e < len; e += blockDim.x) v[e] = d[i0 + e];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double s = 0.0;
-  for (int64_t i = i0; i < i1; ++i) s = __dadd_rn(s, d[i]);
+  for (int e = 0; e < len; ++e) s = __dadd_rn(s, v[e]);
   S[c] = s;
 }
 
@@ -55,44 +59,64 @@ __global__ void chunk_offsets(const double* __restrict__ S, int64_t nch, double*
   }
 }
 
-__global__ void draw_pivots(const double* __restrict__ d, int64_t n, const double* __restrict__ O,
-                            int64_t nch, uint64_t block_key, int count,
-                            int64_t* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+__global__ __launch_bounds__(256) void draw_pivots(const double* __restrict__ d, int64_t n,
+                                                   const double* __restrict__ O, int64_t nch,
+                                                   uint64_t block_key, int count,
+                                                   int64_t* __restrict__ out) {
+  // one workgroup per draw t: binary search over the chunk offsets, then the
+  // chunk staged in LDS and scanned in index order by one thread
+  __shared__ double v[kChunk];
+  __shared__ int64_t found;
+  __shared__ int64_t last[256];
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
   const double T = O[nch];
   const double u = u53(sm64(block_key, (uint64_t)t));
   const double thr = __dmul_rn(u, T);
-  // smallest chunk c with O[c+1] > thr
+  // smallest chunk c with O[c+1] > thr (every thread finds the same one)
   int64_t lo = 0, hi = nch;  // search in [lo, hi)
   while (lo < hi) {
     const int64_t mid = (lo + hi) / 2;
     if (O[mid + 1] > thr) hi = mid;
     else lo = mid + 1;
   }
-  int64_t pick = -1;
+  if (tid == 0) found = -1;
   if (lo < nch) {
     const int64_t i0 = lo * kChunk;
-    const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
-    const double base = O[lo];
-    double p = 0.0;
-    for (int64_t i = i0; i < i1; ++i) {
-      p = __dadd_rn(p, d[i]);
-      if (__dadd_rn(base, p) > thr) {
-        pick = i;
-        break;
+    const int len = (int)((i0 + kChunk < n) ? kChunk : n - i0);
+    for (int e = tid; e < len; e += blockDim.x) v[e] = d[i0 + e];
+    __syncthreads();
+    if (tid == 0) {
+      const double base = O[lo];
+      double p = 0.0;
+      for (int e = 0; e < len; ++e) {
+        p = __dadd_rn(p, v[e]);
+        if (__dadd_rn(base, p) > thr) {
+          found = i0 + e;
+          break;
+        }
       }
     }
   }
-  if (pick < 0) {  // u*T rounded up to T: last index with positive mass
-    for (int64_t i = n - 1; i >= 0; --i)
+  __syncthreads();
+  if (found < 0) {
+    // u*T rounded up to T: the last index with positive mass (0 if none)
+    int64_t mine = -1;
+    for (int64_t i = n - 1 - tid; i >= 0; i -= blockDim.x)
       if (d[i] > 0.0) {
-        pick = i;
+        mine = i;
         break;
       }
-    if (pick < 0) pick = 0;
+    last[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t best = -1;
+      for (int q = 0; q < (int)blockDim.x; ++q) best = last[q] > best ? last[q] : best;
+      found = best < 0 ? 0 : best;
+    }
+    __syncthreads();
   }
-  out[t] = pick;
+  if (tid == 0) out[t] = found;
 }
 
 // out[q][j] = K(A_q, B_j) in FP64, direct differences.  One thread per j;
@@ -160,50 +184,60 @@ __global__ void gather_cols(const double* __restrict__ FT, int64_t ldf, int64_t 
 }
 
 // Pivot-by-pivot Cholesky of G(S',S') with the drop rule, in LDS.
-// R (upper) is built in place over the upper triangle.  Outputs the lower
-// factor of the accepted pivots, Lacc = R_acc^T (acc x acc, ld = ldl), the
-// accepted positions and their count.
+// One array M holds G in its upper triangle and, transposed in its lower
+// triangle, the rows of R of the accepted pivots: R(acc[a], q) lives at
+// M[q][a] (q >= acc[a] >= a), so each Schur sum reads a contiguous piece of
+// one row (left-looking, terms added in acceptance order).  Outputs the
+// lower factor of the accepted pivots, Lacc = R_acc^T (acc x acc, ld =
+// ldl), the accepted positions and their count.
 __global__ __launch_bounds__(256) void chol_drop(const double* __restrict__ GT, int64_t ldg,
                                                  const int64_t* __restrict__ sp, int bp,
                                                  double thresh, double* __restrict__ Lacc,
                                                  int ldl, int* __restrict__ acc_out,
                                                  int* __restrict__ acc_count) {
-  __shared__ double R[kBmax][kBmax + 1];
+  __shared__ double M[kBmax][kBmax + 1];
   __shared__ int acc[kBmax];
   __shared__ int nacc;
   __shared__ int take;
+  __shared__ double rqq;
   const int tid = threadIdx.x;
   for (int e = tid; e < bp * bp; e += blockDim.x) {
     const int q = e / bp, q2 = e % bp;
-    R[q][q2] = GT[(int64_t)q * ldg + sp[q2]];  // G(S'_q, S'_q2)
+    M[q][q2] = GT[(int64_t)q * ldg + sp[q2]];  // G(S'_q, S'_q2)
   }
   if (tid == 0) nacc = 0;
   __syncthreads();
   for (int q = 0; q < bp; ++q) {
+    const int na = nacc;
     if (tid == 0) {
       double s = 0.0;
-      for (int a = 0; a < nacc; ++a) s = __dadd_rn(s, __dmul_rn(R[acc[a]][q], R[acc[a]][q]));
-      s = __dsub_rn(R[q][q], s);
+      for (int a = 0; a < na; ++a) s = __dadd_rn(s, __dmul_rn(M[q][a], M[q][a]));
+      s = __dsub_rn(M[q][q], s);
       take = s > thresh ? 1 : 0;
-      if (take) R[q][q] = sqrt(s);
+      if (take) rqq = sqrt(s);
     }
     __syncthreads();
     if (take) {
-      const double rqq = R[q][q];
+      const double r = rqq;
       for (int q2 = q + 1 + tid; q2 < bp; q2 += blockDim.x) {
         double s = 0.0;
-        for (int a = 0; a < nacc; ++a) s = __dadd_rn(s, __dmul_rn(R[acc[a]][q], R[acc[a]][q2]));
-        R[q][q2] = __ddiv_rn(__dsub_rn(R[q][q2], s), rqq);
+        for (int a = 0; a < na; ++a) s = __dadd_rn(s, __dmul_rn(M[q][a], M[q2][a]));
+        M[q2][na] = __ddiv_rn(__dsub_rn(M[q][q2], s), r);
+      }
+      __syncthreads();  // every read of M[q][q] and row q is done
+      if (tid == 0) {
+        M[q][na] = r;
+        acc[na] = q;
+        nacc = na + 1;
       }
     }
     __syncthreads();
-    if (tid == 0 && take) acc[nacc++] = q;
-    __syncthreads();
   }
   const int na = nacc;
+  // Lacc[a][b] = R(acc[b], acc[a]) = M[acc[a]][b] for b <= a
   for (int e = tid; e < na * na; e += blockDim.x) {
-    const int a = e / na, b = e % na;
-    Lacc[a * ldl + b] = (b <= a) ? R[acc[b]][acc[a]] : 0.0;
+    const int a = e / na, b2 = e % na;
+    Lacc[a * ldl + b2] = (b2 <= a) ? M[acc[a]][b2] : 0.0;
   }
   for (int a = tid; a < na; a += blockDim.x) acc_out[a] = acc[a];
   if (tid == 0) *acc_count = na;
@@ -326,12 +360,12 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   while (i < P.r_req && b <= N) {
     // prefix tables, then the block's draws (they read the total on the
     // device); one readback of the total and the draws
-    chunk_sums<<<(unsigned)ceil_div(nch, 256), 256, 0, s>>>(w.d, N, nch, w.S);
+    chunk_sums<<<(unsigned)nch, 256, 0, s>>>(w.d, N, nch, w.S);
     KRR_LAUNCH_CHECK("chunk_sums");
     chunk_offsets<<<1, 1, 0, s>>>(w.S, nch, w.O);
     KRR_LAUNCH_CHECK("chunk_offsets");
     const int cnt = (int)std::min<int64_t>(P.B, P.r_req - i);
-    draw_pivots<<<(unsigned)ceil_div(cnt, 64), 64, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
+    draw_pivots<<<(unsigned)cnt, 256, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
                                                            cnt, w.draws);
     KRR_LAUNCH_CHECK("draw_pivots");
     KRR_TRY(hip_check(hipMemcpyAsync(hT, w.O + nch, sizeof(double), hipMemcpyDeviceToHost, s), "T"));
