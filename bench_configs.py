@@ -99,8 +99,13 @@ def c3(a, b, torch, synth):
     out = {"product_ms": ms, "entries_per_s": rate,
            "mfma_tflops_executed": rate * mfma_flops / 1e12,
            "mfma_frac_of_bf16_peak": rate * mfma_flops / 2.5e15}
-    ms32 = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, m, launches=1)
-    out["fp32_valu_product_ms"] = ms32
+    ms32 = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, m, launches=2)
+    # FP32 tiles: distance (K = 32) and E.V (16 rhs columns) on
+    # v_mfma_f32_16x16x4f32, 2 flops per multiply-add
+    f32_flops = 2 * 32 + 2 * 16
+    out.update(fp32_product_ms=ms32, fp32_entries_per_s=N * N / (ms32 * 1e-3),
+               fp32_mfma_tflops=N * N * f32_flops / (ms32 * 1e-3) / 1e12,
+               fp32_mfma_frac_of_peak=N * N * f32_flops / (ms32 * 1e-3) / 157.3e12)
     steps = []
     if a.steps > 0:
         ws = b.workspace(b.rpchol_ws(p.kind, b.MIXED, N, d, p.rank, 0, m), X.device)

@@ -45,6 +45,9 @@ struct PointSet {
   const double* xc64 = nullptr;   // FP64 Gaussian: centred points n x dpad
   const double* xn64 = nullptr;   // FP64 Gaussian: ||x - centre||^2
   const double* xmax64 = nullptr; // FP64 Gaussian: max ||x - centre||^2 (one device double)
+  const float* xc32 = nullptr;    // FP32 Gaussian: centred points n x dpad
+  const float* xn32 = nullptr;    // FP32 Gaussian: ||x - centre||^2
+  const float* xmax32 = nullptr;  // FP32 Gaussian: max ||x - centre||^2 (one device float)
   const uint32_t* xq = nullptr;   // n x dpad
   const double* qp = nullptr;     // [lo, S] (device), shared by rows and columns
   double* qpart = nullptr;        // 256 x 2 partial min/max
@@ -134,26 +137,36 @@ int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVi
                  int mc, Arena& scratch, MfmaJob* out, hipStream_t s);
 int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s);
 
-// A prepared FP64 MFMA Gaussian job (product_f64mfma.hip).
-struct F64Job {
-  const double* xc;
-  const double* xn;
-  const double* xmax;  // max ||x||^2 of the rows / columns (device)
-  const double* ymax;
-  const double* yc;
-  const double* yn;
-  const double* v;
-  double* part;
+// A prepared Gaussian MFMA job in FP64 or FP32 (product_gauss_mfma.hip).
+template <typename T>
+struct GJob {
+  const T* xc;      // centred rows, nr x dpad
+  const T* xn;      // their squared norms
+  const T* xmax;    // max ||x||^2 of the rows / columns (device)
+  const T* ymax;
+  const T* yc;      // centred columns, nc x dpad
+  const T* yn;
+  const T* v;       // nc x 16
+  double* part;     // nsplit x nr x 16
   int64_t nr, nc, per, item0;
-  double s;
+  T s;              // exponent scale (FP32: in base 2)
+  double s_nat;     // 1 / (2 sigma^2)
   int nsplit, M, dpad;
 };
+typedef GJob<double> F64Job;
+typedef GJob<float> F32Job;
 int carve_f64c(int64_t n, int32_t dpad, Arena& arena, PointSet* out);
 int fill_f64c(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
+int carve_f32c(int64_t n, int32_t dpad, Arena& arena, PointSet* out);
+int fill_f32c(const double* X, const double* centre, const PointSet& ps, hipStream_t s);
 size_t product_f64mfma_scratch_bytes(int64_t nr, int64_t nc);
+size_t product_f32mfma_scratch_bytes(int64_t nr, int64_t nc);
 int f64_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
                 Arena& scratch, F64Job* out, hipStream_t s);
+int f32_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
+                Arena& scratch, F32Job* out, hipStream_t s);
 int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s);
+int f32_launch(const std::vector<F32Job>& jobs, hipStream_t s);
 
 // bf16-split MFMA path for Gaussian tiles (product_mfma.hip).
 int carve_mixed(int64_t n, int32_t d, Arena& arena, PointSet* out);

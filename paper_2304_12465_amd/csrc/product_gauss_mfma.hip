@@ -1,0 +1,607 @@
+// Gaussian kernel tiles on the matrix cores in FP64 (precision KRR_FP64,
+// v_mfma_f64_16x16x4f64) and FP32 (precision KRR_FP32, v_mfma_f32_16x16x4f32).
+//
+// ||x - y||^2 = ||x||^2 + ||y||^2 - 2 x.y with the contraction on the MFMA
+// over centred points (centring keeps the expansion's cancellation at
+// ~eps ||x||^2).  The distance MFMA starts from -||x||^2 / 2, so one FMA
+// gives the exponent; exp runs on the VALU (FP64: the table-driven exp64;
+// FP32: v_exp_f32 on an exponent scaled by log2 e).  The reduction against V
+// is a second MFMA for more than 4 right-hand sides: the distance output
+// layout (lane l holds, for t = 0..3, column col(t, l/16) of row l % 16) is
+// the A-operand layout of K-step t of the 16x16x4 MFMA with K index l / 16
+// standing for that column, so no lane exchange is needed.  For up to 4
+// right-hand sides E.V runs on the VALU and the four lanes of a row are
+// added at the end.  FP64 sums throughout (FP32 partial sums fold into FP64
+// every 256 columns); per-split partials go to fixed slots (bitwise
+// reproducible).
+#include "product.h"
+#include "exp64.h"
+#include <algorithm>
+#include <type_traits>
+
+namespace krr {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRTg = 2;      // 16-row tiles per wave
+constexpr int kColsG = 64;   // columns per LDS chunk (four 16-column tiles)
+constexpr int kFoldG = 4;    // FP32: chunks per FP64 fold (256 columns)
+
+// Operand layouts (wave64, lane l, g = l / 16, li = l % 16):
+//   A (16 x 4): lane l holds A[li][g];  B (4 x 16): lane l holds B[g][li]
+//   D (16 x 16), element t of lane l:
+//     v_mfma_f64_16x16x4f64: D[4 t + g][li]
+//     v_mfma_f32_16x16x4f32: D[4 g + t][li]
+// col(t, g) names that row index of D.
+template <typename T>
+struct GT;
+template <>
+struct GT<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int t, int g) { return 4 * t + g; }
+  static __device__ __forceinline__ double ex(double x, const double* tab) { return exp64(x, tab); }
+  static constexpr double kFar = -1.0e300;   // exponent of columns past the range
+  // expansion error bound (d + 3) eps s (max||x||^2 + max||y||^2) at most
+  // 400 eps = 8.9e-14, else direct differences
+  static constexpr double kBound = 400.0;
+};
+template <>
+struct GT<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int t, int g) { return 4 * g + t; }
+  static __device__ __forceinline__ float ex(float x, const double*) {
+    return __builtin_amdgcn_exp2f(x);
+  }
+  static constexpr float kFar = -3.0e38f;
+  // 200 eps_32 = 1.2e-5 relative per entry at most (the FP32 tile tolerance
+  // is 2e-5 of sum |K||V|), else direct differences
+  static constexpr double kBound = 200.0;
+};
+
+__device__ __forceinline__ double fma_g(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_g(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
+  return J.s_nat * ((double)*J.xmax + (double)*J.ymax) * (J.dpad + 3) > GT<T>::kBound;
+}
+
+// Per-thread staging of the next 64-column chunk (points, exponent offsets
+// -s ||y||^2, V), loaded into registers while the current chunk is computed.
+template <typename T, int D>
+struct StageG {
+  static constexpr int kY = kColsG * D / 256;  // point values per thread
+  T y[kY];
+  T v[4];  // V: 64 columns x 16 rhs / 256 threads
+  T ay;    // threads 0..63
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_t j1, int tid,
+                                            StageG<T, D>& st) {
+#pragma unroll
+  for (int q = 0; q < StageG<T, D>::kY; ++q) {
+    const int e = tid + q * 256;
+    const int jj = e / D;
+    st.y[q] = (jb + jj < j1) ? J.yc[jb * D + e] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + q * 256;
+    st.v[q] = (jb + e / 16 < j1) ? J.v[jb * 16 + e] : T(0);
+  }
+  if (tid < kColsG) st.ay = (jb + tid < j1) ? -J.s * J.yn[jb + tid] : GT<T>::kFar;
+}
+
+template <typename T, int D, int MV>
+__device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
+                                       const double* __restrict__ etab) {
+  typedef typename GT<T>::acc_t acc_t;
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  constexpr int KS = D / 4;
+  constexpr int NT = kColsG / 16;
+  __shared__ T sY[kColsG][D + 1];
+  __shared__ T sAy[kColsG];
+  __shared__ T sV[kColsG][17];  // [column][rhs]
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t nr = J.nr, nc = J.nc;
+  const int64_t row0 = (rg * 4 + wave) * (16 * kRTg);
+
+  T xb[kRTg][KS];  // B operand: X[i0 + li][4 ks + g]
+  acc_t cinit[kRTg];
+#pragma unroll
+  for (int rt = 0; rt < kRTg; ++rt) {
+    int64_t i = row0 + rt * 16 + li;
+    if (i > nr - 1) i = nr - 1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xb[rt][ks] = J.xc[i * D + 4 * ks + g];
+    const T h = T(-0.5) * J.xn[i];
+    cinit[rt] = acc_t{h, h, h, h};
+  }
+  // E.V on the matrix cores (MV = 0): two accumulators per row tile (even /
+  // odd K steps) keep independent MFMA chains in flight.  On the VALU
+  // (MV = 1, 2, 4 right-hand sides): lane l sums E[li][col] V[col][c] over
+  // its columns.
+  constexpr int MA = MV == 0 ? 2 : 1;
+  constexpr int MC = MV == 0 ? 1 : MV;
+  acc_t acc[kRTg][MA];
+  T accv[kRTg][MC];
+  double fold[kRTg][4];  // FP32 only: FP64 running sums of the output entries
+#pragma unroll
+  for (int rt = 0; rt < kRTg; ++rt) {
+#pragma unroll
+    for (int a = 0; a < MA; ++a) acc[rt][a] = acc_t{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < MC; ++c) accv[rt][c] = T(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) fold[rt][u] = 0.0;
+  }
+  const T s2 = T(2) * J.s;
+
+  const int64_t j0 = (int64_t)split * J.per;
+  int64_t j1 = j0 + J.per;
+  if (j1 > nc) j1 = nc;
+  StageG<T, D> st;
+  if (j0 < j1) stage_fetch<T, D>(J, j0, j1, tid, st);
+  int chunk = 0;
+  for (int64_t jb = j0; jb < j1; jb += kColsG, ++chunk) {
+    __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < StageG<T, D>::kY; ++q) {
+      const int e = tid + q * 256;
+      sY[e / D][e % D] = st.y[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      sV[e / 16][e % 16] = st.v[q];
+    }
+    if (tid < kColsG) sAy[tid] = st.ay;
+    __syncthreads();
+    if (jb + kColsG < j1) stage_fetch<T, D>(J, jb + kColsG, j1, tid, st);
+    if (row0 >= nr) continue;
+    // distance MFMAs of column tile ct + 1 are issued before the exp work
+    // of tile ct, which does not depend on them
+    acc_t dot[2][kRTg];
+    auto distance = [&](int ct, acc_t* dd) {
+      T ya[KS];  // A operand: Y[ct*16 + li][4 ks + g]
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
+#pragma unroll
+      for (int rt = 0; rt < kRTg; ++rt) dd[rt] = cinit[rt];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dd[rt]);
+    };
+    distance(0, dot[0]);
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      if (ct + 1 < NT) distance(ct + 1, dot[(ct + 1) & 1]);
+      T ay[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) ay[t] = sAy[ct * 16 + GT<T>::col(t, g)];
+      // dot[rt][t] = y_{col(t,g)} . x_{li} - ||x_{li}||^2 / 2
+      T e[kRTg][4];
+#pragma unroll
+      for (int rt = 0; rt < kRTg; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          e[rt][t] = GT<T>::ex(fma_g(dot[ct & 1][rt][t], s2, ay[t]), etab);
+      if constexpr (MV == 0) {
+        // A of E.V step t: lane l holds E[li][col(t, g)] (K index g)
+        T vb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) vb[t] = sV[ct * 16 + GT<T>::col(t, g)][li];  // V[col][c = li]
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int rt = 0; rt < kRTg; ++rt)
+            acc[rt][t & 1] = GT<T>::mfma(e[rt][t], vb[t], acc[rt][t & 1]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int c = 0; c < MV; ++c) {
+            const T v = sV[ct * 16 + GT<T>::col(t, g)][c];
+#pragma unroll
+            for (int rt = 0; rt < kRTg; ++rt) accv[rt][c] = fma_g(e[rt][t], v, accv[rt][c]);
+          }
+      }
+    }
+    if constexpr (kF32) {
+      if ((chunk + 1) % kFoldG == 0) {
+#pragma unroll
+        for (int rt = 0; rt < kRTg; ++rt) {
+          if constexpr (MV == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) fold[rt][u] += (double)acc[rt][0][u] + (double)acc[rt][1][u];
+            acc[rt][0] = acc_t{0.f, 0.f, 0.f, 0.f};
+            acc[rt][1] = acc_t{0.f, 0.f, 0.f, 0.f};
+          } else {
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+              fold[rt][c] += (double)accv[rt][c];
+              accv[rt][c] = 0.f;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (row0 >= nr) return;
+  double* __restrict__ out = J.part + (int64_t)split * nr * 16;
+  if constexpr (MV == 0) {
+#pragma unroll
+    for (int rt = 0; rt < kRTg; ++rt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // E.V output: lane l, element t holds W[i0 + col(t, g)][c = li]
+        const int64_t i = row0 + rt * 16 + GT<T>::col(t, g);
+        const double w = kF32 ? fold[rt][t] + ((double)acc[rt][0][t] + (double)acc[rt][1][t])
+                              : (double)acc[rt][0][t] + (double)acc[rt][1][t];
+        if (i < nr && li < J.M) out[i * 16 + li] = w;
+      }
+  } else {
+#pragma unroll
+    for (int rt = 0; rt < kRTg; ++rt)
+#pragma unroll
+      for (int c = 0; c < MV; ++c) {
+        // lanes li, li+16, li+32, li+48 hold partial sums of row li: add in
+        // a fixed pairing ((g0 + g1) + (g2 + g3))
+        double a = kF32 ? fold[rt][c] + (double)accv[rt][c] : (double)accv[rt][c];
+        a += __shfl_xor(a, 16);
+        a += __shfl_xor(a, 32);
+        const int64_t i = row0 + rt * 16 + li;
+        if (g == 0 && i < nr && c < J.M) out[i * 16 + c] = a;
+      }
+  }
+}
+
+constexpr int kMaxGJobs = 8;
+template <typename T>
+struct GTable {
+  GJob<T> job[kMaxGJobs];
+  int njobs;
+  int64_t total;
+};
+
+template <typename T, int D, int MV>
+__global__ __launch_bounds__(256) void tile_gauss_mfma(const GTable<T> tab) {
+  __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 tiles)
+  if constexpr (std::is_same<T, double>::value) {
+    exp64_table_fill(etab);
+    __syncthreads();
+  }
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const GJob<T>& J = tab.job[jn];
+    if (needs_direct(J)) continue;  // uniform over the workgroup
+    const int64_t local = item - J.item0;
+    g_item<T, D, MV>(J, local / J.nsplit, (int)(local % J.nsplit), etab);
+  }
+}
+
+// Direct-difference Gaussian tile for the jobs the expansion cannot serve to
+// the precision's accuracy: same items and partial-sum layout as
+// tile_gauss_mfma.  Thread t owns row t % 128 of the item and every other
+// column (t / 128 picks the parity); the column points and V are
+// wave-uniform (scalar loads).  FP32 sums fold into FP64 every 256 columns;
+// the two parities are added in a fixed order.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void tile_gauss_direct(const GTable<T> tab) {
+  constexpr bool kF32 = std::is_same<T, float>::value;
+  __shared__ double etab[kExpTable];
+  __shared__ double sW[128][17];
+  if constexpr (!kF32) exp64_table_fill(etab);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int r = tid & 127, h = tid >> 7;
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const GJob<T>& J = tab.job[jn];
+    if (!needs_direct(J)) continue;  // uniform over the workgroup
+    const int64_t local = item - J.item0;
+    const int64_t rg = local / J.nsplit;
+    const int split = (int)(local % J.nsplit);
+    const int64_t nr = J.nr;
+    const int64_t i = rg * (4 * 16 * kRTg) + r;
+    const int64_t ic = i < nr ? i : nr - 1;
+    T x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = J.xc[ic * D + k];
+    double acc64[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc64[c] = 0.0;
+    const int64_t j0 = (int64_t)split * J.per;
+    int64_t j1 = j0 + J.per;
+    if (j1 > J.nc) j1 = J.nc;
+    for (int64_t jb = j0; jb < j1; jb += 2 * 256) {
+      const int64_t je = jb + 2 * 256 < j1 ? jb + 2 * 256 : j1;
+      T acc[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] = T(0);
+      for (int64_t j = jb + h; j < je; j += 2) {
+        const T* __restrict__ y = J.yc + j * D;
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const T t = x[k] - y[k];
+          s = fma_g(t, t, s);
+        }
+        const T e = GT<T>::ex(-J.s * s, etab);
+        const T* __restrict__ v = J.v + j * 16;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = fma_g(e, v[c], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc64[c] += (double)acc[c];
+    }
+    __syncthreads();  // sW of the previous item is consumed
+    if (h == 1) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) sW[r][c] = acc64[c];
+    }
+    __syncthreads();
+    if (h == 0 && i < nr) {
+      double* __restrict__ out = J.part + (int64_t)split * nr * 16 + i * 16;
+      for (int c = 0; c < J.M; ++c) out[c] = acc64[c] + sW[r][c];
+    }
+  }
+}
+
+template <typename T>
+__global__ void zero_scalar(T* p) {
+  *p = T(0);
+}
+
+// centred copy and squared norms (formed in FP64 from the rounded centred
+// coordinates); the largest norm goes to *xmax (wave maximum, then an integer
+// atomic max on the bits: the norms are >= 0, whose IEEE bit patterns order
+// like the values)
+template <typename T>
+__global__ void pack_centred(const double* __restrict__ X, int64_t n, int d, int dpad,
+                             const double* __restrict__ centre, T* __restrict__ xc,
+                             T* __restrict__ xn, T* __restrict__ xmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < n) {
+    for (int k = 0; k < dpad; ++k) {
+      const T v = k < d ? (T)(X[i * d + k] - centre[k]) : T(0);
+      xc[i * dpad + k] = v;
+      s += (double)v * (double)v;
+    }
+    xn[i] = (T)s;
+  }
+  T m = (T)s;
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) {
+    if constexpr (std::is_same<T, double>::value)
+      atomicMax(reinterpret_cast<unsigned long long*>(xmax), (unsigned long long)__double_as_longlong(m));
+    else
+      atomicMax(reinterpret_cast<unsigned int*>(xmax), (unsigned int)__float_as_uint(m));
+  }
+}
+
+template <typename T>
+__global__ void pack_v16(VecView V, int64_t n, int c0, int mc, T* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 16) return;
+  const int64_t j = t / 16;
+  const int c = (int)(t % 16);
+  out[t] = c < mc ? (T)V.p[j * V.rs + (int64_t)(c0 + c) * V.cs] : T(0);
+}
+
+struct GSplit {
+  int nsplit;
+  int64_t per;
+};
+
+GSplit g_split(int64_t nr, int64_t nc) {
+  const int64_t ns = split_count(nr, nc, 4 * 16 * kRTg, 256);
+  int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
+  per = ceil_div(per, kColsG) * kColsG;
+  return {(int)ns, per};
+}
+
+// E.V reduction variant for m right-hand sides: VALU for m <= 4, MFMA above
+int g_variant(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : 0; }
+
+template <typename T, int D>
+void launch_d(int mv, unsigned grid, const GTable<T>& tab, hipStream_t s) {
+  switch (mv) {
+    case 1: tile_gauss_mfma<T, D, 1><<<grid, 256, 0, s>>>(tab); break;
+    case 2: tile_gauss_mfma<T, D, 2><<<grid, 256, 0, s>>>(tab); break;
+    case 4: tile_gauss_mfma<T, D, 4><<<grid, 256, 0, s>>>(tab); break;
+    default: tile_gauss_mfma<T, D, 0><<<grid, 256, 0, s>>>(tab); break;
+  }
+}
+
+template <typename T>
+int carve_centred(int64_t n, int32_t dpad, Arena& arena, PointSet* out, const T** xc,
+                  const T** xn, const T** xmax) {
+  *xc = arena.take<T>((size_t)n * dpad);
+  *xn = arena.take<T>(n);
+  *xmax = arena.take<T>(1);
+  if (!out->centre) {
+    out->centre = arena.take<double>(64);
+    out->cpart = arena.take<double>(256 * 64);
+  }
+  return KRR_OK;
+}
+
+template <typename T>
+int fill_centred(const double* X, const double* centre, const PointSet& ps, const T* xc,
+                 const T* xn, const T* xmax, hipStream_t s) {
+  const int64_t n = ps.n;
+  zero_scalar<T><<<1, 1, 0, s>>>(const_cast<T*>(xmax));
+  KRR_LAUNCH_CHECK("zero_scalar");
+  if (n == 0) return KRR_OK;
+  double* c = const_cast<double*>(ps.centre);
+  if (centre) {
+    if (centre != c)
+      KRR_TRY(hip_check(hipMemcpyAsync(c, centre, sizeof(double) * ps.d, hipMemcpyDeviceToDevice, s),
+                        "centre copy"));
+  } else {
+    KRR_TRY(compute_centre(X, n, ps.d, c, ps.cpart, s));
+  }
+  pack_centred<T><<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(X, n, ps.d, ps.dpad, c,
+                                                             const_cast<T*>(xc), const_cast<T*>(xn),
+                                                             const_cast<T*>(xmax));
+  KRR_LAUNCH_CHECK("pack_centred");
+  return KRR_OK;
+}
+
+template <typename T>
+size_t g_scratch_bytes(int64_t nr, int64_t nc) {
+  GSplit sp = g_split(nr, nc);
+  Arena a;
+  a.take<T>((size_t)std::max<int64_t>(nc, 1) * 16);
+  a.take<double>((size_t)sp.nsplit * std::max<int64_t>(nr, 1) * 16);
+  return a.used;
+}
+
+template <typename T>
+int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T* cxc,
+              const T* cxn, const T* cxmax, int64_t nr, int64_t nc, int dpad, VecView V, int c0,
+              int mc, Arena& scratch, GJob<T>* out, hipStream_t s) {
+  GSplit sp = g_split(nr, nc);
+  T* v = scratch.take<T>((size_t)std::max<int64_t>(nc, 1) * 16);
+  double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
+  if (!scratch.ok()) {
+    set_error("Gaussian MFMA product scratch too small");
+    return KRR_EWORKSPACE;
+  }
+  if (nc > 0) {
+    pack_v16<T><<<(unsigned)ceil_div(nc * 16, 256), 256, 0, s>>>(V, nc, c0, mc, v);
+    KRR_LAUNCH_CHECK("pack_v16");
+  }
+  const double s_nat = 1.0 / (2.0 * sigma * sigma);
+  GJob<T>& j = *out;
+  j.xc = rxc;
+  j.xn = rxn;
+  j.xmax = rxmax;
+  j.ymax = cxmax;
+  j.yc = cxc;
+  j.yn = cxn;
+  j.v = v;
+  j.part = part;
+  j.nr = nr;
+  j.nc = nc;
+  j.per = sp.per;
+  j.item0 = 0;
+  // FP32 exponents are in base 2 (v_exp_f32)
+  j.s = std::is_same<T, float>::value ? (T)(1.4426950408889634 * s_nat) : (T)s_nat;
+  j.s_nat = s_nat;
+  j.nsplit = sp.nsplit;
+  j.M = mc;
+  j.dpad = dpad;
+  return KRR_OK;
+}
+
+template <typename T>
+int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
+  for (int D : {4, 8, 16, 20, 24, 32, 48, 64}) {
+    for (int mv : {1, 2, 4, 0}) {
+      std::vector<GJob<T>> sel;
+      for (const GJob<T>& j : jobs)
+        if (j.dpad == D && g_variant(j.M) == mv) sel.push_back(j);
+      for (size_t j0 = 0; j0 < sel.size(); j0 += kMaxGJobs) {
+        GTable<T> tab{};
+        int64_t total = 0;
+        int nj = 0;
+        for (size_t j = j0; j < sel.size() && nj < kMaxGJobs; ++j, ++nj) {
+          tab.job[nj] = sel[j];
+          tab.job[nj].item0 = total;
+          total += ceil_div(sel[j].nr, (int64_t)4 * 16 * kRTg) * sel[j].nsplit;
+        }
+        tab.njobs = nj;
+        tab.total = total;
+        if (total == 0) continue;
+        const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+        void* tok = tile_timer_start(s);
+        switch (D) {
+          case 4: launch_d<T, 4>(mv, grid, tab, s); break;
+          case 8: launch_d<T, 8>(mv, grid, tab, s); break;
+          case 16: launch_d<T, 16>(mv, grid, tab, s); break;
+          case 20: launch_d<T, 20>(mv, grid, tab, s); break;
+          case 24: launch_d<T, 24>(mv, grid, tab, s); break;
+          case 32: launch_d<T, 32>(mv, grid, tab, s); break;
+          case 48: launch_d<T, 48>(mv, grid, tab, s); break;
+          default: launch_d<T, 64>(mv, grid, tab, s); break;
+        }
+        KRR_LAUNCH_CHECK("tile_gauss_mfma");
+        // the direct tile serves the jobs the MFMA tile skipped (the choice is
+        // made on the device, so the launch stays asynchronous)
+        switch (D) {
+          case 4: tile_gauss_direct<T, 4><<<grid, 256, 0, s>>>(tab); break;
+          case 8: tile_gauss_direct<T, 8><<<grid, 256, 0, s>>>(tab); break;
+          case 16: tile_gauss_direct<T, 16><<<grid, 256, 0, s>>>(tab); break;
+          case 20: tile_gauss_direct<T, 20><<<grid, 256, 0, s>>>(tab); break;
+          case 24: tile_gauss_direct<T, 24><<<grid, 256, 0, s>>>(tab); break;
+          case 32: tile_gauss_direct<T, 32><<<grid, 256, 0, s>>>(tab); break;
+          case 48: tile_gauss_direct<T, 48><<<grid, 256, 0, s>>>(tab); break;
+          default: tile_gauss_direct<T, 64><<<grid, 256, 0, s>>>(tab); break;
+        }
+        KRR_LAUNCH_CHECK("tile_gauss_direct");
+        tile_timer_stop(tok, s);
+      }
+    }
+  }
+  return KRR_OK;
+}
+
+}  // namespace
+
+int carve_f64c(int64_t n, int32_t dpad, Arena& arena, PointSet* out) {
+  return carve_centred<double>(n, dpad, arena, out, &out->xc64, &out->xn64, &out->xmax64);
+}
+int fill_f64c(const double* X, const double* centre, const PointSet& ps, hipStream_t s) {
+  return fill_centred<double>(X, centre, ps, ps.xc64, ps.xn64, ps.xmax64, s);
+}
+int carve_f32c(int64_t n, int32_t dpad, Arena& arena, PointSet* out) {
+  return carve_centred<float>(n, dpad, arena, out, &out->xc32, &out->xn32, &out->xmax32);
+}
+int fill_f32c(const double* X, const double* centre, const PointSet& ps, hipStream_t s) {
+  return fill_centred<float>(X, centre, ps, ps.xc32, ps.xn32, ps.xmax32, s);
+}
+
+size_t product_f64mfma_scratch_bytes(int64_t nr, int64_t nc) { return g_scratch_bytes<double>(nr, nc); }
+size_t product_f32mfma_scratch_bytes(int64_t nr, int64_t nc) { return g_scratch_bytes<float>(nr, nc); }
+
+int f64_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
+                Arena& scratch, F64Job* out, hipStream_t s) {
+  if (!rows.xc64 || !cols.xc64 || rows.dpad != cols.dpad) {
+    set_error("FP64 Gaussian product: centred layouts missing or inconsistent");
+    return KRR_EINVAL;
+  }
+  return g_prepare<double>(sigma, rows.xc64, rows.xn64, rows.xmax64, cols.xc64, cols.xn64,
+                           cols.xmax64, rows.n, cols.n, rows.dpad, V, c0, mc, scratch, out, s);
+}
+int f32_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
+                Arena& scratch, F32Job* out, hipStream_t s) {
+  if (!rows.xc32 || !cols.xc32 || rows.dpad != cols.dpad) {
+    set_error("FP32 Gaussian product: centred layouts missing or inconsistent");
+    return KRR_EINVAL;
+  }
+  return g_prepare<float>(sigma, rows.xc32, rows.xn32, rows.xmax32, cols.xc32, cols.xn32,
+                          cols.xmax32, rows.n, cols.n, rows.dpad, V, c0, mc, scratch, out, s);
+}
+int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s) { return g_launch<double>(jobs, s); }
+int f32_launch(const std::vector<F32Job>& jobs, hipStream_t s) { return g_launch<float>(jobs, s); }
+
+}  // namespace krr

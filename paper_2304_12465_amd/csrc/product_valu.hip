@@ -544,6 +544,7 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
   }
   out->x32 = arena.take<float>((size_t)n * D);
   if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) KRR_TRY(carve_mixed(n, d, arena, out));
+  if (prec == KRR_FP32 && kind == KRR_GAUSSIAN) KRR_TRY(carve_f32c(n, D, arena, out));
   if (kind == KRR_LAPLACE) {
     out->qbits = quant_bits(D);
     out->xq = arena.take<uint32_t>((size_t)n * D);
@@ -595,7 +596,7 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     set_error("fill_points: layout not carved");
     return KRR_EINVAL;
   }
-  // FP32 points are not centred (VALU tiles use direct differences)
+  // uncentred FP32 copy (KRILL's sketch); Gaussian tiles use the centred copy
   pack_pts<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(X, n, ps.d, D, nullptr,
                                                                 const_cast<float*>(ps.x32));
   KRR_LAUNCH_CHECK("pack_pts<float>");
@@ -614,7 +615,7 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     return KRR_OK;
   }
   if (prec == KRR_MIXED) return fill_mixed(X, shared, ps, s);
-  return KRR_OK;
+  return fill_f32c(X, shared, ps, s);  // FP32 Gaussian: centred MFMA layout
 }
 
 int pack_points(krr_kernel_kind kind, krr_precision prec, const double* X, int64_t n, int32_t d,
@@ -640,6 +641,7 @@ size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t
   a.take<double>((size_t)ns * std::max<int64_t>(nr, 1) * M);
   if (prec == KRR_MIXED) return std::max(a.used, product_mfma_scratch_bytes(nr, nc));
   if (prec == KRR_FP64) return std::max(a.used, product_f64mfma_scratch_bytes(nr, nc));
+  if (prec == KRR_FP32) return std::max(a.used, product_f32mfma_scratch_bytes(nr, nc));
   return a.used;
 }
 
@@ -701,6 +703,7 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
     };
     std::vector<MfmaJob> mjobs;
     std::vector<F64Job> fjobs;
+    std::vector<F32Job> gjobs;
     std::vector<int> mreq;
     struct Pending {
       int q;
@@ -723,6 +726,13 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
         KRR_TRY(f64_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &fj, s));
         pend.push_back(Pending{q, fj.part, nc > 0 ? fj.nsplit : 0, 16, mc, true});
         if (nc > 0) fjobs.push_back(fj);
+        continue;
+      }
+      if (r.prec == KRR_FP32 && r.kind == KRR_GAUSSIAN) {
+        F32Job gj;
+        KRR_TRY(f32_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &gj, s));
+        pend.push_back(Pending{q, gj.part, nc > 0 ? gj.nsplit : 0, 16, mc, true});
+        if (nc > 0) gjobs.push_back(gj);
         continue;
       }
       if (r.prec == KRR_MIXED && r.kind == KRR_GAUSSIAN) {
@@ -755,8 +765,7 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
         pack_vec<double><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(r.V, nc, c0, mc, M, (double*)vp);
         KRR_LAUNCH_CHECK("pack_vec");
         const double sc64 = r.kind == KRR_LAPLACE ? -1.0 / r.sigma : -1.0 / (2.0 * r.sigma * r.sigma);
-        void* fn = r.kind == KRR_LAPLACE ? pick_d<KRR_LAPLACE, double>(D, M)
-                                         : pick_d<KRR_GAUSSIAN, double>(D, M);
+        void* fn = pick_d<KRR_LAPLACE, double>(D, M);  // Gaussian FP64 runs on the MFMA tile
         TileJob<double> j{};
         j.Xr = r.rows->x64;
         j.Xc = r.cols->x64;
@@ -771,18 +780,14 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       } else {
         pack_vec<float><<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(r.V, nc, c0, mc, M, (float*)vp);
         KRR_LAUNCH_CHECK("pack_vec");
-        const bool quant = r.kind == KRR_LAPLACE;
-        if (quant && (!r.rows->xq || !r.cols->xq || r.rows->qp != r.cols->qp)) {
-          // rows and columns must share one quantisation (same qp buffer or
-          // identical copies): the row set's parameters are used
-          if (!r.rows->xq || !r.cols->xq) {
-            set_error("Laplace FP32 tiles: quantised layout missing");
-            return KRR_EINVAL;
-          }
+        // Laplace under FP32 / MIXED: rows and columns share one quantisation
+        // (the same qp buffer or identical copies); the row set's is used
+        if (!r.rows->xq || !r.cols->xq) {
+          set_error("Laplace FP32 tiles: quantised layout missing");
+          return KRR_EINVAL;
         }
-        const float sc32 = (float)(r.kind == KRR_LAPLACE ? -log2e / r.sigma
-                                                         : -log2e / (2.0 * r.sigma * r.sigma));
-        void* fn = quant ? pickq_d(D, M) : pick_d<KRR_GAUSSIAN, float>(D, M);
+        const float sc32 = (float)(-log2e / r.sigma);
+        void* fn = pickq_d(D, M);  // Gaussian FP32 runs on the MFMA tile
         TileJob<float> j{};
         j.Qr = r.rows->xq;
         j.Qc = r.cols->xq;
@@ -805,6 +810,7 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
     }
     if (!mjobs.empty()) KRR_TRY(mfma_launch(mjobs, s));
     if (!fjobs.empty()) KRR_TRY(f64_launch(fjobs, s));
+    if (!gjobs.empty()) KRR_TRY(f32_launch(gjobs, s));
     for (const Pending& pd : pend) {
       const ProductReq& r = reqs[pd.q];
       const int64_t nr = r.rows->n;

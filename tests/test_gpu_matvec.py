@@ -76,16 +76,19 @@ def test_multiple_rhs(m):
             check(kind, prec, Xr, Xc, V, sigma=3.0)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sigma", [1e-8, 0.05, 0.4, 3.0, 1e3])
-def test_fp64_gaussian_exponent_range(sigma):
-    # exponents from 0 (coincident points) down past the FP64 underflow
-    # threshold (exp(-745) = 0): covers the table-driven exp's whole range
+def test_gaussian_exponent_range(prec, sigma):
+    # exponents from 0 (coincident points) down past the underflow threshold
+    # (FP64: exp(-745) = 0): covers the table-driven exp's whole range, and
+    # the small bandwidths route the MFMA jobs to the direct-difference tile
     g = np.random.default_rng(11)
     X = g.standard_normal((900, 6))
     X[100:150] = X[0]  # duplicates: exponent exactly 0 after centring
     V = g.standard_normal((900, 3))
-    check(0, 0, X, X, V, sigma=sigma)
-    check(0, 0, X, X, V[:, :1], sigma=sigma, shift=0.5)
+    check(0, prec, X, X, V, sigma=sigma)
+    check(0, prec, X, X, V[:, :1], sigma=sigma, shift=0.5)
+    check(0, prec, X, X, np.hstack([V, V, V]), sigma=sigma)  # 9 rhs: E.V on the MFMA
 
 
 def test_rectangular_shapes_and_edges():
