@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-baseline", action="store_true", help="c5: skip the one-at-a-time run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--fp32", action="store_true",
+                    help="c3 --product-only: FP32 tiles instead of MIXED")
     ap.add_argument("--product-only", action="store_true",
                     help="only run 5 launches of the headline product (for counter runs)")
     return ap.parse_args()

@@ -88,7 +88,8 @@ def c3(a, b, torch, synth):
     Y = torch.from_numpy(p.Y).cuda()
     m = p.Y.shape[1]
     if a.product_only:
-        ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)
+        prec = b.FP32 if a.fp32 else b.MIXED
+        ms = _product_rate(b, torch, p.kind, p.sigma, prec, X, m)
         print(json.dumps({"product_ms": ms, "entries_per_launch": N * N}), flush=True)
         return
     ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)

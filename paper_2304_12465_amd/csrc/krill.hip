@@ -472,7 +472,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
   // 5. P = B^T B + H, 6. C = chol(P) (lower factor L, P = L L^T, C = L^T)
   KRR_TRY(hip_check(hipMemcpyAsync(P.C, P.H, sizeof(double) * k * k, hipMemcpyDeviceToDevice, s),
                     "P = H"));
-  KRR_TRY(gemm_f64_ex(true, false, k, k, ds, 1.0, w.B, k, w.B, k, 1.0, P.C, k, s, &P.scratch));
+  // lower-triangle tiles only: the Cholesky reads nothing above the diagonal
+  KRR_TRY(gemm_f64_ex(true, false, k, k, ds, 1.0, w.B, k, w.B, k, 1.0, P.C, k, s, &P.scratch, true));
   KRR_TRY(potrf_lower(k, P.C, k, w.ints + 1, s));
   int info = 0;
   KRR_TRY(hip_check(hipMemcpyAsync(&info, w.ints + 1, sizeof(int), hipMemcpyDeviceToHost, s), "info"));
@@ -481,12 +482,12 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     set_error("Cholesky of the KRILL matrix failed at column %d", info);
     return KRR_ENOTSPD;
   }
-  // 7. L^{-1} by a blocked forward solve on the identity: each apply of
+  // 7. L^{-1} by a right-looking blocked solve on the identity: each apply of
   // P^{-1} = L^{-T} L^{-1} is then two dense k x k products streamed from
   // HBM instead of two sequential triangular solves
   set_identity<<<(unsigned)ceil_div(k * k, 256), 256, 0, s>>>(P.Linv, k);
   KRR_LAUNCH_CHECK("set_identity");
-  KRR_TRY(trsm_lower_left(k, k, P.C, k, P.Linv, k, s));
+  KRR_TRY(tri_inv_lower(k, P.C, k, P.Linv, k, s));
   KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
   P.build_seconds = std::chrono::duration<double>(clk::now() - t0).count();
   return KRR_OK;

@@ -17,13 +17,18 @@ size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K);
 // As gemm_f64; a_trans = true reads A as K x M (C = A^T op(B)).
 int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, double alpha,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                int64_t ldc, hipStream_t s, Arena* scratch = nullptr);
+                int64_t ldc, hipStream_t s, Arena* scratch = nullptr, bool lower_only = false);
 
 // In-place lower Cholesky of the n x n SPD matrix A (row-major, lda):
 // A = L L^T, L in the lower triangle (the strict upper triangle is left
 // holding values of no meaning).  `info` (device int) receives 0 or the
 // 1-based column of the first non-positive pivot.
 int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s);
+
+// X <- L^{-1} for lower-triangular L (n x n, lda); X (n x n, ldx) must hold
+// the identity on entry.
+int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ldx,
+                  hipStream_t s);
 
 // Solves L X = B in place for lower-triangular L (n x n, lda) and B
 // (n x ncols, ldb): B <- L^{-1} B.

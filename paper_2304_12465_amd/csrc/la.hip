@@ -25,12 +25,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
                                                        int64_t lda, const double* __restrict__ B,
                                                        int64_t ldb, double beta,
                                                        double* __restrict__ C, int64_t ldc,
-                                                       int64_t kchunk, double* __restrict__ slots) {
+                                                       int64_t kchunk, double* __restrict__ slots,
+                                                       int lower) {
   __shared__ double As[kTile][kPad];  // [m][k]
   __shared__ double Bs[kTile][kPad];  // [n][k]
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
+  if (lower && n0 > m0) return;  // tile strictly above the diagonal: not wanted
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f64x4 acc[2][2];
 #pragma unroll
@@ -114,10 +116,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 // C = sum_z slots[z] (fixed order) + beta C
 __global__ __launch_bounds__(256) void splitk_reduce(const double* __restrict__ slots, int nz,
                                                      int64_t M, int64_t N, double beta,
-                                                     double* __restrict__ C, int64_t ldc) {
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     int lower) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * N) return;
   const int64_t m = t / N, n = t % N;
+  if (lower && n / kTile > m / kTile) return;  // tile skipped by the GEMM
   double v = 0.0;
   for (int z = 0; z < nz; ++z) v += slots[((int64_t)z * M + m) * N + n];
   if (beta != 0.0) v += beta * C[m * ldc + n];
@@ -314,7 +318,7 @@ int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const 
 
 int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, double alpha,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                int64_t ldc, hipStream_t s, Arena* scratch) {
+                int64_t ldc, hipStream_t s, Arena* scratch, bool lower_only) {
   if (M <= 0 || N <= 0) return KRR_OK;
   if (!a_trans && b_trans && M <= 8) {
     const unsigned g = (unsigned)N;
@@ -355,21 +359,22 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
   if (a_trans) {
     if (b_trans)
       gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                       ldc, kchunk, slots);
+                                                       ldc, kchunk, slots, lower_only ? 1 : 0);
     else
       gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, kchunk, slots);
+                                                        ldc, kchunk, slots, lower_only ? 1 : 0);
   } else {
     if (b_trans)
       gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, kchunk, slots);
+                                                        ldc, kchunk, slots, lower_only ? 1 : 0);
     else
       gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                         ldc, kchunk, slots);
+                                                         ldc, kchunk, slots, lower_only ? 1 : 0);
   }
   KRR_LAUNCH_CHECK("gemm_f64");
   if (slots) {
-    splitk_reduce<<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(slots, z, M, N, beta, C, ldc);
+    splitk_reduce<<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(slots, z, M, N, beta, C, ldc,
+                                                                  lower_only ? 1 : 0);
     KRR_LAUNCH_CHECK("splitk_reduce");
     scratch->used = mark;
   }
@@ -387,11 +392,33 @@ int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s) {
     if (rest > 0) {
       potrf_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(Akk, lda, nb, rest);
       KRR_LAUNCH_CHECK("potrf_panel");
-      // trailing update A22 -= L21 L21^T (full square keeps A22 symmetric)
+      // trailing update A22 -= L21 L21^T on the lower-triangle tiles (the
+      // factorisation reads nothing above the diagonal)
       double* L21 = A + (k + nb) * lda + k;
       double* A22 = A + (k + nb) * lda + (k + nb);
-      KRR_TRY(gemm_f64(true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, s));
+      KRR_TRY(gemm_f64_ex(false, true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, s,
+                          nullptr, true));
     }
+  }
+  return KRR_OK;
+}
+
+int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ldx,
+                  hipStream_t s) {
+  // right-looking blocked forward substitution on X = I: after block row k
+  // is solved, the rows below are updated at once (one GEMM with many
+  // tiles).  Block row k of L^{-1} is zero right of column k + nb, so every
+  // step touches only columns 0 .. k + nb.
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    const int64_t ncols = k + nb;
+    trsm_diag<<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb, X + k * ldx,
+                                                             ldx, ncols);
+    KRR_LAUNCH_CHECK("trsm_diag");
+    const int64_t below = n - k - nb;
+    if (below > 0)
+      KRR_TRY(gemm_f64(false, below, ncols, nb, -1.0, L + (k + nb) * lda + k, lda, X + k * ldx,
+                       ldx, 1.0, X + (k + nb) * ldx, ldx, s));
   }
   return KRR_OK;
 }
