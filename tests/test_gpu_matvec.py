@@ -7,11 +7,13 @@ oracle, element by element, with tolerances derived from the arithmetic:
   point sets, so each entry's exponent is off by at most
   dpad * range / ((2^qbits - 1) sigma) plus FP32 rounding of the sum, scale
   and exp (test_laplace_quantised_wide_range checks this bound directly).
-* FP32 tiles: entries carry a relative error of about
-  |arg| (d + 2) 2^-24 + 2 ulp(exp) <= 0.37 (d + 2) 6e-8 absolute, V is rounded
+* FP32 Gaussian tiles (f32 MFMA on centred points): each exponent carries at
+  most (d + 3) 2^-24 s (max ||x||^2 + max ||y||^2) from the expansion, which
+  the tile's routing guard keeps <= 200 * 2^-24 = 1.2e-5 (larger bounds take
+  direct differences, |arg| (d + 2) 2^-24), plus 2 ulp of exp; V is rounded
   to FP32 (6e-8 relative) and at most 256 terms are summed in FP32 before
   the FP64 fold (<= 256 * 6e-8 relative to the partial sum of |terms|).
-  The bound used is 2e-5 * sum_j |K_ij| |V_jc|.
+  The bound used for all FP32 tiles is 2e-5 * sum_j |K_ij| |V_jc|.
 """
 import numpy as np
 import pytest
@@ -223,6 +225,22 @@ def test_mixed_full_size_uniform_sampled_rows():
     scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
     tol = mixed_tol(p.X[rows], p.X, p.sigma)
     assert np.all(np.abs(W[rows] - ref) <= tol * scale), np.max(np.abs(W[rows] - ref) / scale)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gaussian_full_size_sampled_rows(prec):
+    # The 10^12-entry d = 32, m = 8 product on the FP64 / FP32 MFMA tiles:
+    # 48 sampled rows against the oracle at the product tolerances.
+    p = synth.c3()
+    g = np.random.default_rng(13)
+    V = g.standard_normal((p.X.shape[0], 8))
+    W = run(0, prec, p.X, p.X, V, p.sigma, shift=p.mu)
+    rows = np.sort(g.choice(p.X.shape[0], 48, replace=False))
+    Kb = OK.block(p.X[rows], p.X, 0, p.sigma)
+    ref = Kb @ V + p.mu * V[rows]
+    scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
+    err = np.abs(W[rows] - ref)
+    assert np.all(err <= TOL[prec] * scale), np.max(err / scale)
 
 
 def test_laplace_quantised_wide_range():
