@@ -13,7 +13,9 @@ oracle, element by element, with tolerances derived from the arithmetic:
   direct differences, |arg| (d + 2) 2^-24), plus 2 ulp of exp; V is rounded
   to FP32 (6e-8 relative) and at most 256 terms are summed in FP32 before
   the FP64 fold (<= 256 * 6e-8 relative to the partial sum of |terms|).
-  The bound used for all FP32 tiles is 2e-5 * sum_j |K_ij| |V_jc|.
+  The bounds used: FP32 Laplace tiles 2e-5 * sum_j |K_ij| |V_jc|; FP32
+  Gaussian tiles 3e-5 (1.2e-5 expansion + 1.5e-5 FP32 sums + exp and V
+  rounding).
 """
 import numpy as np
 import pytest
@@ -24,6 +26,11 @@ import synth
 
 pytestmark = pytest.mark.gpu
 TOL = {0: 1e-13, 1: 2e-5}
+TOL_GAUSS32 = 3e-5
+
+
+def tol(kind, prec):
+    return TOL_GAUSS32 if (kind == 0 and prec == 1) else TOL[prec]
 
 
 def B():
@@ -50,7 +57,7 @@ def check(kind, prec, Xr, Xc, V, sigma, shift=0.0):
     ref = Kb @ V2 + shift * V2 if shift else Kb @ V2
     scale = np.abs(Kb) @ np.abs(V2) + abs(shift) * np.abs(V2 if shift else 0)
     err = np.abs(W2 - ref)
-    bound = TOL[prec] * scale + 1e-300
+    bound = tol(kind, prec) * scale + 1e-300
     worst = float(np.max(err / bound)) if err.size else 0.0
     assert np.all(err <= bound), f"worst err/bound = {worst}"
     return worst
@@ -240,7 +247,7 @@ def test_gaussian_full_size_sampled_rows(prec):
     ref = Kb @ V + p.mu * V[rows]
     scale = np.abs(Kb) @ np.abs(V) + p.mu * np.abs(V[rows])
     err = np.abs(W[rows] - ref)
-    assert np.all(err <= TOL[prec] * scale), np.max(err / scale)
+    assert np.all(err <= tol(0, prec) * scale), np.max(err / scale)
 
 
 def test_laplace_quantised_wide_range():
