@@ -303,6 +303,46 @@ __global__ __launch_bounds__(256) void gemm_rowdot(int64_t M, int64_t N, int64_t
   }
 }
 
+// C[M x N] = alpha A B + beta C for M <= MM rows of A (row-major M x K) and
+// B row-major K x N: a workgroup owns 64 output columns; its four waves take
+// the k = w mod 4 rows of B (each load of a wave reads 64 consecutive
+// columns) and their partial sums are added in wave order through LDS.
+// Used for the second product of each preconditioner apply on large
+// problems (one row per right-hand side, B = Q^T).
+template <int MM>
+__global__ __launch_bounds__(256) void gemm_colsum(int64_t M, int64_t N, int64_t K, double alpha,
+                                                   const double* __restrict__ A, int64_t lda,
+                                                   const double* __restrict__ B, int64_t ldb,
+                                                   double beta, double* __restrict__ C,
+                                                   int64_t ldc) {
+  __shared__ double red[4][MM][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t jj = j < N ? j : N - 1;
+  double acc[MM];
+#pragma unroll
+  for (int c = 0; c < MM; ++c) acc[c] = 0.0;
+#pragma unroll 4
+  for (int64_t k = wave; k < K; k += 4) {
+    const double bv = B[k * ldb + jj];
+#pragma unroll
+    for (int c = 0; c < MM; ++c)
+      if (c < M) acc[c] = __builtin_fma(A[c * lda + k], bv, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < MM; ++c) red[wave][c][lane] = acc[c];
+  __syncthreads();
+  if (wave == 0 && j < N) {
+#pragma unroll
+    for (int c = 0; c < MM; ++c)
+      if (c < M) {
+        const double v = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
+        const double old = beta != 0.0 ? beta * C[c * ldc + j] : 0.0;
+        C[c * ldc + j] = alpha * v + old;
+      }
+  }
+}
+
 }  // namespace
 
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
@@ -320,7 +360,22 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, hipStream_t s, Arena* scratch, bool lower_only) {
   if (M <= 0 || N <= 0) return KRR_OK;
-  if (!a_trans && b_trans && M <= 8) {
+  if (!a_trans && !b_trans && M <= 8 && !lower_only && N >= 65536) {
+    // enough columns for ~1000 workgroups; below that the tiled GEMM (with
+    // its K split) keeps more of the chip busy
+    const unsigned g = (unsigned)ceil_div(N, 64);
+    if (M == 1)
+      gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (M <= 2)
+      gemm_colsum<2><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (M <= 4)
+      gemm_colsum<4><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+      gemm_colsum<8><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    KRR_LAUNCH_CHECK("gemm_colsum");
+    return KRR_OK;
+  }
+  if (!a_trans && b_trans && M <= 8 && !lower_only) {
     const unsigned g = (unsigned)N;
     if (M == 1)
       gemm_rowdot<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
