@@ -334,7 +334,7 @@ int krill_layout(Arena& a, Precond& P) {
                              product_scratch_bytes(P.prec, k, N, P.m_max));
   const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, k, P.m_max),
                                product_scratch_bytes(KRR_FP64, k, N, P.m_max));
-  const size_t gs = std::max(gemm_scratch_bytes(k, k, P.sketch_rows),
+  const size_t gs = std::max(gemm_scratch_bytes(k, k, P.sketch_rows, true),
                              gemm_scratch_bytes(P.m_max, k, k));
   const size_t sb = std::max(std::max(ps, ps64), gs) + kAlign;
   char* sc = a.take<char>(sb);

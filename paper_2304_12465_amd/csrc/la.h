@@ -13,7 +13,7 @@ namespace krr {
 int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
              hipStream_t s, Arena* scratch = nullptr);
-size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K);
+size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K, bool lower_only = false);
 // As gemm_f64; a_trans = true reads A as K x M (C = A^T op(B)).
 int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, double alpha,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,

@@ -11,92 +11,232 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;   // output tile per workgroup (64 x 64)
-constexpr int kKStep = 16;  // K slice staged in LDS per iteration
-constexpr int kPad = 17;    // LDS row pitch in doubles
+constexpr int kKStep = 16;          // K slice staged in LDS per iteration
+constexpr int kPad = kKStep + 1;    // LDS row pitch in doubles
+constexpr int kUE = kKStep / 4;     // entries per thread and operand per 64 tile rows
 
 // v_mfma_f64_16x16x4f64 operand layout (wave64):
 //   A (16 x 4): lane l holds A[l % 16][l / 16]
 //   B (4 x 16): lane l holds B[l / 16][l % 16]
 //   D (16 x 16): lane l, element t holds D[4 t + l / 16][l % 16]
-template <bool AT, bool BT>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
+//
+// Output tiles in the order the workgroups take them: column by column
+// (all row tiles of one column tile together), or, for the lower triangle
+// of a square product, row by row over the tiles on or below the diagonal.
+// Consecutive workgroups go to the eight XCDs in turn (workgroup L to XCD
+// L mod 8), so each XCD is given a contiguous run of that order: tiles that
+// read the same operand slab then share one L2.
+__host__ __device__ inline int64_t tile_count(int64_t gx, int64_t gy, int lower) {
+  return lower ? gy * (gy + 1) / 2 : gx * gy;
+}
+__device__ inline bool tile_of(int64_t L, int64_t gx, int64_t gy, int lower, int64_t& ty,
+                               int64_t& tx) {
+  const int64_t T = tile_count(gx, gy, lower);
+  const int64_t per = (T + 7) / 8;
+  const int64_t t = (L % 8) * per + L / 8;
+  if (t >= T) return false;
+  if (lower) {
+    int64_t y = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (y * (y + 1) / 2 > t) --y;
+    while ((y + 1) * (y + 2) / 2 <= t) ++y;
+    ty = y;
+    tx = t - y * (y + 1) / 2;
+  } else {
+    tx = t / gy;
+    ty = t % gy;
+  }
+  return true;
+}
+
+// C = alpha op(A) op(B) + beta C on a TM x TN output tile per workgroup
+// (TM, TN in {64, 128}); the four waves split it 2 x 2, each wave holding
+// (TM / 32) x (TN / 32) MFMA accumulators.  A 128 x 128 tile does twice
+// the MFMA work of a 64 x 64 tile per byte staged, which the FP64 matrix
+// rate needs when the operands stream from memory.
+template <bool AT, bool BT, int TM, int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM * TN > 64 * 64 ? 2 : 4)))
+void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
                                                        double alpha, const double* __restrict__ A,
                                                        int64_t lda, const double* __restrict__ B,
                                                        int64_t ldb, double beta,
                                                        double* __restrict__ C, int64_t ldc,
                                                        int64_t kchunk, double* __restrict__ slots,
                                                        int lower) {
-  __shared__ double As[kTile][kPad];  // [m][k]
-  __shared__ double Bs[kTile][kPad];  // [n][k]
+  constexpr int FM = TM / 32, FN = TN / 32;  // MFMA blocks per wave
+  constexpr int RA = TM / 64, RB = TN / 64;  // 64-row loader passes
+  __shared__ double As[TM][kPad];  // [m][k]
+  __shared__ double Bs[TN][kPad];  // [n][k]
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
-  if (lower && n0 > m0) return;  // tile strictly above the diagonal: not wanted
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f64x4 acc[2][2];
+  int64_t ty, tx;
+  if (!tile_of(blockIdx.x, (N + TN - 1) / TN, (M + TM - 1) / TM, lower, ty, tx)) return;
+  const int64_t m0 = ty * TM, n0 = tx * TN;
+  const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
+  f64x4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  const int ar = tid >> 2, ak = (tid & 3) * 4;  // A tile loader: 64 rows x 16 k
+  // Tile loaders: per K step every thread fetches kKStep / 4 entries of A per
+  // 64 tile rows, and the same of B, all in flight at once; the next step's
+  // loads are issued before this step's MFMAs.  A row-major operand reads
+  // through per-thread row pointers clamped to the last row (the values of
+  // rows past the end are replaced by zero), so every step but the last
+  // needs no per-element checks; a K-major operand takes that path when its
+  // whole tile is in range.  The last step of a K range, and K-major tiles
+  // at the edge, clamp every address instead.
+  // row-major operand: 64 rows x kKStep k; K-major operand: kKStep k x 64 rows
+  const int ar = tid >> 2, ak = (tid & 3) * kUE;
+  const int kk = tid / (64 / kUE), mn = (tid % (64 / kUE)) * kUE;
   // split K: this workgroup covers [kb, ke); the bounds checks below use ke
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const double* arow[RA];
+  bool aok[RA];
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const int64_t gm = m0 + 64 * r + ar;
+    aok[r] = gm < M;
+    arow[r] = A + (aok[r] ? gm : M - 1) * lda;
+  }
+  const double* brow[RB];
+  bool bok[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int64_t gn = n0 + 64 * r + ar;
+    bok[r] = gn < N;
+    brow[r] = B + (bok[r] ? gn : N - 1) * ldb;
+  }
+  const bool afull = !AT || m0 + TM <= M, bfull = BT || n0 + TN <= N;
+  // raw loaded values; the zero mask (bit 4 r + u, A in the low half, B in
+  // the high half) is applied only when they are stored to LDS, so nothing
+  // waits on the loads before the MFMAs of the current step
+  double ra[RA][kUE], rb[RB][kUE];
+  uint32_t okm = 0;
+  auto fetch = [&](int64_t k0) {
+    okm = 0;
+    if (k0 + kKStep <= ke && afull && bfull) {
+#pragma unroll
+      for (int r = 0; r < RA; ++r)
+#pragma unroll
+        for (int u = 0; u < kUE; ++u) {
+          if (!AT) {
+            ra[r][u] = arow[r][k0 + ak + u];
+            okm |= (aok[r] ? 1u : 0u) << (kUE * r + u);
+          } else {
+            ra[r][u] = A[(k0 + kk) * lda + m0 + 64 * r + mn + u];
+            okm |= 1u << (kUE * r + u);
+          }
+        }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int u = 0; u < kUE; ++u) {
+          if (BT) {
+            rb[r][u] = brow[r][k0 + ak + u];
+            okm |= (bok[r] ? 1u : 0u) << (16 + kUE * r + u);
+          } else {
+            rb[r][u] = B[(k0 + kk) * ldb + n0 + 64 * r + mn + u];
+            okm |= 1u << (16 + kUE * r + u);
+          }
+        }
+      return;
+    }
+    // past the end of the range (the last prefetch) every k reads ke - 1
+#pragma unroll
+    for (int r = 0; r < RA; ++r)
+#pragma unroll
+      for (int u = 0; u < kUE; ++u) {
+        int64_t gm, gk;
+        if (!AT) {
+          gm = m0 + 64 * r + ar;
+          gk = k0 + ak + u;
+        } else {
+          gm = m0 + 64 * r + mn + u;
+          gk = k0 + kk;
+        }
+        const bool ok = gm < M && gk < ke;
+        const int64_t cm = gm < M ? gm : M - 1, ck = gk < ke ? gk : ke - 1;
+        ra[r][u] = AT ? A[ck * lda + cm] : A[cm * lda + ck];
+        okm |= (ok ? 1u : 0u) << (kUE * r + u);
+      }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int u = 0; u < kUE; ++u) {
+        int64_t gn, gk;
+        if (BT) {
+          gn = n0 + 64 * r + ar;
+          gk = k0 + ak + u;
+        } else {
+          gn = n0 + 64 * r + mn + u;
+          gk = k0 + kk;
+        }
+        const bool ok = gn < N && gk < ke;
+        const int64_t cn = gn < N ? gn : N - 1, ck = gk < ke ? gk : ke - 1;
+        rb[r][u] = BT ? B[cn * ldb + ck] : B[ck * ldb + cn];
+        okm |= (ok ? 1u : 0u) << (16 + kUE * r + u);
+      }
+  };
+  if (kb < ke) fetch(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
-    if (!AT) {
-      const int64_t gm = m0 + ar;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t gk = k0 + ak + u;
-        As[ar][ak + u] = (gm < M && gk < ke) ? A[gm * lda + gk] : 0.0;
-      }
-    } else {
-      const int kk = tid >> 4, mm = (tid & 15) * 4;  // A is K x M: 16 k x 64 m
-      const int64_t gk = k0 + kk;
+    for (int r = 0; r < RA; ++r)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t gm = m0 + mm + u;
-        As[mm + u][kk] = (gk < ke && gm < M) ? A[gk * lda + gm] : 0.0;
+      for (int u = 0; u < kUE; ++u) {
+        const double v = (okm >> (kUE * r + u)) & 1u ? ra[r][u] : 0.0;
+        if (!AT)
+          As[64 * r + ar][ak + u] = v;
+        else
+          As[64 * r + mn + u][kk] = v;
       }
-    }
-    if (BT) {
-      const int64_t gn = n0 + ar;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t gk = k0 + ak + u;
-        Bs[ar][ak + u] = (gn < N && gk < ke) ? B[gn * ldb + gk] : 0.0;
-      }
-    } else {
-      const int kk = tid >> 4, nn = (tid & 15) * 4;  // 16 k x 64 n
-      const int64_t gk = k0 + kk;
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t gn = n0 + nn + u;
-        Bs[nn + u][kk] = (gk < ke && gn < N) ? B[gk * ldb + gn] : 0.0;
+      for (int u = 0; u < kUE; ++u) {
+        const double v = (okm >> (16 + kUE * r + u)) & 1u ? rb[r][u] : 0.0;
+        if (BT)
+          Bs[64 * r + ar][ak + u] = v;
+        else
+          Bs[64 * r + mn + u][kk] = v;
       }
-    }
     __syncthreads();
+    fetch(k0 + kKStep);  // clamped addresses: harmless past the end
 #pragma unroll
     for (int ks = 0; ks < kKStep; ks += 4) {
-      double a[2], b[2];
+      double a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int i = 0; i < FM; ++i) a[i] = As[wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int j = 0; j < FN; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // epilogue, one block row at a time: the old values of C are fetched
+  // together (clamped addresses) before any store
+  const bool use_c = !slots && beta != 0.0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i) {
+    double old[FN][4] = {};
+    if (use_c) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t gm = m0 + wm + i * 16 + 4 * t + (lane >> 4);
+          const int64_t gn = n0 + wn + j * 16 + (lane & 15);
+          const int64_t cm = gm < M ? gm : M - 1, cn = gn < N ? gn : N - 1;
+          old[j][t] = C[cm * ldc + cn];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t gm = m0 + wm + i * 16 + 4 * t + (lane >> 4);
@@ -106,73 +246,120 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
           if (slots) {
             slots[((int64_t)blockIdx.z * M + gm) * N + gn] = v;
           } else {
-            if (beta != 0.0) v += beta * C[gm * ldc + gn];
+            if (use_c) v += beta * old[j][t];
             C[gm * ldc + gn] = v;
           }
         }
       }
+  }
 }
 
-// C = sum_z slots[z] (fixed order) + beta C
+// C = sum_z slots[z] (fixed order) + beta C; with `lower`, only the square
+// tiles (tile x tile) on or below the diagonal, as the GEMM wrote them
 __global__ __launch_bounds__(256) void splitk_reduce(const double* __restrict__ slots, int nz,
                                                      int64_t M, int64_t N, double beta,
                                                      double* __restrict__ C, int64_t ldc,
-                                                     int lower) {
+                                                     int lower, int tile) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * N) return;
   const int64_t m = t / N, n = t % N;
-  if (lower && n / kTile > m / kTile) return;  // tile skipped by the GEMM
+  if (lower && n / tile > m / tile) return;  // tile skipped by the GEMM
   double v = 0.0;
   for (int z = 0; z < nz; ++z) v += slots[((int64_t)z * M + m) * N + n];
   if (beta != 0.0) v += beta * C[m * ldc + n];
   C[m * ldc + n] = v;
 }
 
-int choose_ksplit(int64_t M, int64_t N, int64_t K) {
-  const int64_t tiles = ceil_div(M, kTile) * ceil_div(N, kTile);
-  if (tiles >= 512 || K < 8192) return 1;
-  int64_t z = ceil_div(1024, tiles);
+// Output tile shape: 128 x 128 for large products, 128 x 64 when all of a
+// short M (65 .. 128 rows) fits one tile row over many columns (each
+// column block of B is then read once), else 64 x 64.
+struct TileShape {
+  int tm, tn;
+};
+TileShape choose_tile(int64_t M, int64_t N, int64_t K, bool lower) {
+  if (M >= 2048 && N >= 2048 && K >= 1024) return {128, 128};
+  if (!lower && M > 64 && M <= 128 && N >= 8192) return {128, 64};
+  return {64, 64};
+}
+
+// K split for outputs with few tiles and a long K: as many K slices as fit
+// one full round of resident workgroups on every XCD (each XCD takes a
+// contiguous run of ceil(tiles / 8) tiles per slice; a CU holds four 64 x 64
+// or two larger tiles), so no second, mostly idle round follows.
+int choose_ksplit(int64_t M, int64_t N, int64_t K, bool lower) {
+  const TileShape ts = choose_tile(M, N, K, lower);
+  const int64_t gx = ceil_div(N, ts.tn), gy = ceil_div(M, ts.tm);
+  const int64_t per_xcd = ceil_div(tile_count(gx, gy, lower ? 1 : 0), 8);
+  const int64_t slots = 32 * (ts.tm == 64 ? 4 : 2);  // per XCD
+  if (per_xcd >= slots / 2 || K < 8192) return 1;
+  int64_t z = slots / per_xcd;
   z = std::min<int64_t>(z, K / 2048);
   return (int)std::max<int64_t>(1, std::min<int64_t>(z, 4096));
 }
 
+template <bool AT, bool BT>
+void launch_gemm(TileShape ts, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K,
+                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double beta, double* C, int64_t ldc, int64_t kchunk, double* slots, int lower) {
+  if (ts.tm == 128 && ts.tn == 128)
+    gemm_f64_kernel<AT, BT, 128, 128><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta,
+                                                            C, ldc, kchunk, slots, lower);
+  else if (ts.tm == 128)
+    gemm_f64_kernel<AT, BT, 128, 64><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                           ldc, kchunk, slots, lower);
+  else
+    gemm_f64_kernel<AT, BT, 64, 64><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                          ldc, kchunk, slots, lower);
+}
+
 constexpr int kNb = 64;  // block size of the blocked factorisation and solves
 
-// Cholesky of one nb x nb diagonal block held in LDS (right-looking).
-__global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ A, int64_t lda, int nb,
-                                                  int64_t col0, int* __restrict__ info) {
-  __shared__ double T[kNb][kNb + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = A[(e / nb) * lda + e % nb];
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    if (tid == 0) {
-      const double p = T[k][k];
-      if (!(p > 0.0)) {
-        if (!bad) bad = (int)(col0 + k + 1);
-        T[k][k] = 1.0;  // keep going with finite values; info reports the failure
-      } else {
-        T[k][k] = sqrt(p);
-      }
+// Cholesky of one nb x nb diagonal block (nb <= kNb), right-looking, in
+// one wave: lane i keeps row i in registers (the loops are unrolled, so
+// every index is a constant); the multipliers of column k pass through LDS
+// to all lanes.  Whole rows are read and written: the entries above the
+// diagonal start with whatever A holds there and collect values of no
+// meaning, but no entry on or below the diagonal ever reads one (row i's
+// entry j <= i takes the multipliers of columns k < j from rows i and j).
+// Rows and columns past nb stay zero and take pivot 1.  A non-positive
+// pivot is replaced by 1 so the sweep stays finite; `info` reports the
+// first one.
+__global__ __launch_bounds__(64) void potrf_diag(double* __restrict__ A, int64_t lda, int nb,
+                                                 int64_t col0, int* __restrict__ info) {
+  __shared__ double colv[kNb];
+  const int i = threadIdx.x;
+  const bool row = i < nb;
+  double t[kNb];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) t[j] = (row && j < nb) ? A[i * lda + j] : 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) {
+    __builtin_amdgcn_sched_barrier(0);  // one column at a time: bounds the live LDS reads
+    const double p = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(t[k]), k),
+                                      __builtin_amdgcn_readlane(__double2loint(t[k]), k));
+    double piv = 1.0;
+    if (k < nb) {
+      if (p > 0.0)
+        piv = sqrt(p);
+      else if (!bad)
+        bad = (int)(col0 + k + 1);
     }
+    // row k gets p / piv on its diagonal (sqrt(p) to within one rounding)
+    const double l = t[k] / piv;
+    t[k] = l;
+    colv[i] = l;
     __syncthreads();
-    const double piv = T[k][k];
-    for (int i = k + 1 + tid; i < nb; i += blockDim.x) T[i][k] /= piv;
-    __syncthreads();
-    const int rem = nb - k - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) T[i][j] -= T[i][k] * T[j][k];
-    }
+#pragma unroll
+    for (int j = k + 1; j < kNb; ++j) t[j] = __builtin_fma(-l, colv[j], t[j]);
     __syncthreads();
   }
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    if (j <= i) A[i * lda + j] = T[i][j];
+  if (row) {
+#pragma unroll
+    for (int j = 0; j < kNb; ++j)
+      if (j < nb) A[i * lda + j] = t[j];
   }
-  if (tid == 0 && bad && *info == 0) *info = bad;
+  if (i == 0 && bad && *info == 0) *info = bad;
 }
 
 // A lower-triangular nb x nb block (nb <= kNb) staged in LDS, padded to
@@ -228,17 +415,18 @@ __device__ __forceinline__ void store_col(double* __restrict__ base, int64_t str
   for (int q = kNb - 1; q >= 0; --q) base[(int64_t)(q < nb ? q : nb - 1) * stride] = x[q];
 }
 
-// Rows below the diagonal block: L_i = A_i L_kk^{-T}, one thread per row
-// (the row solve is a forward substitution with L_kk).
-__global__ __launch_bounds__(256) void potrf_panel(double* __restrict__ A, int64_t lda, int nb,
+// X <- X L^{-T} for X (nrows x nb, ld ldx) and an nb x nb (nb <= kNb) lower
+// factor L, one thread per row (the row solve is a forward substitution
+// with L).  In the factorisation X is the panel below the diagonal block.
+__global__ __launch_bounds__(256) void potrf_panel(const double* __restrict__ L, int64_t lda,
+                                                   int nb, double* __restrict__ X, int64_t ldx,
                                                    int64_t nrows) {
   __shared__ double T[kNb][kNb + 1];
   __shared__ double tinv[kNb];
-  // A points at the diagonal block; panel rows start nb rows below
-  stage_tri(A, lda, nb, T, tinv);
+  stage_tri(L, lda, nb, T, tinv);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
-  double* row = A + (nb + r) * lda;
+  double* row = X + r * ldx;
   double x[kNb];
   load_col(row, 1, nb, x);
   tri_forward(T, tinv, x);
@@ -345,8 +533,8 @@ __global__ __launch_bounds__(256) void gemm_colsum(int64_t M, int64_t N, int64_t
 
 }  // namespace
 
-size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K) {
-  const int z = choose_ksplit(M, N, K);
+size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K, bool lower_only) {
+  const int z = choose_ksplit(M, N, K, lower_only);
   return z > 1 ? align_up((size_t)z * M * N * sizeof(double)) : 0;
 }
 
@@ -388,12 +576,18 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
     KRR_LAUNCH_CHECK("gemm_rowdot");
     return KRR_OK;
   }
-  const int64_t gx = ceil_div(N, kTile), gy = ceil_div(M, kTile);
-  if (gy > 65535) {
-    set_error("gemm_f64: M=%lld too large for the grid", (long long)M);
+  const TileShape ts = choose_tile(M, N, K, lower_only);
+  const int64_t gx = ceil_div(N, ts.tn), gy = ceil_div(M, ts.tm);
+  if (lower_only && M != N) {
+    set_error("gemm_f64: the lower-triangle product needs a square C (M=%lld, N=%lld)",
+              (long long)M, (long long)N);
     return KRR_EINVAL;
   }
-  int z = scratch ? choose_ksplit(M, N, K) : 1;
+  if (tile_count(gx, gy, lower_only ? 1 : 0) > ((int64_t)1 << 30)) {
+    set_error("gemm_f64: %lld x %lld output too large for the grid", (long long)M, (long long)N);
+    return KRR_EINVAL;
+  }
+  int z = scratch ? choose_ksplit(M, N, K, lower_only) : 1;
   double* slots = nullptr;
   const size_t mark = scratch ? scratch->used : 0;
   if (z > 1) {
@@ -410,47 +604,112 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
     slots = nullptr;
     scratch->used = mark;
   }
-  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)z);
+  const int64_t tiles = tile_count(gx, gy, lower_only ? 1 : 0);
+  dim3 grid((unsigned)(ceil_div(tiles, 8) * 8), 1, (unsigned)z);
+  const int lw = lower_only ? 1 : 0;
   if (a_trans) {
     if (b_trans)
-      gemm_f64_kernel<true, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                       ldc, kchunk, slots, lower_only ? 1 : 0);
+      launch_gemm<true, true>(ts, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                              slots, lw);
     else
-      gemm_f64_kernel<true, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, kchunk, slots, lower_only ? 1 : 0);
+      launch_gemm<true, false>(ts, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                               slots, lw);
   } else {
     if (b_trans)
-      gemm_f64_kernel<false, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                        ldc, kchunk, slots, lower_only ? 1 : 0);
+      launch_gemm<false, true>(ts, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                               slots, lw);
     else
-      gemm_f64_kernel<false, false><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                                         ldc, kchunk, slots, lower_only ? 1 : 0);
+      launch_gemm<false, false>(ts, grid, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                slots, lw);
   }
   KRR_LAUNCH_CHECK("gemm_f64");
   if (slots) {
     splitk_reduce<<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(slots, z, M, N, beta, C, ldc,
-                                                                  lower_only ? 1 : 0);
+                                                                  lw, ts.tm);
     KRR_LAUNCH_CHECK("splitk_reduce");
     scratch->used = mark;
   }
   return KRR_OK;
 }
 
-int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s) {
-  KRR_TRY(hip_check(hipMemsetAsync(info, 0, sizeof(int), s), "potrf info reset"));
+namespace {
+
+constexpr int64_t kNbOuter = 512;  // outer block of the two-level factorisation and solves
+
+// Cholesky of an n x n block (n <= kNbOuter) in kNb steps: diagonal block in
+// one wave, the panel below it row by row, then the lower-triangle trailing
+// update (K = kNb).  col0 is the block's first column in the whole matrix.
+int potrf_block(int64_t n, double* A, int64_t lda, int* info, int64_t col0, hipStream_t s) {
   for (int64_t k = 0; k < n; k += kNb) {
     const int nb = (int)std::min<int64_t>(kNb, n - k);
     double* Akk = A + k * lda + k;
-    potrf_diag<<<1, 256, 0, s>>>(Akk, lda, nb, k, info);
+    potrf_diag<<<1, 64, 0, s>>>(Akk, lda, nb, col0 + k, info);
     KRR_LAUNCH_CHECK("potrf_diag");
     const int64_t rest = n - k - nb;
     if (rest > 0) {
-      potrf_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(Akk, lda, nb, rest);
+      potrf_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(Akk, lda, nb, Akk + nb * lda, lda,
+                                                                 rest);
       KRR_LAUNCH_CHECK("potrf_panel");
-      // trailing update A22 -= L21 L21^T on the lower-triangle tiles (the
-      // factorisation reads nothing above the diagonal)
       double* L21 = A + (k + nb) * lda + k;
       double* A22 = A + (k + nb) * lda + (k + nb);
+      KRR_TRY(gemm_f64_ex(false, true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, s,
+                          nullptr, true));
+    }
+  }
+  return KRR_OK;
+}
+
+// X <- X L^{-T} for X (rows x nb) and the nb x nb lower factor L, left-looking
+// over kNb-column blocks: one GEMM with the columns already solved, then the
+// row-wise substitution.
+int panel_trsm(int64_t rows, int64_t nb, const double* L, int64_t lda, double* X, int64_t ldx,
+               hipStream_t s) {
+  for (int64_t j = 0; j < nb; j += kNb) {
+    const int jb = (int)std::min<int64_t>(kNb, nb - j);
+    if (j > 0)
+      KRR_TRY(gemm_f64(true, rows, jb, j, -1.0, X, ldx, L + j * lda, lda, 1.0, X + j, ldx, s));
+    potrf_panel<<<(unsigned)ceil_div(rows, 256), 256, 0, s>>>(L + j * lda + j, lda, jb, X + j, ldx,
+                                                               rows);
+    KRR_LAUNCH_CHECK("potrf_panel");
+  }
+  return KRR_OK;
+}
+
+// B <- L^{-1} B for an n x n (n <= kNbOuter) lower L, left-looking in kNb
+// steps: B_k -= L[k, 0:k] B[0:k], then the block substitution.
+int trsm_block(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B, int64_t ldb,
+               hipStream_t s) {
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int nb = (int)std::min<int64_t>(kNb, n - k);
+    if (k > 0)
+      KRR_TRY(gemm_f64(false, nb, ncols, k, -1.0, L + k * lda, lda, B, ldb, 1.0, B + k * ldb, ldb,
+                       s));
+    trsm_diag<<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
+                                                                    B + k * ldb, ldb, ncols);
+    KRR_LAUNCH_CHECK("trsm_diag");
+  }
+  return KRR_OK;
+}
+
+}  // namespace
+
+// Two levels of blocking: kNbOuter-wide outer steps whose GEMMs have
+// K = kNbOuter (the MFMA work dominates the C traffic), and kNb-wide inner
+// steps inside each diagonal block.
+
+int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s) {
+  KRR_TRY(hip_check(hipMemsetAsync(info, 0, sizeof(int), s), "potrf info reset"));
+  for (int64_t k = 0; k < n; k += kNbOuter) {
+    const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
+    double* Akk = A + k * lda + k;
+    KRR_TRY(potrf_block(nb, Akk, lda, info, k, s));
+    const int64_t rest = n - k - nb;
+    if (rest > 0) {
+      // panel L21 = A21 L11^{-T}, then A22 -= L21 L21^T on the lower-triangle
+      // tiles (the factorisation reads nothing above the diagonal)
+      double* L21 = A + (k + nb) * lda + k;
+      double* A22 = A + (k + nb) * lda + (k + nb);
+      KRR_TRY(panel_trsm(rest, nb, Akk, lda, L21, lda, s));
       KRR_TRY(gemm_f64_ex(false, true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, s,
                           nullptr, true));
     }
@@ -464,12 +723,10 @@ int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ld
   // is solved, the rows below are updated at once (one GEMM with many
   // tiles).  Block row k of L^{-1} is zero right of column k + nb, so every
   // step touches only columns 0 .. k + nb.
-  for (int64_t k = 0; k < n; k += kNb) {
-    const int nb = (int)std::min<int64_t>(kNb, n - k);
+  for (int64_t k = 0; k < n; k += kNbOuter) {
+    const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
     const int64_t ncols = k + nb;
-    trsm_diag<<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb, X + k * ldx,
-                                                             ldx, ncols);
-    KRR_LAUNCH_CHECK("trsm_diag");
+    KRR_TRY(trsm_block(nb, ncols, L + k * lda + k, lda, X + k * ldx, ldx, s));
     const int64_t below = n - k - nb;
     if (below > 0)
       KRR_TRY(gemm_f64(false, below, ncols, nb, -1.0, L + (k + nb) * lda + k, lda, X + k * ldx,
@@ -481,16 +738,13 @@ int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ld
 int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
                     int64_t ldb, hipStream_t s) {
   if (ncols <= 0 || n <= 0) return KRR_OK;
-  for (int64_t k = 0; k < n; k += kNb) {
-    const int nb = (int)std::min<int64_t>(kNb, n - k);
-    if (k > 0) {
-      // B_k -= L[k, 0:k] B[0:k]
+  for (int64_t k = 0; k < n; k += kNbOuter) {
+    const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
+    // B_k -= L[k, 0:k] B[0:k], then the block solve
+    if (k > 0)
       KRR_TRY(gemm_f64(false, nb, ncols, k, -1.0, L + k * lda, lda, B, ldb, 1.0, B + k * ldb, ldb,
                        s));
-    }
-    trsm_diag<<<(unsigned)ceil_div(ncols, 256), 256, 0, s>>>(L + k * lda + k, lda, nb,
-                                                                    B + k * ldb, ldb, ncols);
-    KRR_LAUNCH_CHECK("trsm_diag");
+    KRR_TRY(trsm_block(nb, ncols, L + k * lda + k, lda, B + k * ldb, ldb, s));
   }
   return KRR_OK;
 }

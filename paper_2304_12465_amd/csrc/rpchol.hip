@@ -184,56 +184,86 @@ __global__ void gather_cols(const double* __restrict__ FT, int64_t ldf, int64_t 
 }
 
 // Pivot-by-pivot Cholesky of G(S',S') with the drop rule, in LDS.
-// One array M holds G in its upper triangle and, transposed in its lower
-// triangle, the rows of R of the accepted pivots: R(acc[a], q) lives at
-// M[q][a] (q >= acc[a] >= a), so each Schur sum reads a contiguous piece of
-// one row (left-looking, terms added in acceptance order).  Outputs the
-// lower factor of the accepted pivots, Lacc = R_acc^T (acc x acc, ld =
-// ldl), the accepted positions and their count.
-__global__ __launch_bounds__(256) void chol_drop(const double* __restrict__ GT, int64_t ldg,
+// One array M holds G in its upper triangle (diagonal included); below the
+// diagonal it holds, transposed, the rows of R of the accepted pivots
+// (R(acc[a], q) at M[q][a], q >= acc[a] >= a) and the running Schur sums
+// S(q3, q2) = sum_a R(a, q3) R(a, q2) at M[q3][q2] for the rows not yet
+// reached (q < q2 < q3); the diagonal sums sit in dsum.  Each accepted
+// pivot adds its rank-1 term to every sum at once (right-looking), so no
+// thread runs a chain as long as the pivot count; each sum still takes its
+// terms in acceptance order, one rounding per product and per addition,
+// which is the left-looking order term for term.  Rows beyond the current
+// pivot never overlap the R columns (a < na <= q < q2).  Outputs the lower
+// factor of the accepted pivots, Lacc = R_acc^T (acc x acc, ld = ldl), the
+// accepted positions and their count.
+constexpr int kCholThreads = 1024;  // 32 x 32 threads over the Schur sums
+static_assert(kBmax <= kCholThreads, "chol_drop: one thread per column");
+__global__ __launch_bounds__(kCholThreads) void chol_drop(const double* __restrict__ GT, int64_t ldg,
                                                  const int64_t* __restrict__ sp, int bp,
                                                  double thresh, double* __restrict__ Lacc,
                                                  int ldl, int* __restrict__ acc_out,
                                                  int* __restrict__ acc_count) {
   __shared__ double M[kBmax][kBmax + 1];
+  __shared__ double dsum[kBmax];
+  __shared__ int64_t spl[kBmax];
   __shared__ int acc[kBmax];
-  __shared__ int nacc;
-  __shared__ int take;
-  __shared__ double rqq;
   const int tid = threadIdx.x;
-  for (int e = tid; e < bp * bp; e += blockDim.x) {
-    const int q = e / bp, q2 = e % bp;
-    M[q][q2] = GT[(int64_t)q * ldg + sp[q2]];  // G(S'_q, S'_q2)
+  for (int q = tid; q < bp; q += blockDim.x) {
+    spl[q] = sp[q];
+    dsum[q] = 0.0;
   }
-  if (tid == 0) nacc = 0;
   __syncthreads();
-  for (int q = 0; q < bp; ++q) {
-    const int na = nacc;
-    if (tid == 0) {
-      double s = 0.0;
-      for (int a = 0; a < na; ++a) s = __dadd_rn(s, __dmul_rn(M[q][a], M[q][a]));
-      s = __dsub_rn(M[q][q], s);
-      take = s > thresh ? 1 : 0;
-      if (take) rqq = sqrt(s);
+  // G(S'_q, S'_q2) for q2 >= q, zero below; eight loads in flight per thread
+  const int nn = bp * bp;
+  for (int e0 = 0; e0 < nn; e0 += 8 * kCholThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kCholThreads + tid;
+      const int ec = e < nn ? e : nn - 1;
+      v[u] = GT[(int64_t)(ec / bp) * ldg + spl[ec % bp]];
     }
-    __syncthreads();
-    if (take) {
-      const double r = rqq;
-      for (int q2 = q + 1 + tid; q2 < bp; q2 += blockDim.x) {
-        double s = 0.0;
-        for (int a = 0; a < na; ++a) s = __dadd_rn(s, __dmul_rn(M[q][a], M[q2][a]));
-        M[q2][na] = __ddiv_rn(__dsub_rn(M[q][q2], s), r);
-      }
-      __syncthreads();  // every read of M[q][q] and row q is done
-      if (tid == 0) {
-        M[q][na] = r;
-        acc[na] = q;
-        nacc = na + 1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kCholThreads + tid;
+      if (e < nn) {
+        const int q = e / bp, q2 = e % bp;
+        M[q][q2] = q2 >= q ? v[u] : 0.0;
       }
     }
-    __syncthreads();
   }
-  const int na = nacc;
+  __syncthreads();
+  const int ty = tid >> 5, tx = tid & 31;
+  int na = 0;
+  for (int q = 0; q < bp; ++q) {
+    // every thread reads the same finished values, so all take the same
+    // branch
+    const double sd = __dsub_rn(M[q][q], dsum[q]);
+    if (!(sd > thresh)) continue;
+    const double r = sqrt(sd);
+    for (int q2 = q + 1 + tid; q2 < bp; q2 += blockDim.x)
+      M[q2][na] = __ddiv_rn(__dsub_rn(M[q][q2], M[q2][q]), r);  // M[q2][q] = S(q2, q)
+    __syncthreads();
+    // rank-1 update of the sums of the rows after q: thread (ty, tx) takes
+    // rows i = q + 1 + ty (+32) and, in each, columns j = q + 1 + tx (+32)
+    // up to i
+    for (int i = q + 1 + ty; i < bp; i += 32) {
+      const double ri = M[i][na];
+      for (int j = q + 1 + tx; j <= i; j += 32) {
+        const double t = __dmul_rn(ri, M[j][na]);
+        if (j == i)
+          dsum[i] = __dadd_rn(dsum[i], t);
+        else
+          M[i][j] = __dadd_rn(M[i][j], t);
+      }
+    }
+    if (tid == 0) {
+      M[q][na] = r;
+      acc[na] = q;
+    }
+    __syncthreads();
+    ++na;
+  }
   // Lacc[a][b] = R(acc[b], acc[a]) = M[acc[a]][b] for b <= a
   for (int e = tid; e < na * na; e += blockDim.x) {
     const int a = e / na, b2 = e % na;
@@ -321,7 +351,7 @@ int rpchol_layout(Arena& a, Precond& P) {
   const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max);
   const size_t ps64 = product_scratch_bytes(KRR_FP64, N, N, P.m_max);
   const size_t gs = std::max(gemm_scratch_bytes(P.m_max, P.r_req, N),
-                             std::max(gemm_scratch_bytes(P.r_req, P.r_req, N),
+                             std::max(gemm_scratch_bytes(P.r_req, P.r_req, N, true),
                                       gemm_scratch_bytes(P.B, N, P.r_req)));
   const size_t sb = std::max(std::max(ps, ps64), gs) + kAlign;
   char* sc = a.take<char>(sb);
@@ -396,7 +426,7 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
       KRR_LAUNCH_CHECK("gather_cols");
       KRR_TRY(gemm_f64(false, bp, N, i, -1.0, w.Fs, i, P.QT, N, 1.0, w.GT, N, s, &P.scratch));
     }
-    chol_drop<<<1, 256, 0, s>>>(w.GT, N, w.sp, bp, thresh, w.Lacc, kBmax, w.acc, w.ints);
+    chol_drop<<<1, kCholThreads, 0, s>>>(w.GT, N, w.sp, bp, thresh, w.Lacc, kBmax, w.acc, w.ints);
     KRR_LAUNCH_CHECK("chol_drop");
     KRR_TRY(hip_check(hipMemcpyAsync(hints, w.ints, sizeof(int), hipMemcpyDeviceToHost, s), "acc"));
     KRR_TRY(hip_check(hipMemcpyAsync(hacc, w.acc, sizeof(int) * bp, hipMemcpyDeviceToHost, s),
@@ -421,8 +451,11 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   P.rank = (int32_t)i;
   const int64_t rk = i;
   if (rk > 0) {
-    // core = mu I + F^T F, its Cholesky factor L, then Q^T = L^{-1} F^T in place
-    KRR_TRY(gemm_f64(true, rk, rk, N, 1.0, P.QT, N, P.QT, N, 0.0, P.core, rk, s, &P.scratch));
+    // core = mu I + F^T F (its lower triangle: the Cholesky factorisation
+    // reads nothing else), its Cholesky factor L, then Q^T = L^{-1} F^T in
+    // place
+    KRR_TRY(gemm_f64_ex(false, true, rk, rk, N, 1.0, P.QT, N, P.QT, N, 0.0, P.core, rk, s,
+                        &P.scratch, true));
     add_diag<<<(unsigned)ceil_div(rk, 256), 256, 0, s>>>(P.core, rk, rk, P.mu);
     KRR_LAUNCH_CHECK("add_diag");
     KRR_TRY(potrf_lower(rk, P.core, rk, w.ints + 1, s));

@@ -79,6 +79,30 @@ def test_sketch_H_and_factor(prec, tol):
         np.testing.assert_allclose(L @ L.T, kr.P, rtol=0, atol=1e-10 * np.abs(kr.P).max())
 
 
+def test_factor_and_apply_past_one_outer_block():
+    # k = 1,100 centres: the Cholesky factor and the inverse of L are built
+    # in two levels of blocks (outer steps of 512 with a ragged 76-wide last
+    # step), so the outer panel solves and trailing updates all run.
+    # sigma = 0.3 keeps kappa(P) near 2e4, so the apply bound below is tight.
+    p = small(n=6000, k=1100)
+    p.sigma = 0.3
+    P = build(p, 0, m_max=2)
+    k = p.centers
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, np.array(P.pivots()), sketch_rows=p.sketch_rows,
+                   zeta=p.zeta, seed=p.algo_seed)
+    L = B().krill_export(P, 4, (k, k), torch.float64).cpu().numpy()
+    assert np.all(np.triu(L, 1) == 0)
+    np.testing.assert_allclose(L @ L.T, kr.P, rtol=0, atol=1e-10 * np.abs(kr.P).max())
+    # P^{-1} z through the explicit inverse of L: forward error of an
+    # SPD solve, 100 k eps kappa(P)
+    Z = np.random.default_rng(11).standard_normal((k, 2))
+    got = P.apply(T(Z)).cpu().numpy()
+    ref = np.linalg.solve(kr.P, Z)
+    kap = np.linalg.cond(kr.P)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 100 * k * 2.0 ** -52 * kap, (rel, kap)
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 4e-5)])
 def test_restricted_operator(prec, tol):
     p = small()

@@ -71,6 +71,23 @@ def test_pivots_and_factor_match_oracle_c1(kind):
     assert rel <= 100 * len(S) * EPS * kap, (rel, kap)
 
 
+def test_pivots_and_factor_match_oracle_wide():
+    # N = 10,000 columns and rank 300 in blocks of 100: the block updates
+    # G^T -= F_S F^T run as one 128-row tile row over the columns, and
+    # F^T F as a K-split product of 128 x 128 tiles (lower triangle only)
+    p = synth.c2(n=10_000)
+    r = 300
+    P = build(p, 0, r=r)
+    F_o, piv_o = oracle_factor(p, r=r)
+    piv = P.pivots()
+    assert piv == piv_o, f"first mismatch at {first_mismatch(piv, piv_o)}"
+    F = P.factor().cpu().numpy().T
+    S = np.array(piv_o)
+    kap = np.linalg.cond(OK.block(p.X[S], p.X[S], p.kind, p.sigma))
+    rel = np.linalg.norm(F - F_o) / np.linalg.norm(F_o)
+    assert rel <= 100 * len(S) * EPS * kap, (rel, kap)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_apply_matches_svd_form(prec):
     p = synth.c1(n=1500)
