@@ -16,6 +16,7 @@
 // signed sum of kernel rows, so the build is bitwise reproducible.
 #include "solver.h"
 #include "exp64.h"
+#include "gauss_mfma.h"
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -199,11 +200,20 @@ __global__ __launch_bounds__(256) void seg_sort(const int64_t* __restrict__ offs
   }
 }
 
+// row_of[e] = r for every entry of row r (one workgroup per row)
+__global__ void entry_rows(const int64_t* __restrict__ offs, int* __restrict__ row_of) {
+  const int64_t r = blockIdx.x;
+  for (int64_t e = offs[r] + threadIdx.x; e < offs[r + 1]; e += blockDim.x) row_of[e] = (int)r;
+}
+
 // ---- sketch B = Phi A(:,S) ---------------------------------------------
 // Lanes own centres (R per lane, in registers); the workgroup walks a range
 // of sketch rows; each row's entries (point index and sign) are
 // wave-uniform, read with scalar loads, and their points enter the VALU as
 // SGPR operands.  B[r][c] = zeta^{-1/2} sum_e s_e K(x_{j_e}, c).
+// Gaussian sketches run here only when the matrix-core sketch cannot serve
+// them to the precision's accuracy (guard: the largest centred squared norms
+// of points and centres; null for Laplace).
 template <int KIND, typename T, int D, int R>
 __global__ __launch_bounds__(256) void sketch_apply(const T* __restrict__ C, int64_t k,
                                                     const T* __restrict__ X,
@@ -211,8 +221,11 @@ __global__ __launch_bounds__(256) void sketch_apply(const T* __restrict__ C, int
                                                     const int64_t* __restrict__ entries,
                                                     int64_t d_rows, int rows_per_wg, T scale,
                                                     double inv_sqrt_zeta,
-                                                    double* __restrict__ Bout) {
+                                                    double* __restrict__ Bout,
+                                                    const T* __restrict__ gmax_x,
+                                                    const T* __restrict__ gmax_c, double s_nat) {
   __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 sketches)
+  if (gmax_x && !gauss_expansion_too_coarse<T>(s_nat, (double)*gmax_x, (double)*gmax_c, D)) return;
   if constexpr (sizeof(T) == 8) {
     exp64_table_fill(etab);
     __syncthreads();
@@ -449,23 +462,42 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     const int rows_per_wg = 8;
     dim3 g((unsigned)ceil_div(k, 256 * R), (unsigned)ceil_div(ds, rows_per_wg));
     const double log2e = 1.4426950408889634;
+    const double izeta = 1.0 / std::sqrt((double)z);
+    const bool gauss = P.kind == KRR_GAUSSIAN;
+    const double s_nat = 1.0 / (2.0 * P.sigma * P.sigma);
+    // Gaussian: the matrix-core sketch, unless its device-side guard sends
+    // the problem to the direct differences below (each kernel skips the
+    // other's case)
+    if (gauss) {
+      // the unsorted entries are no longer needed: their space holds row_of
+      int* row_of = reinterpret_cast<int*>(w.entries);
+      entry_rows<<<(unsigned)ds, 256, 0, s>>>(w.offs, row_of);
+      KRR_LAUNCH_CHECK("entry_rows");
+      KRR_TRY(sketch_gauss_mfma_launch(P.prec == KRR_FP64 ? KRR_FP64 : KRR_FP32, P.sigma,
+                                       P.prec == KRR_FP64 ? P.pts64 : P.pts,
+                                       P.prec == KRR_FP64 ? P.cpts64 : P.cpts, w.offs, w.tmp,
+                                       row_of, ds, izeta, w.B, s));
+    }
     if (P.prec == KRR_FP64) {
-      const double sc = P.kind == KRR_LAPLACE ? -1.0 / P.sigma : -1.0 / (2.0 * P.sigma * P.sigma);
+      const double sc = P.kind == KRR_LAPLACE ? -1.0 / P.sigma : -s_nat;
       void* fn = P.kind == KRR_LAPLACE ? sketch_pick<KRR_LAPLACE, double>(D)
                                        : sketch_pick<KRR_GAUSSIAN, double>(D);
       using Fn = void (*)(const double*, int64_t, const double*, const int64_t*, const int64_t*,
-                          int64_t, int, double, double, double*);
-      reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(P.cpts64.x64, k, P.pts64.x64, w.offs, w.tmp, ds,
-                                                 rows_per_wg, sc, 1.0 / std::sqrt((double)z), w.B);
+                          int64_t, int, double, double, double*, const double*, const double*,
+                          double);
+      reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(
+          P.cpts64.x64, k, P.pts64.x64, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
+          gauss ? P.pts64.xmax64 : nullptr, gauss ? P.cpts64.xmax64 : nullptr, s_nat);
     } else {
-      const float sc = (float)(P.kind == KRR_LAPLACE ? -log2e / P.sigma
-                                                     : -log2e / (2.0 * P.sigma * P.sigma));
+      const float sc = (float)(P.kind == KRR_LAPLACE ? -log2e / P.sigma : -log2e * s_nat);
       void* fn = P.kind == KRR_LAPLACE ? sketch_pick<KRR_LAPLACE, float>(D)
                                        : sketch_pick<KRR_GAUSSIAN, float>(D);
       using Fn = void (*)(const float*, int64_t, const float*, const int64_t*, const int64_t*,
-                          int64_t, int, float, double, double*);
-      reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(P.cpts.x32, k, P.pts.x32, w.offs, w.tmp, ds,
-                                                 rows_per_wg, sc, 1.0 / std::sqrt((double)z), w.B);
+                          int64_t, int, float, double, double*, const float*, const float*,
+                          double);
+      reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(
+          P.cpts.x32, k, P.pts.x32, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
+          gauss ? P.pts.xmax32 : nullptr, gauss ? P.cpts.xmax32 : nullptr, s_nat);
     }
     KRR_LAUNCH_CHECK("sketch_apply");
   }

@@ -79,6 +79,18 @@ const double* shared_params(krr_kernel_kind kind, krr_precision prec, const Poin
 int pack_points(krr_kernel_kind kind, krr_precision prec, const double* X, int64_t n, int32_t d,
                 const double* centre, Arena& arena, PointSet* out, hipStream_t s);
 
+// KRILL sketch B = Phi A(:, S) for the Gaussian kernel on the matrix cores
+// (FP64 or FP32 tiles, FP64 sums): B[r][c] = inv_sqrt_zeta * sum over the
+// nonzeros of row r (entries[offs[r] .. offs[r+1]), each 2 j + (sign < 0),
+// ascending j; row_of[e] = r) of sign K(x_j, s_c).  pts: all points, cpts:
+// the centres, both packed centred with one centre.  The kernel checks the
+// expansion guard on the device and does nothing when the direct-difference
+// sketch must serve the problem instead.
+int sketch_gauss_mfma_launch(krr_precision prec, double sigma, const PointSet& pts,
+                             const PointSet& cpts, const int64_t* offs, const int64_t* entries,
+                             const int* row_of, int64_t ds, double inv_sqrt_zeta, double* B,
+                             hipStream_t s);
+
 // Scratch bytes for product(rows=nr, cols=nc, m).
 size_t product_scratch_bytes(krr_precision prec, int64_t nr, int64_t nc, int32_t m);
 

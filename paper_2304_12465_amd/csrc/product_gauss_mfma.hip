@@ -15,7 +15,7 @@
 // every 256 columns); per-split partials go to fixed slots (bitwise
 // reproducible).
 #include "product.h"
-#include "exp64.h"
+#include "gauss_mfma.h"
 #include <algorithm>
 #include <type_traits>
 
@@ -23,56 +23,13 @@ namespace krr {
 
 namespace {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 constexpr int kRTg = 2;      // 16-row tiles per wave
 constexpr int kColsG = 64;   // columns per LDS chunk (four 16-column tiles)
 constexpr int kFoldG = 4;    // FP32: chunks per FP64 fold (256 columns)
 
-// Operand layouts (wave64, lane l, g = l / 16, li = l % 16):
-//   A (16 x 4): lane l holds A[li][g];  B (4 x 16): lane l holds B[g][li]
-//   D (16 x 16), element t of lane l:
-//     v_mfma_f64_16x16x4f64: D[4 t + g][li]
-//     v_mfma_f32_16x16x4f32: D[4 g + t][li]
-// col(t, g) names that row index of D.
-template <typename T>
-struct GT;
-template <>
-struct GT<double> {
-  typedef f64x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int col(int t, int g) { return 4 * t + g; }
-  static __device__ __forceinline__ double ex(double x, const double* tab) { return exp64(x, tab); }
-  static constexpr double kFar = -1.0e300;   // exponent of columns past the range
-  // expansion error bound (d + 3) eps s (max||x||^2 + max||y||^2) at most
-  // 400 eps = 8.9e-14, else direct differences
-  static constexpr double kBound = 400.0;
-};
-template <>
-struct GT<float> {
-  typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int col(int t, int g) { return 4 * g + t; }
-  static __device__ __forceinline__ float ex(float x, const double*) {
-    return __builtin_amdgcn_exp2f(x);
-  }
-  static constexpr float kFar = -3.0e38f;
-  // 200 eps_32 = 1.2e-5 relative per entry at most (the FP32 tile tolerance
-  // is 2e-5 of sum |K||V|), else direct differences
-  static constexpr double kBound = 200.0;
-};
-
-__device__ __forceinline__ double fma_g(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_g(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
 template <typename T>
 __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
-  return J.s_nat * ((double)*J.xmax + (double)*J.ymax) * (J.dpad + 3) > GT<T>::kBound;
+  return gauss_expansion_too_coarse<T>(J.s_nat, (double)*J.xmax, (double)*J.ymax, J.dpad);
 }
 
 // Per-thread staging of the next 64-column chunk (points, exponent offsets
