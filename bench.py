@@ -66,6 +66,8 @@ def parse():
                          "workloads for the design notes")
     ap.add_argument("--requests", type=int, default=64, help="c5: number of served requests")
     ap.add_argument("--no-baseline", action="store_true", help="c5: skip the one-at-a-time run")
+    ap.add_argument("--build-workers", type=int, default=1,
+                    help="c5: preconditioner builds on this many worker threads (0: in the loop)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     ap.add_argument("--fp32", action="store_true",

@@ -10,12 +10,20 @@ products of all active requests share kernel launches.  A request leaves as
 soon as its solve finishes, freeing memory for the next ones.  Latency is
 completion time minus arrival time (queueing included).
 
+With ``build_workers > 0`` a request's preconditioner build (a chain of
+small, latency-bound kernels with host synchronisations) runs on a worker
+thread while the main loop keeps stepping the admitted solves; the GPU
+backend gives each worker thread a stream of its own, so the build's
+kernels interleave with the product tiles of the running solves.
+
 The scheduling policy lives here; every numerical step runs in the HIP
 library behind a backend object.  ``GpuBackend`` is the product backend;
 tests may plug in a fake backend with the same four methods.
 """
+import threading
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor, wait, FIRST_COMPLETED
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -51,6 +59,18 @@ class GpuBackend:
         self.max_iter = max_iter
         self.dev = torch.device(device)
         self.keep_beta = keep_beta
+        self._local = threading.local()
+
+    def _build_stream(self):
+        """The main thread builds on its current stream; every other thread
+        on a stream of its own (default priority)."""
+        if threading.current_thread() is threading.main_thread():
+            return None
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            st = self.torch.cuda.Stream(device=self.dev)
+            self._local.stream = st
+        return st
 
     def footprint(self, prob):
         N, d = prob.X.shape
@@ -64,6 +84,16 @@ class GpuBackend:
         return float(N) * N * (d + prob.Y.shape[1])
 
     def start(self, prob):
+        st = self._build_stream()
+        if st is not None:
+            with self.torch.cuda.stream(st):
+                return self._start(prob)
+        return self._start(prob)
+
+    def _start(self, prob):
+        # the build and the solve's first step end with a synchronisation of
+        # this stream, so the handle is ready for steps on any stream; the
+        # request's arrays are freed only after its solve has synchronised
         t = lambda a: self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
         X, Y = t(prob.X), t(prob.Y)
         P = self.b.rpchol_build(prob.kind, prob.sigma, self.prec, X, prob.mu, prob.rank,
@@ -86,9 +116,11 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, hbm_budget, max_active=64, clock=time.perf_counter,
-                 sleep=time.sleep, on_finish=None, order="fifo"):
+                 sleep=time.sleep, on_finish=None, order="fifo", build_workers=0):
         """order: "fifo" admits in arrival order; "sjf" admits the waiting
-        request with the smallest estimated work (backend.cost) first."""
+        request with the smallest estimated work (backend.cost) first.
+        build_workers: 0 builds in the loop; n > 0 builds on n worker
+        threads while the admitted solves keep stepping."""
         self.be = backend
         self.budget = hbm_budget
         self.max_active = max_active
@@ -96,28 +128,60 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.on_finish = on_finish  # called with each finished Result
+        self.build_workers = build_workers
 
     def run(self, stream, make_problem):
         """Serves ``stream`` (objects with .rid and .arrival in seconds);
         ``make_problem(req)`` gives its arrays.  Returns {rid: Result}."""
+        pool = ThreadPoolExecutor(self.build_workers) if self.build_workers > 0 else None
+        try:
+            return self._run(stream, make_problem, pool)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
+
+    def _run(self, stream, make_problem, pool):
         pending = deque(sorted(stream, key=lambda r: r.arrival))
         results = {r.rid: Result(r.rid, r.arrival) for r in stream}
         problems = {}
         waiting = deque()
+        building = []  # (req, future, bytes): builds on worker threads
         active = []  # (req, handle, bytes)
         used = 0
         t0 = self.clock()
-        while pending or waiting or active:
+
+        def fail_build(req, need, e):
+            nonlocal used
+            r = results[req.rid]
+            r.status, r.error = "failed", str(e)
+            r.finished = self.clock() - t0
+            used -= need
+            problems.pop(req.rid, None)
+            if self.on_finish:
+                self.on_finish(r)
+
+        while pending or waiting or active or building:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 req = pending.popleft()
                 problems[req.rid] = make_problem(req)
                 waiting.append(req)
+            # finished background builds join the stepped solves
+            still = []
+            for req, fut, need in building:
+                if not fut.done():
+                    still.append((req, fut, need))
+                    continue
+                try:
+                    active.append((req, fut.result(), need))
+                except Exception as e:  # a failed build isolates this request only
+                    fail_build(req, need, e)
+            building = still
             # admission while the footprint fits: arrival order, or smallest
             # estimated work first
             if self.order == "sjf" and len(waiting) > 1:
                 waiting = deque(sorted(waiting, key=lambda q: self.be.cost(problems[q.rid])))
-            while waiting and len(active) < self.max_active:
+            while waiting and len(active) + len(building) < self.max_active:
                 req = waiting[0]
                 prob = problems[req.rid]
                 need = self.be.footprint(prob)
@@ -132,16 +196,20 @@ class Server:
                 waiting.popleft()
                 r = results[req.rid]
                 r.admitted = self.clock() - t0
+                used += need
+                if pool is not None:
+                    building.append((req, pool.submit(self.be.start, prob), need))
+                    continue
                 try:
                     h = self.be.start(prob)
                 except Exception as e:  # a failed build isolates this request only
-                    r.status, r.error = "failed", str(e)
-                    r.finished = self.clock() - t0
+                    fail_build(req, need, e)
                     continue
                 active.append((req, h, need))
-                used += need
             if not active:
-                if pending and not waiting:
+                if building:
+                    wait([f for _, f, _ in building], timeout=0.05, return_when=FIRST_COMPLETED)
+                elif pending and not waiting:
                     self.sleep(max(0.0, min(0.05, pending[0].arrival - (self.clock() - t0))))
                 continue
             states = self.be.step([h for _, h, _ in active])

@@ -80,13 +80,16 @@ def test_failing_request_is_isolated():
         assert np.array_equal(beta.cpu().numpy(), ba)
 
 
-def test_small_served_stream_matches_alone():
+@pytest.mark.parametrize("workers", [0, 1])
+def test_small_served_stream_matches_alone(workers):
+    # workers = 1: builds run on a worker thread and its own stream while the
+    # admitted solves keep stepping; the results do not depend on that
     reqs = [synth.Request(i, 0.02 * i, n, d, kind, m, min(200, n // 20), 8000 + i)
             for i, (n, d, kind, m) in enumerate([(4000, 8, 0, 2), (6000, 16, 1, 1),
                                                  (3000, 32, 0, 4), (8000, 8, 1, 3),
                                                  (5000, 16, 0, 1), (2000, 32, 1, 2)])]
     be = GpuBackend(2, tol=1e-6, max_iter=400, keep_beta=True)
-    srv = Server(be, hbm_budget=4 << 30, max_active=4)
+    srv = Server(be, hbm_budget=4 << 30, max_active=4, build_workers=workers)
     res = srv.run(reqs, synth.c5_problem)
     s = summarize(res)
     assert s["done"] == len(reqs), [r.error for r in res.values()]

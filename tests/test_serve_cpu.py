@@ -65,11 +65,12 @@ class FakeBackend:
         self.used -= h["p"]["fp"]
 
 
-def run(problems, arrivals, budget, max_active=64, order="fifo"):
+def run(problems, arrivals, budget, max_active=64, order="fifo", build_workers=0):
     clk = FakeClock()
     be = FakeBackend(clk)
     reqs = [Req(i, a) for i, a in enumerate(arrivals)]
-    srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep, order=order)
+    srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep, order=order,
+                 build_workers=build_workers)
     res = srv.run(reqs, lambda r: dict(problems[r.rid], rid=r.rid))
     return res, be
 
@@ -137,3 +138,19 @@ def test_shortest_first_admission_lowers_mean_latency():
     mean = lambda res: sum(r.latency for r in res.values()) / len(res)
     assert mean(sjf) < mean(fifo)
     assert be.started[:2] == [4, 2]  # smallest work first
+
+
+def test_background_builds_keep_budget_and_isolate_failures():
+    # builds on a worker thread: admission still counts the footprint at
+    # once, the budget and the active limit hold, a failed build is isolated
+    probs = [dict(fp=30, steps=4 + i % 3) for i in range(9)]
+    probs[4] = dict(fp=30, steps=4, fail="build")
+    probs[6] = dict(fp=30, steps=5, fail="solve")
+    res, be = run(probs, [0.004 * i for i in range(9)], budget=100, max_active=3,
+                  build_workers=1)
+    assert be.max_used <= 100
+    assert res[4].status == "failed" and "build" in res[4].error
+    assert res[6].status == "failed"
+    assert all(res[i].status == "done" for i in range(9) if i not in (4, 6))
+    assert be.used == 0
+    assert be.started == sorted(be.started)  # FIFO admission, one worker
