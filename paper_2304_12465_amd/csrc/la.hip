@@ -55,13 +55,10 @@ __device__ inline bool tile_of(int64_t L, int64_t gx, int64_t gy, int lower, int
 // rate needs when the operands stream from memory.
 template <bool AT, bool BT, int TM, int TN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM * TN > 64 * 64 ? 2 : 4)))
-void gemm_f64_kernel(int64_t M, int64_t N, int64_t K,
-                                                       double alpha, const double* __restrict__ A,
-                                                       int64_t lda, const double* __restrict__ B,
-                                                       int64_t ldb, double beta,
-                                                       double* __restrict__ C, int64_t ldc,
-                                                       int64_t kchunk, double* __restrict__ slots,
-                                                       int lower) {
+void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
+                     int64_t lda, const double* __restrict__ B, int64_t ldb, double beta,
+                     double* __restrict__ C, int64_t ldc, int64_t kchunk,
+                     double* __restrict__ slots, int lower) {
   constexpr int FM = TM / 32, FN = TN / 32;  // MFMA blocks per wave
   constexpr int RA = TM / 64, RB = TN / 64;  // 64-row loader passes
   __shared__ double As[TM][kPad];  // [m][k]
