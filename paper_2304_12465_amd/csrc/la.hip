@@ -545,9 +545,11 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, hipStream_t s, Arena* scratch, bool lower_only) {
   if (M <= 0 || N <= 0) return KRR_OK;
-  if (!a_trans && !b_trans && M <= 8 && !lower_only && N >= 65536) {
-    // enough columns for ~1000 workgroups; below that the tiled GEMM (with
-    // its K split) keeps more of the chip busy
+  if (!a_trans && !b_trans && M <= 8 && !lower_only && (N >= 65536 || K <= 1024)) {
+    // enough columns for ~1000 workgroups, or a short K (little work per
+    // workgroup, where the tiled GEMM's staging and 64-row tiles cost more
+    // than they save); otherwise the tiled GEMM's K split keeps more of the
+    // chip busy
     const unsigned g = (unsigned)ceil_div(N, 64);
     if (M == 1)
       gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);

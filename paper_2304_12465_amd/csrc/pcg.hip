@@ -31,73 +31,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
-// part[c*nblk + blk] = sum over this block's rows of A_c * B_c
-__global__ __launch_bounds__(kThreads) void dot_part(const double* __restrict__ A,
-                                                     const double* __restrict__ B, int64_t n,
-                                                     int64_t chunk, int nblk,
-                                                     double* __restrict__ part) {
-  __shared__ double sh[kThreads];
-  const int c = blockIdx.y, blk = blockIdx.x;
-  const int64_t i0 = (int64_t)blk * chunk;
-  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
-  const double* a = A + (int64_t)c * n;
-  const double* b = B + (int64_t)c * n;
-  double s = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) s += a[i] * b[i];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(int64_t)c * nblk + blk] = s;
-}
-
-// x += alpha p; r -= alpha w; part = partial sums of r^2 (new r)
-__global__ __launch_bounds__(kThreads) void update_xr(double* __restrict__ x,
-                                                      double* __restrict__ r,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ w,
-                                                      const double* __restrict__ scal, int m_max,
-                                                      int64_t n, int64_t chunk, int nblk,
-                                                      double* __restrict__ part) {
-  __shared__ double sh[kThreads];
-  const int c = blockIdx.y, blk = blockIdx.x;
-  const double alpha = scal[kAlpha * m_max + c];
-  const int64_t i0 = (int64_t)blk * chunk;
-  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
-  const int64_t off = (int64_t)c * n;
-  double s = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
-    x[off + i] += alpha * p[off + i];
-    const double rv = r[off + i] - alpha * w[off + i];
-    r[off + i] = rv;
-    s += rv * rv;
-  }
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(int64_t)c * nblk + blk] = s;
-}
-
-// p = active ? z + beta p : 0
-__global__ __launch_bounds__(kThreads) void update_p(double* __restrict__ p,
-                                                     const double* __restrict__ z,
-                                                     const double* __restrict__ scal, int m_max,
-                                                     int64_t n) {
-  const int c = blockIdx.y;
-  const double beta = scal[kBeta * m_max + c];
-  const bool act = scal[kActive * m_max + c] != 0.0;
-  const int64_t off = (int64_t)c * n;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads)
-    p[off + i] = act ? z[off + i] + beta * p[off + i] : 0.0;
-}
-
 enum FinalOp { kFinPW = 0, kFinRR = 1, kFinRZ = 2, kFinInit = 3, kFinSum = 4, kFinActivate = 5 };
 
-// One thread per column: sums the partial slots in a fixed order and applies
-// the scalar step of the recurrence.
-__global__ void finalize(const double* __restrict__ part, int nblk, int m, int m_max, int op,
-                         double tol2, int slot, double* __restrict__ scal) {
-  const int c = threadIdx.x;
-  if (c >= m) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)c * nblk + b];
-  double* S = scal;
+// The scalar step of the recurrence for column c, given the column's sum s.
+__device__ __forceinline__ void final_op(int op, int c, double s, int m_max, double tol2, int slot,
+                                         double* __restrict__ S) {
   const bool act = S[kActive * m_max + c] != 0.0;
   switch (op) {
     case kFinPW:
@@ -113,13 +51,11 @@ __global__ void finalize(const double* __restrict__ part, int nblk, int m, int m
       S[kRR * m_max + c] = s;
       S[kActive * m_max + c] = (S[kBB * m_max + c] > 0.0 && s > tol2 * S[kBB * m_max + c]) ? 1.0 : 0.0;
       break;
-    case kFinRZ: {
-      const bool a2 = act;
+    case kFinRZ:
       S[kRZnew * m_max + c] = s;
-      S[kBeta * m_max + c] = a2 ? s / S[kRZ * m_max + c] : 0.0;
-      if (a2) S[kRZ * m_max + c] = s;
+      S[kBeta * m_max + c] = act ? s / S[kRZ * m_max + c] : 0.0;
+      if (act) S[kRZ * m_max + c] = s;
       break;
-    }
     case kFinInit:  // s = ||b||^2
       S[kBB * m_max + c] = s;
       S[kRR * m_max + c] = s;
@@ -128,6 +64,91 @@ __global__ void finalize(const double* __restrict__ part, int nblk, int m, int m
     default:
       S[slot * m_max + c] = s;
   }
+}
+
+// Where a reduction's block sums go: partial slots for finalize, or, when
+// the whole column is one block (fin >= 0), straight into the scalar step
+// (the sum 0 + s is what finalize would form from the single slot).
+struct RedOut {
+  double* part;
+  int fin;  // FinalOp, or -1
+  int m_max;
+  double tol2;
+  int slot;
+  double* scal;
+};
+__device__ __forceinline__ void red_store(const RedOut& o, int c, int nblk, int blk, double s) {
+  if (o.fin >= 0)
+    final_op(o.fin, c, 0.0 + s, o.m_max, o.tol2, o.slot, o.scal);
+  else
+    o.part[(int64_t)c * nblk + blk] = s;
+}
+
+// One thread per column: sums the partial slots in a fixed order and applies
+// the scalar step of the recurrence.
+__global__ void finalize(const double* __restrict__ part, int nblk, int m, int m_max, int op,
+                         double tol2, int slot, double* __restrict__ scal) {
+  const int c = threadIdx.x;
+  if (c >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)c * nblk + b];
+  final_op(op, c, s, m_max, tol2, slot, scal);
+}
+
+// part[c*nblk + blk] = sum over this block's rows of A_c * B_c
+__global__ __launch_bounds__(kThreads) void dot_part(const double* __restrict__ A,
+                                                     const double* __restrict__ B, int64_t n,
+                                                     int64_t chunk, int nblk, const RedOut out) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.y, blk = blockIdx.x;
+  const int64_t i0 = (int64_t)blk * chunk;
+  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  const double* a = A + (int64_t)c * n;
+  const double* b = B + (int64_t)c * n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) s += a[i] * b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) red_store(out, c, nblk, blk, s);
+}
+
+// x += alpha p; r -= alpha w; partial sums of r^2 (new r); scal is read
+// here and, for a one-block column, written by the scalar step
+__global__ __launch_bounds__(kThreads) void update_xr(double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ w,
+                                                      const double* scal, int m_max,
+                                                      int64_t n, int64_t chunk, int nblk,
+                                                      const RedOut out) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.y, blk = blockIdx.x;
+  const double alpha = scal[kAlpha * m_max + c];
+  const int64_t i0 = (int64_t)blk * chunk;
+  const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  const int64_t off = (int64_t)c * n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    x[off + i] += alpha * p[off + i];
+    const double rv = r[off + i] - alpha * w[off + i];
+    r[off + i] = rv;
+    s += rv * rv;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) red_store(out, c, nblk, blk, s);
+}
+
+// p = active ? z + beta p : 0
+__global__ __launch_bounds__(kThreads) void update_p(double* __restrict__ p,
+                                                     const double* __restrict__ z,
+                                                     const double* __restrict__ scal, int m_max,
+                                                     int64_t n) {
+  const int c = blockIdx.y;
+  const double beta = scal[kBeta * m_max + c];
+  const bool act = scal[kActive * m_max + c] != 0.0;
+  const int64_t off = (int64_t)c * n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[off + i] = act ? z[off + i] + beta * p[off + i] : 0.0;
 }
 
 __global__ void colmajor_from_rowmajor(const double* __restrict__ src, int64_t n, int m,
@@ -159,7 +180,12 @@ __global__ void fill(double* __restrict__ y, double v, int64_t len) {
   if (t < len) y[t] = v;
 }
 
-int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(n, 2048))); }
+// one block per column up to 16,384 rows (its sum then goes straight into
+// the scalar step, one launch instead of two), else 2,048 rows per block
+int blocks_for(int64_t n) {
+  if (n <= 16384) return 1;
+  return (int)std::min<int64_t>(512, ceil_div(n, 2048));
+}
 
 struct Red {
   int nblk;
@@ -176,10 +202,13 @@ int dot_cols(const PcgState& st, const double* A, const double* B, int m, int op
              int slot, hipStream_t s) {
   const Red rd = red_for(st.n);
   dim3 g((unsigned)rd.nblk, (unsigned)m);
-  dot_part<<<g, kThreads, 0, s>>>(A, B, st.n, rd.chunk, rd.nblk, st.part);
+  const RedOut out{st.part, rd.nblk == 1 ? op : -1, st.m_max, tol2, slot, st.scal};
+  dot_part<<<g, kThreads, 0, s>>>(A, B, st.n, rd.chunk, rd.nblk, out);
   KRR_LAUNCH_CHECK("dot_part");
-  finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, m, st.m_max, op, tol2, slot, st.scal);
-  KRR_LAUNCH_CHECK("finalize");
+  if (rd.nblk > 1) {
+    finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, m, st.m_max, op, tol2, slot, st.scal);
+    KRR_LAUNCH_CHECK("finalize");
+  }
   return KRR_OK;
 }
 
@@ -393,12 +422,13 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       rc = dot_cols(st, st.p, st.w, S.m, kFinPW, 0, 0, s);
       if (rc == KRR_OK) {
         const Red rd = red_for(nn);
+        const double tol2 = S.tol_inner * S.tol_inner;
+        const RedOut out{st.part, rd.nblk == 1 ? (int)kFinRR : -1, mm, tol2, 0, st.scal};
         update_xr<<<dim3((unsigned)rd.nblk, (unsigned)S.m), kThreads, 0, s>>>(
-            st.x, st.r, st.p, st.w, st.scal, mm, nn, rd.chunk, rd.nblk, st.part);
+            st.x, st.r, st.p, st.w, st.scal, mm, nn, rd.chunk, rd.nblk, out);
         rc = hip_check(hipGetLastError(), "update_xr");
-        if (rc == KRR_OK) {
-          finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, S.m, mm, kFinRR, S.tol_inner * S.tol_inner, 0,
-                                    st.scal);
+        if (rc == KRR_OK && rd.nblk > 1) {
+          finalize<<<1, 64, 0, s>>>(st.part, rd.nblk, S.m, mm, kFinRR, tol2, 0, st.scal);
           rc = hip_check(hipGetLastError(), "finalize rr");
         }
       }
