@@ -79,12 +79,14 @@ def test_sketch_H_and_factor(prec, tol):
         np.testing.assert_allclose(L @ L.T, kr.P, rtol=0, atol=1e-10 * np.abs(kr.P).max())
 
 
-def test_factor_and_apply_past_one_outer_block():
-    # k = 1,100 centres: the Cholesky factor and the inverse of L are built
-    # in two levels of blocks (outer steps of 512 with a ragged 76-wide last
-    # step), so the outer panel solves and trailing updates all run.
-    # sigma = 0.3 keeps kappa(P) near 2e4, so the apply bound below is tight.
-    p = small(n=6000, k=1100)
+@pytest.mark.parametrize("n,k", [(6000, 1100), (8000, 2100)])
+def test_factor_and_apply_past_one_outer_block(n, k):
+    # k = 1,100 and 2,100 centres: the Cholesky factor and the inverse of L
+    # are built in two levels of blocks (outer steps of 512 with a ragged
+    # last step), so the outer panel solves and trailing updates all run;
+    # at k = 2,100 B^T B runs on 128 x 128 tiles.  sigma = 0.3 keeps kappa(P)
+    # near 1e4-1e5, so the apply bound below is tight.
+    p = small(n=n, k=k)
     p.sigma = 0.3
     P = build(p, 0, m_max=2)
     k = p.centers
