@@ -26,6 +26,7 @@ namespace krr {
 namespace {
 
 constexpr int kChunk = 1024;
+constexpr int kOffLds = 4096;  // chunk offsets staged in LDS up to this many
 
 __global__ void fill_d(double* __restrict__ d, double v, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,8 +44,18 @@ __global__ __launch_bounds__(256) void chunk_sums(const double* __restrict__ d, 
   for (int e = threadIdx.x; e < len; e += blockDim.x) v[e] = d[i0 + e];
   __syncthreads();
   if (threadIdx.x != 0) return;
+  // the chain of additions is sequential; its operands are read from LDS
+  // sixteen at a time ahead of it
   double s = 0.0;
-  for (int e = 0; e < len; ++e) s = __dadd_rn(s, v[e]);
+  int e = 0;
+  for (; e + 16 <= len; e += 16) {
+    double w[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w[u] = v[e + u];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = __dadd_rn(s, w[u]);
+  }
+  for (; e < len; ++e) s = __dadd_rn(s, v[e]);
   S[c] = s;
 }
 
@@ -63,21 +74,28 @@ __global__ __launch_bounds__(256) void draw_pivots(const double* __restrict__ d,
                                                    const double* __restrict__ O, int64_t nch,
                                                    uint64_t block_key, int count,
                                                    int64_t* __restrict__ out) {
-  // one workgroup per draw t: binary search over the chunk offsets, then the
-  // chunk staged in LDS and scanned in index order by one thread
+  // one workgroup per draw t: binary search over the chunk offsets (staged
+  // in LDS when they fit), then the chunk staged in LDS and scanned in index
+  // order by one thread
   __shared__ double v[kChunk];
+  __shared__ double so[kOffLds];
   __shared__ int64_t found;
   __shared__ int64_t last[256];
   const int t = blockIdx.x;
   const int tid = threadIdx.x;
-  const double T = O[nch];
+  const bool staged = nch + 1 <= kOffLds;
+  if (staged)
+    for (int64_t c = tid; c <= nch; c += blockDim.x) so[c] = O[c];
+  __syncthreads();
+  const double* __restrict__ off = staged ? so : O;
+  const double T = off[nch];
   const double u = u53(sm64(block_key, (uint64_t)t));
   const double thr = __dmul_rn(u, T);
   // smallest chunk c with O[c+1] > thr (every thread finds the same one)
   int64_t lo = 0, hi = nch;  // search in [lo, hi)
   while (lo < hi) {
     const int64_t mid = (lo + hi) / 2;
-    if (O[mid + 1] > thr) hi = mid;
+    if (off[mid + 1] > thr) hi = mid;
     else lo = mid + 1;
   }
   if (tid == 0) found = -1;
@@ -87,15 +105,24 @@ __global__ __launch_bounds__(256) void draw_pivots(const double* __restrict__ d,
     for (int e = tid; e < len; e += blockDim.x) v[e] = d[i0 + e];
     __syncthreads();
     if (tid == 0) {
-      const double base = O[lo];
+      // the running sum is sequential; its operands are read from LDS
+      // sixteen at a time ahead of it
+      const double base = off[lo];
       double p = 0.0;
-      for (int e = 0; e < len; ++e) {
-        p = __dadd_rn(p, v[e]);
-        if (__dadd_rn(base, p) > thr) {
-          found = i0 + e;
-          break;
+      int64_t hit = -1;
+      for (int e = 0; e < len && hit < 0; e += 16) {
+        double w[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) w[q] = e + q < len ? v[e + q] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          if (hit < 0 && e + q < len) {
+            p = __dadd_rn(p, w[q]);
+            if (__dadd_rn(base, p) > thr) hit = i0 + e + q;
+          }
         }
       }
+      found = hit;
     }
   }
   __syncthreads();
