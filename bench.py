@@ -121,8 +121,8 @@ def run_steps(b, torch, p, X, Y, prec, steps, warmup):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the multi-GPU sharding is a design note, not code)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
+              "(sharding over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if a.config != "c2":
         import bench_configs
