@@ -66,6 +66,8 @@ def parse():
                          "other workloads, one JSON line each")
     ap.add_argument("--requests", type=int, default=64, help="c5: number of served requests")
     ap.add_argument("--no-baseline", action="store_true", help="c5: skip the one-at-a-time run")
+    ap.add_argument("--order", default="fifo", choices=["fifo", "sjf"],
+                    help="c5: admission order (arrival, or smallest estimated work first)")
     ap.add_argument("--build-workers", type=int, default=1,
                     help="c5: preconditioner builds on this many worker threads (0: in the loop)")
     ap.add_argument("--copy-calibration", action="store_true",

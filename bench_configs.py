@@ -198,12 +198,12 @@ def c5(a, b, torch, synth):
                   file=sys.stderr, flush=True)
         return f
     srv = Server(be, hbm_budget=160 << 30, max_active=64, on_finish=progress("batched"),
-                 build_workers=a.build_workers)
+                 build_workers=a.build_workers, order=a.order)
     t0 = time.perf_counter()
     res = srv.run(stream, make)
     tmix = time.perf_counter() - t0
     s_mix = summarize(res)
-    out = {"batched_mixed": s_mix, "batched_wall_s": tmix}
+    out = {"batched_mixed": s_mix, "batched_wall_s": tmix, "admission_order": a.order}
     if not a.no_baseline:
         be64 = GpuBackend(b.FP64, tol=1e-6, max_iter=500)
         res64 = serve_one_at_a_time(be64, stream, make, on_finish=progress("fp64"))
