@@ -32,31 +32,54 @@ __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
   return gauss_expansion_too_coarse<T>(J.s_nat, (double)*J.xmax, (double)*J.ymax, J.dpad);
 }
 
-// Per-thread staging of the next 64-column chunk (points, exponent offsets
-// -s ||y||^2, V), loaded into registers while the current chunk is computed.
+// Per-thread staging of the next 64-column chunk (points, squared norms, V),
+// loaded into registers while the current chunk is computed.  A chunk inside
+// the column range reads with linear addresses; the last chunk of a range
+// repeats its last column in the positions past the end, whose exponent is
+// set to kFar when the norms are stored, so their kernel values are exactly
+// 0.  No value is tested when it is loaded: the loads stay in flight across
+// the current chunk's MFMAs.
 template <typename T, int D>
 struct StageG {
   static constexpr int kY = kColsG * D / 256;  // point values per thread
   T y[kY];
-  T v[4];  // V: 64 columns x 16 rhs / 256 threads
-  T ay;    // threads 0..63
+  T v[4];      // V: 64 columns x 16 rhs / 256 threads
+  T yn;        // threads 0..63: squared norm of their column
+  bool valid;  // threads 0..63: the column is in range
 };
 
 template <typename T, int D>
 __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_t j1, int tid,
                                             StageG<T, D>& st) {
+  if (jb + kColsG <= j1) {
 #pragma unroll
-  for (int q = 0; q < StageG<T, D>::kY; ++q) {
-    const int e = tid + q * 256;
-    const int jj = e / D;
-    st.y[q] = (jb + jj < j1) ? J.yc[jb * D + e] : T(0);
-  }
+    for (int q = 0; q < StageG<T, D>::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + q * 256;
-    st.v[q] = (jb + e / 16 < j1) ? J.v[jb * 16 + e] : T(0);
+    for (int q = 0; q < 4; ++q) st.v[q] = J.v[jb * 16 + tid + q * 256];
+    if (tid < kColsG) {
+      st.yn = J.yn[jb + tid];
+      st.valid = true;
+    }
+  } else {
+    const int64_t last = j1 - 1;
+#pragma unroll
+    for (int q = 0; q < StageG<T, D>::kY; ++q) {
+      const int e = tid + q * 256;
+      const int64_t col = jb + e / D < last ? jb + e / D : last;
+      st.y[q] = J.yc[col * D + e % D];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int64_t col = jb + e / 16 < last ? jb + e / 16 : last;
+      st.v[q] = J.v[col * 16 + e % 16];
+    }
+    if (tid < kColsG) {
+      const int64_t col = jb + tid < last ? jb + tid : last;
+      st.yn = J.yn[col];
+      st.valid = jb + tid < j1;
+    }
   }
-  if (tid < kColsG) st.ay = (jb + tid < j1) ? -J.s * J.yn[jb + tid] : GT<T>::kFar;
 }
 
 template <typename T, int D, int MV>
@@ -125,7 +148,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
       const int e = tid + q * 256;
       sV[e / 16][e % 16] = st.v[q];
     }
-    if (tid < kColsG) sAy[tid] = st.ay;
+    if (tid < kColsG) sAy[tid] = st.valid ? -J.s * st.yn : GT<T>::kFar;
     __syncthreads();
     if (jb + kColsG < j1) stage_fetch<T, D>(J, jb + kColsG, j1, tid, st);
     if (row0 >= nr) continue;
@@ -136,10 +159,11 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
       T ya[KS];  // A operand: Y[ct*16 + li][4 ks + g]
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
+      // the first K step reads the -||x||^2 / 2 start from cinit directly
 #pragma unroll
-      for (int rt = 0; rt < kRTg; ++rt) dd[rt] = cinit[rt];
+      for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[0], xb[rt][0], cinit[rt]);
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+      for (int ks = 1; ks < KS; ++ks)
 #pragma unroll
         for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dd[rt]);
     };
