@@ -54,40 +54,44 @@ struct Stage {
   static constexpr int kSeg = KP / 32;  // 16-byte point segments per thread and array
   bf16x8 yh[kSeg], yl[kSeg];
   bf16x8 v;    // one 16-byte V segment (hi for threads 0..127, lo for 128..255)
-  float ay;    // threads 0..63
+  float yn;    // threads 0..63: squared norm of their column
+  bool valid;  // threads 0..63: the column is in range
 };
 
+// A chunk inside the column range reads with linear addresses; the last
+// chunk of a range repeats its last column past the end, and those columns
+// get a huge distance when the norms are stored (exp -> 0).  No loaded value
+// is tested here, so the loads stay in flight across the current chunk.
 template <int KP>
 __device__ __forceinline__ void stage_fetch(const MfmaJob& J, int64_t jb, int64_t j1, int tid,
                                             Stage<KP>& st) {
   constexpr int SPR = KP / 8;  // segments per column
+  const int64_t last = j1 - 1;
+  const bool full = jb + kCols <= j1;
 #pragma unroll
   for (int q = 0; q < Stage<KP>::kSeg; ++q) {
     const int e = tid + q * 256;
     const int jj = e / SPR, seg = e % SPR;
-    if (jb + jj < j1) {
-      st.yh[q] = *reinterpret_cast<const bf16x8*>(J.yhi + (jb + jj) * KP + seg * 8);
-      st.yl[q] = *reinterpret_cast<const bf16x8*>(J.ylo + (jb + jj) * KP + seg * 8);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        st.yh[q][k] = to_bf16(0.f);
-        st.yl[q][k] = to_bf16(0.f);
-      }
-    }
+    const int64_t col = full || jb + jj < last ? jb + jj : last;
+    st.yh[q] = *reinterpret_cast<const bf16x8*>(J.yhi + col * KP + seg * 8);
+    st.yl[q] = *reinterpret_cast<const bf16x8*>(J.ylo + col * KP + seg * 8);
   }
   // V is stored pre-permuted in 32-column groups of 16 x 32 slots, zero
   // padded to whole 64-column chunks: a chunk is 2 x 512 contiguous values
   const uint16_t* vsrc = tid < 128 ? J.vh : J.vl;
   st.v = *reinterpret_cast<const bf16x8*>(vsrc + jb * 16 + (tid & 127) * 8);
-  // columns past the range get a huge distance: exp -> 0
-  if (tid < kCols) st.ay = (jb + tid < j1) ? -J.s * J.yn[jb + tid] : -3.0e38f;
+  if (tid < kCols) {
+    const int64_t col = full || jb + tid < last ? jb + tid : last;
+    st.yn = J.yn[col];
+    st.valid = full || jb + tid < j1;
+  }
 }
 
 template <int KP>
-__device__ __forceinline__ void stage_store(const Stage<KP>& st, int tid, __bf16 (*sYh)[KP + 8],
-                                            __bf16 (*sYl)[KP + 8], float* sAy,
-                                            __bf16 (*sVh)[16][40], __bf16 (*sVl)[16][40]) {
+__device__ __forceinline__ void stage_store(const Stage<KP>& st, int tid, float s,
+                                            __bf16 (*sYh)[KP + 8], __bf16 (*sYl)[KP + 8],
+                                            float* sAy, __bf16 (*sVh)[16][40],
+                                            __bf16 (*sVl)[16][40]) {
   constexpr int SPR = KP / 8;
 #pragma unroll
   for (int q = 0; q < Stage<KP>::kSeg; ++q) {
@@ -99,7 +103,8 @@ __device__ __forceinline__ void stage_store(const Stage<KP>& st, int tid, __bf16
   const int vs = tid & 127;  // (group, rhs, 8-slot segment)
   __bf16(*dst)[16][40] = tid < 128 ? sVh : sVl;
   *reinterpret_cast<bf16x8*>(&dst[vs >> 6][(vs >> 2) & 15][(vs & 3) * 8]) = st.v;
-  if (tid < kCols) sAy[tid] = st.ay;
+  // columns past the range get a huge distance: exp -> 0
+  if (tid < kCols) sAy[tid] = st.valid ? -s * st.yn : -3.0e38f;
 }
 
 template <int KP>
@@ -162,7 +167,7 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
   int chunk = 0;
   for (int64_t jb = j0; jb < j1; jb += kCols, ++chunk) {
     __syncthreads();  // the previous chunk's LDS reads are done
-    stage_store<KP>(st, tid, sYh, sYl, sAy, sVh, sVl);
+    stage_store<KP>(st, tid, J.s, sYh, sYl, sAy, sVh, sVl);
     __syncthreads();
     if (jb + kCols < j1) stage_fetch<KP>(J, jb + kCols, j1, tid, st);
     if (row0 >= nr) continue;  // idle wave still joins the barriers
