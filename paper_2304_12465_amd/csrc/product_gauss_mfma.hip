@@ -112,7 +112,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   }
   // E.V on the matrix cores (MV = 0): two accumulators per row tile (even /
   // odd K steps) keep independent MFMA chains in flight.  On the VALU
-  // (MV = 1, 2, 4 right-hand sides): lane l sums E[li][col] V[col][c] over
+  // (MV = 1, 2, 4, 8 right-hand sides): lane l sums E[li][col] V[col][c] over
   // its columns.
   constexpr int MA = MV == 0 ? 2 : 1;
   constexpr int MC = MV == 0 ? 1 : MV;
@@ -399,8 +399,16 @@ GSplit g_split(int64_t nr, int64_t nc) {
   return {(int)ns, per};
 }
 
-// E.V reduction variant for m right-hand sides: VALU for m <= 4, MFMA above
-int g_variant(int m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : 0; }
+// E.V reduction variant for m right-hand sides.  Per 16 x 16 tile the MFMA
+// reduction costs four 16x16x4 MFMAs whatever m is, the VALU one m FMAs per
+// entry: FP64 (64-cycle MFMA) keeps the VALU up to 8 right-hand sides, FP32
+// (32-cycle MFMA, and a tile already bound by the matrix cores) up to 4.
+template <typename T>
+int g_variant(int m) {
+  const int vmax = std::is_same<T, double>::value ? 8 : 4;
+  if (m > vmax) return 0;
+  return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : 8;
+}
 
 template <typename T, int D>
 void launch_d(int mv, unsigned grid, const GTable<T>& tab, hipStream_t s) {
@@ -408,6 +416,12 @@ void launch_d(int mv, unsigned grid, const GTable<T>& tab, hipStream_t s) {
     case 1: tile_gauss_mfma<T, D, 1><<<grid, 256, 0, s>>>(tab); break;
     case 2: tile_gauss_mfma<T, D, 2><<<grid, 256, 0, s>>>(tab); break;
     case 4: tile_gauss_mfma<T, D, 4><<<grid, 256, 0, s>>>(tab); break;
+    case 8:
+      if constexpr (std::is_same<T, double>::value) {
+        tile_gauss_mfma<T, D, 8><<<grid, 256, 0, s>>>(tab);
+        break;
+      }
+      [[fallthrough]];
     default: tile_gauss_mfma<T, D, 0><<<grid, 256, 0, s>>>(tab); break;
   }
 }
@@ -497,10 +511,10 @@ int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T*
 template <typename T>
 int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
   for (int D : {4, 8, 16, 20, 24, 32, 48, 64}) {
-    for (int mv : {1, 2, 4, 0}) {
+    for (int mv : {1, 2, 4, 8, 0}) {
       std::vector<GJob<T>> sel;
       for (const GJob<T>& j : jobs)
-        if (j.dpad == D && g_variant(j.M) == mv) sel.push_back(j);
+        if (j.dpad == D && g_variant<T>(j.M) == mv) sel.push_back(j);
       for (size_t j0 = 0; j0 < sel.size(); j0 += kMaxGJobs) {
         GTable<T> tab{};
         int64_t total = 0;

@@ -85,6 +85,19 @@ def test_multiple_rhs(m):
             check(kind, prec, Xr, Xc, V, sigma=3.0)
 
 
+@pytest.mark.parametrize("d", [3, 32, 64])
+@pytest.mark.parametrize("m", [6, 8])
+def test_gaussian_rhs_on_vector_units(d, m):
+    # 5..8 right-hand sides: the FP64 Gaussian tile reduces E.V on the vector
+    # units, the FP32 one on the matrix cores
+    g = np.random.default_rng(300 + d + m)
+    Xr = g.standard_normal((1100, d))
+    Xc = g.standard_normal((1500, d))
+    V = g.standard_normal((1500, m))
+    for prec in (0, 1):
+        check(0, prec, Xr, Xc, V, sigma=np.sqrt(d))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sigma", [1e-8, 0.05, 0.4, 3.0, 1e3])
 def test_gaussian_exponent_range(prec, sigma):
