@@ -198,6 +198,29 @@ Red red_for(int64_t n) {
   return r;
 }
 
+// Residual gap on the sampled rows, one block per column c:
+//   scal[kGap][c] = sum_q ((b - mu x - W)_i - r_i)^2,  i = gap_row(q, n, ns),
+// with W = K(sampled rows, :) x in FP64: the squared distance between the
+// FP64 residual and the recursive one on the sample, in a fixed order.
+__global__ __launch_bounds__(kThreads) void gap_sums(const double* __restrict__ b,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ r,
+                                                     const double* __restrict__ W, double mu,
+                                                     int64_t n, int64_t ns, int m_max,
+                                                     double* __restrict__ scal) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.x;
+  const int64_t o = (int64_t)c * n;
+  double acc = 0.0;
+  for (int64_t q = threadIdx.x; q < ns; q += kThreads) {
+    const int64_t i = o + gap_row(q, n, ns);
+    const double g = ((b[i] - mu * x[i]) - W[(int64_t)c * ns + q]) - r[i];
+    acc += g * g;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) scal[kGap * m_max + c] = acc;
+}
+
 int dot_cols(const PcgState& st, const double* A, const double* B, int m, int op, double tol2,
              int slot, hipStream_t s) {
   const Red rd = red_for(st.n);
@@ -369,6 +392,9 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
     any = any || S.active[c];
   }
   S.phase = (any && max_iter > 0) ? kPhaseIterate : kPhaseCheck;
+  // MIXED full-data solves estimate the residual gap each time the worst
+  // relative recursive residual has fallen 4x since the last estimate
+  if (P.type == kRPChol && P.nsamp > 0) S.gap_next = 0.25;
   return KRR_OK;
 }
 
@@ -409,6 +435,30 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
     if (rc < 0) {
       for (int q : owner) fail(*solves[q], rc);
     }
+  }
+  // residual-gap estimates: FP64 rows of the sample against all points, on
+  // x and r before this step's update (the solve's own scratch, after its
+  // direction product in stream order)
+  for (int q = 0; q < n; ++q) {
+    Solve& S = *solves[q];
+    if (S.phase != kPhaseIterate || !S.gap_pending) continue;
+    S.gap_pending = false;
+    Precond& P = *S.P;
+    PcgState& st = P.pcg;
+    VecBlock X{st.x, st.n}, Ws{P.samp_w, P.nsamp};
+    int rc = product(P.kind, P.sigma, KRR_FP64, P.spts64, P.pts64, X.view(), S.m, 0.0, X.view(),
+                     Ws.out(), P.scratch, s);
+    if (rc == KRR_OK) {
+      gap_sums<<<(unsigned)S.m, kThreads, 0, s>>>(st.b, st.x, st.r, P.samp_w, P.mu, st.n, P.nsamp,
+                                                  st.m_max, st.scal);
+      rc = hip_check(hipGetLastError(), "gap_sums");
+    }
+    if (rc < 0) {
+      fail(S, rc);
+      continue;
+    }
+    S.gap_read = true;
+    ++S.gap_checks;
   }
   // 2. post-product kernels and scalar read-back
   for (int q = 0; q < n; ++q) {
@@ -472,6 +522,25 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
         S.phase = kPhaseCheck;
         continue;
       }
+      if (S.gap_read) {
+        // The recursive residual r tracks b - A_mixed x; the FP64 residual
+        // differs from it by the sampled gap g (scaled to all N rows).  Once
+        // |r| <= |g| / 4 in every active column, further steps cannot lower
+        // the FP64 residual by more than ~3%: the round ends at this floor.
+        S.gap_read = false;
+        const double scale = (double)st.n / (double)P.nsamp;
+        bool floor = true;
+        for (int c = 0; c < S.m; ++c)
+          if (S.active[c] && 16.0 * h[kRR * mm + c] > scale * h[kGap * mm + c]) floor = false;
+        if (floor) {
+          S.phase = kPhaseCheck;
+          continue;
+        }
+      }
+      if (S.gap_next > 0.0 && worst <= S.gap_next) {
+        S.gap_pending = true;
+        S.gap_next = 0.25 * worst;
+      }
       VecBlock R{st.r, st.n}, Z{st.z, st.n};
       int rc = apply_precond(P, R, S.m, Z, s);
       if (rc == KRR_OK) rc = dot_cols(st, st.r, st.z, S.m, kFinRZ, 0, 0, s);
@@ -510,6 +579,8 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       // a refinement round aims below tol: the lower-precision operator
       // leaves part of each round's correction in the true residual
       if (P.prec != KRR_FP64) S.tol_inner = 0.1 * S.tol;
+      S.gap_read = S.gap_pending = false;
+      if (P.nsamp > 0) S.gap_next = 0.25 * S.worst_true;
       const int64_t len = st.n * S.m;
       int rc = hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
                          "r = true residual");

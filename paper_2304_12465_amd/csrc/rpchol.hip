@@ -200,6 +200,15 @@ __global__ void gather_points(const double* __restrict__ X, int D, const int64_t
   out[t] = X[idx[q] * D + k];
 }
 
+// out[q][k] = X[gap_row(q, N, ns)][k]  (ns x d, row-major)
+__global__ void gather_strided(const double* __restrict__ X, int64_t N, int d, int64_t ns,
+                               double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns * d) return;
+  const int64_t q = t / d;
+  out[t] = X[gap_row(q, N, ns) * d + t % d];
+}
+
 // Fs[q][p] = FT[p][idx[q]]  (cnt x i, row-major)
 __global__ void gather_cols(const double* __restrict__ FT, int64_t ldf, int64_t i,
                             const int64_t* __restrict__ idx, int64_t cnt,
@@ -361,6 +370,13 @@ int rpchol_layout(Arena& a, Precond& P) {
   P.QT = a.take<double>((size_t)P.r_req * N);
   P.core = a.take<double>((size_t)P.r_req * P.r_req);
   pcg_carve(a, P.pcg, N, P.m_max, 0, P.r_req);
+  // MIXED: sampled rows for the residual-gap estimate of the refinement
+  P.nsamp = P.prec == KRR_MIXED ? std::min<int64_t>(N, kGapRows) : 0;
+  if (P.nsamp > 0) {
+    P.samp_x = a.take<double>((size_t)P.nsamp * P.d);
+    KRR_TRY(carve_points(P.kind, KRR_FP64, P.nsamp, P.d, a, &P.spts64));
+    P.samp_w = a.take<double>((size_t)P.nsamp * P.m_max);
+  }
   RPWork& w = P.rp;
   const int64_t nch = ceil_div(N, kChunk);
   w.d = a.take<double>(N);
@@ -376,7 +392,8 @@ int rpchol_layout(Arena& a, Precond& P) {
   w.spx = a.take<double>((size_t)kBmax * 64);
   // scratch for products, split-K GEMMs of the build and of the applies
   const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max);
-  const size_t ps64 = product_scratch_bytes(KRR_FP64, N, N, P.m_max);
+  const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, N, P.m_max),
+                               product_scratch_bytes(KRR_FP64, P.nsamp, N, P.m_max));
   const size_t gs = std::max(gemm_scratch_bytes(P.m_max, P.r_req, N),
                              std::max(gemm_scratch_bytes(P.r_req, P.r_req, N, true),
                                       gemm_scratch_bytes(P.B, N, P.r_req)));
@@ -395,6 +412,13 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   // fill the point layouts carved by rpchol_layout
   KRR_TRY(fill_points(P.kind, KRR_FP64, X, nullptr, P.pts64, s));
   if (P.prec != KRR_FP64) KRR_TRY(fill_points(P.kind, P.prec, X, nullptr, P.pts, s));
+  if (P.nsamp > 0) {
+    gather_strided<<<(unsigned)ceil_div(P.nsamp * P.d, 256), 256, 0, s>>>(X, N, P.d, P.nsamp,
+                                                                         P.samp_x);
+    KRR_LAUNCH_CHECK("gather_strided");
+    KRR_TRY(fill_points(P.kind, KRR_FP64, P.samp_x, shared_params(P.kind, KRR_FP64, P.pts64),
+                        P.spts64, s));
+  }
   // d = diag(A): both kernels equal exp(0) = 1 on the diagonal
   fill_d<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(w.d, 1.0, N);
   KRR_LAUNCH_CHECK("fill_d");

@@ -92,6 +92,13 @@ struct Precond {
   int32_t m_max = 1;
   PointSet pts64;  // FP64 layout of X (build steps, true residuals)
   PointSet pts;    // layout of the product precision (== pts64 for FP64)
+  // MIXED full-data solves: FP64 layout of a fixed strided sample of the rows
+  // (row gap_row(q, N, nsamp) for q < nsamp) and the sampled product output
+  // (nsamp x m_max, column-major), for estimating the operator's residual gap
+  int64_t nsamp = 0;
+  double* samp_x = nullptr;  // nsamp x d
+  PointSet spts64;
+  double* samp_w = nullptr;
   // RPCholesky: Q^T (rank x N, row-major) with Q Q^T = F (mu I + F^T F)^{-1} F^T,
   // and the lower Cholesky factor L of mu I + F^T F (rank x rank).
   int32_t r_req = 0, B = 0, rank = 0;
@@ -119,7 +126,18 @@ struct Precond {
 
 // Fixed-order reductions and vector updates (pcg.hip).
 constexpr int kScalars = 12;
-enum ScalarSlot { kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp, kActivePrev };
+enum ScalarSlot {
+  kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp, kActivePrev, kGap
+};
+
+static_assert(kGap < kScalars, "scalar slots");
+
+// Rows sampled for the residual-gap estimate of MIXED solves: at most
+// kGapRows, evenly strided over the N rows.
+constexpr int64_t kGapRows = 1024;
+__host__ __device__ inline int64_t gap_row(int64_t q, int64_t N, int64_t nsamp) {
+  return q * N / nsamp;
+}
 
 size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_for_restricted, int32_t rank);
 void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_for_restricted,
@@ -155,6 +173,13 @@ struct Solve {
   std::vector<char> active;
   std::vector<double> history;
   double worst_true = 0.0;
+  // residual-gap estimates (MIXED full-data solves): the next one is taken
+  // once the worst relative recursive residual is at or below gap_next
+  // (0: none); pending = its product runs in the next step, read = its sums
+  // arrive with this step's scalars
+  double gap_next = 0.0;
+  bool gap_pending = false, gap_read = false;
+  int gap_checks = 0;
   std::chrono::steady_clock::time_point t0;
 };
 int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter,

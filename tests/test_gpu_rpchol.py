@@ -177,6 +177,31 @@ def test_exact_recovery_stops_early_and_converges_in_one_iteration():
     assert info["iters"] == 1
 
 
+def test_mixed_refinement_rounds_end_at_the_operator_floor():
+    # Ill-conditioned Gaussian problem (near-duplicate points, mu = 1e-6 N):
+    # the bf16x3 operator's floor lies far above tol, so a MIXED round ends
+    # once the sampled FP64 residual gap exceeds 4x the recursive residual,
+    # not at tol/10 -- and the refined solution still meets tol.
+    tol = 1e-6
+    p = synth.c3(n=40_000, m=4)
+    P = build(p, 2, r=800, m_max=4)
+    beta, info = P.solve(T(p.Y), tol, 400, history=400)
+    assert info["relres_true"] <= tol and info["converged_cols"] == 4
+    h = np.array(info["history"])
+    restarts = np.nonzero(h[1:] > 3.0 * h[:-1])[0]
+    assert restarts.size >= 1
+    # the first round ended on its floor, well above tol
+    assert h[restarts[0]] > 10 * tol
+    # independent check of the residual with the oracle's kernel on 400
+    # sampled rows: mean squared row residual scaled to N rows
+    b_ = beta.cpu().numpy()
+    rows = np.random.default_rng(5).choice(p.X.shape[0], 400, replace=False)
+    K = OK.block(p.X[rows], p.X, p.kind, p.sigma)
+    res = p.Y[rows] - (K @ b_ + p.mu * b_[rows])
+    est = np.sqrt((res ** 2).sum(axis=0) * p.X.shape[0] / rows.size)
+    assert np.all(est <= 3 * tol * np.linalg.norm(p.Y, axis=0))
+
+
 def test_errors():
     b = B()
     p = synth.c1(n=200)
