@@ -21,6 +21,23 @@ notes, and the GPU library implements the same rules independently):
   (its exact value) and d is clamped at 0 (rounding can leave -1e-16).
 * The loop stops early when T <= eps * tr(A) (the matrix is exhausted;
   exact recovery, Sec. 5.1).
+
+Two other pivot rules that Sec. 3.2 sets against RPCholesky (its failure
+modes of uniform sampling and of greedy selection) run through the same
+block loop, differing only in how a block's pivots are chosen:
+
+* uniform: the block's draws are i.i.d. uniform over the indices never
+  drawn before -- the same fixed-order prefix rule and random stream as
+  above, applied to the weights w_i = 1 (never drawn) / 0 (drawn) instead
+  of d; every drawn index (accepted or dropped) leaves the pool.  The rank
+  r budgets the distinct indices drawn (r columns sampled uniformly, as the
+  Nystrom approximation A(:,S) A(S,S)^+ A(S,:) takes them; dependent ones
+  are dropped), not the accepted pivots.  With B = 1 this is uniform
+  sampling of r indices without replacement.
+* greedy: one pivot per block (B is ignored), the index of the largest
+  residual diagonal entry (smallest index among equal maxima); the loop
+  also stops when that entry is <= eps * tr(A), since no further pivot
+  could be accepted.
 """
 import numpy as np
 from scipy.linalg import solve_triangular
@@ -91,32 +108,70 @@ def chol_drop(Gss, thresh):
     return R[np.ix_(acc, acc)], acc
 
 
-def rpcholesky(X, kind, sigma, r, B=None, seed=0, record=None):
+RULES = ("rpcholesky", "uniform", "greedy")
+
+
+def select_block(rule, d, pool, seed, b, count):
+    """The draws of block b under ``rule``: ``count`` i.i.d. draws ~ d
+    (RPCholesky) or ~ pool (uniform over the indices never drawn), or the
+    single index of the largest residual diagonal entry (greedy)."""
+    if rule == "greedy":
+        return [int(np.argmax(d))]  # first index of the maximum
+    if rule == "uniform":
+        return draw_block(pool, seed, b, count)
+    return draw_block(d, seed, b, count)
+
+
+def rpcholesky(X, kind, sigma, r, B=None, seed=0, record=None, rule="rpcholesky"):
     """Blocked RPCholesky, Alg. 3: returns (F, pivots) with F F^T ~ A.
 
     ``record`` (optional list) receives per block: dict(T=..., drawn=...,
-    accepted=...), used by invariant tests.
+    accepted=...), used by invariant tests.  ``rule`` selects the pivot rule
+    (RULES; see the module notes).
     """
     X = np.asarray(X, dtype=np.float64)
-    N = X.shape[0]
+    return nystrom_columns(kernels.diag(X, kind, sigma),
+                           lambda S: kernels.block(X, X[S], kind, sigma),
+                           r, B=B, seed=seed, record=record, rule=rule)
+
+
+def nystrom_columns(diag, columns, r, B=None, seed=0, record=None, rule="rpcholesky"):
+    """The block loop of Alg. 3 on a PSD matrix A given by its diagonal
+    (length N) and ``columns(S)`` -> A(:, S) (N x len(S)); returns (F, pivots).
+    """
+    if rule not in RULES:
+        raise ValueError(f"unknown pivot rule {rule!r}")
+    d = np.array(diag, dtype=np.float64)
+    N = d.shape[0]
     if B is None or B <= 0:
         B = default_block(r)
+    if rule == "greedy":
+        B = 1
     F = np.zeros((N, r))
-    d = kernels.diag(X, kind, sigma)
     trA = float(np.sum(d))
     thresh = EPS * trA
+    pool = np.ones(N)  # uniform rule: 1 for indices never drawn
     pivots = []
     i = 0
+    ndrawn = 0  # uniform rule: distinct indices drawn so far
     b = 0
-    while i < r and b <= N:
+    while (ndrawn if rule == "uniform" else i) < r and b <= N:
         O = prefix_tables(d)
-        if O[-1] <= thresh:
+        stop = O[-1] <= thresh
+        if rule == "greedy":
+            stop = stop or np.max(d) <= thresh
+        elif rule == "uniform":
+            stop = stop or not pool.any()
+        if stop:
             if record is not None:
                 record.append(dict(T=float(O[-1]), drawn=[], accepted=[]))
             break
-        draws = draw_block(d, seed, b, min(B, r - i))
+        count = min(B, r - (ndrawn if rule == "uniform" else i))
+        draws = select_block(rule, d, pool, seed, b, count)
         Sp = sorted(set(draws))
-        G = kernels.block(X, X[Sp], kind, sigma) - F[:, :i] @ F[Sp, :i].T
+        pool[Sp] = 0.0
+        ndrawn += len(Sp)
+        G = columns(Sp) - F[:, :i] @ F[Sp, :i].T
         R, acc = chol_drop(G[Sp, :], thresh)
         if acc:
             Gacc = G[:, acc]

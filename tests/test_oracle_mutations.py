@@ -13,6 +13,7 @@ import tests.test_oracle_kernels as TK
 import tests.test_oracle_rpcholesky as TR
 import tests.test_oracle_pcg as TP
 import tests.test_oracle_krill as TKR
+import tests.test_oracle_pivot_rules as TPR
 
 
 def must_fail(fn, *args):
@@ -62,6 +63,36 @@ def test_off_by_one_sampler_is_caught(monkeypatch):
         return min(i + 1, len(d) - 1)
     monkeypatch.setattr(RP, "sample_index", bad)
     must_fail(TR.test_sampler_distribution_is_proportional_to_d)
+
+
+def test_greedy_smallest_diagonal_mistake_is_caught(monkeypatch):
+    orig = RP.select_block
+
+    def bad(rule, d, pool, seed, b, count):  # smallest positive residual instead
+        if rule == "greedy":
+            return [int(np.argmin(np.where(d > 0, d, np.inf)))]
+        return orig(rule, d, pool, seed, b, count)
+    monkeypatch.setattr(RP, "select_block", bad)
+    must_fail(TPR.test_greedy_trap_greedy_takes_the_identity_block_first)
+    must_fail(TPR.test_greedy_equals_diagonal_pivoting, K.GAUSSIAN)
+
+
+def test_uniform_weighted_by_residual_mistake_is_caught(monkeypatch):
+    orig = RP.select_block
+
+    def bad(rule, d, pool, seed, b, count):  # weights from d: RPCholesky again
+        return orig("rpcholesky" if rule == "uniform" else rule, d, pool, seed, b, count)
+    monkeypatch.setattr(RP, "select_block", bad)
+    must_fail(TPR.test_rank2_block_uniform_misses_the_small_block_hypergeometrically)
+
+
+def test_uniform_with_replacement_mistake_is_caught(monkeypatch):
+    orig = RP.select_block
+
+    def bad(rule, d, pool, seed, b, count):  # drawn indices not retired
+        return orig(rule, d, np.ones_like(pool), seed, b, count)
+    monkeypatch.setattr(RP, "select_block", bad)
+    must_fail(TPR.test_uniform_blocks_budget_distinct_draws)
 
 
 def test_transposed_triangular_solve_is_caught(monkeypatch):
