@@ -22,7 +22,7 @@ notes, and the GPU library implements the same rules independently):
 * The loop stops early when T <= eps * tr(A) (the matrix is exhausted;
   exact recovery, Sec. 5.1).
 
-Two other pivot rules that Sec. 3.2 sets against RPCholesky (its failure
+Two other pivot rules that Sec. 3.1 sets against RPCholesky (its failure
 modes of uniform sampling and of greedy selection) run through the same
 block loop, differing only in how a block's pivots are chosen:
 

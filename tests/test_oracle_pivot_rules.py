@@ -1,4 +1,4 @@
-"""Pins of the oracle's uniform and greedy pivot rules (Sec. 3.2's
+"""Pins of the oracle's uniform and greedy pivot rules (Sec. 3.1's
 alternatives to RPCholesky), run through the block loop of Alg. 3.
 
 * The rank-2 block matrix of the uniform-sampling failure mode: greedy and
