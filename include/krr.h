@@ -123,6 +123,25 @@ int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec, con
                      int64_t N, int32_t d, double mu, int32_t r, int32_t B, uint64_t seed,
                      int32_t m_max, void* ws, size_t ws_bytes, krr_precond* out,
                      hipStream_t stream);
+/* Nystrom preconditioner with another pivot rule in the same block loop
+ * (Sec. 3.1 sets uniform sampling and greedy selection against RPCholesky):
+ *   KRR_PIVOT_RPCHOL   draws ~ residual diagonal (krr_rpchol_build);
+ *   KRR_PIVOT_UNIFORM  per block, B i.i.d. draws uniform over the indices
+ *                      never drawn before (same prefix rule and random
+ *                      stream, on 0/1 weights); r counts the distinct
+ *                      indices drawn, dependent ones are dropped, so the
+ *                      rank can end below r;
+ *   KRR_PIVOT_GREEDY   one pivot per block (B ignored): the largest residual
+ *                      diagonal entry, smallest index among equal maxima;
+ *                      stops when it is <= eps tr(A).
+ * Arguments, workspace (krr_rpchol_ws with the same shape covers every
+ * rule), ownership and errors as krr_rpchol_build; KRR_EINVAL for an
+ * unknown rule.                                                            */
+typedef enum { KRR_PIVOT_RPCHOL = 0, KRR_PIVOT_UNIFORM = 1, KRR_PIVOT_GREEDY = 2 } krr_pivot_rule;
+int krr_nystrom_build(krr_kernel_kind kind, double sigma, krr_precision prec, const double* X,
+                      int64_t N, int32_t d, double mu, int32_t r, int32_t B, uint64_t seed,
+                      krr_pivot_rule rule, int32_t m_max, void* ws, size_t ws_bytes,
+                      krr_precond* out, hipStream_t stream);
 /* F^T (rank x N, row-major, device) of the RPCholesky factor, recomputed as
  * L Q^T into the caller's buffer.                                          */
 int krr_rpchol_factor(krr_precond P, double* FT, hipStream_t stream);

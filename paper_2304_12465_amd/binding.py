@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libkrr.so")
 
 GAUSSIAN, LAPLACE = 0, 1
 FP64, FP32, MIXED = 0, 1, 2
+PIVOT_RPCHOL, PIVOT_UNIFORM, PIVOT_GREEDY = 0, 1, 2
 NOT_CONVERGED = 1
 ERRORS = {-1: "EINVAL", -2: "EWORKSPACE", -3: "ENOTSPD", -4: "ENAN", -5: "EHIP"}
 
@@ -42,6 +43,8 @@ _SIGS = {
     "krr_rpchol_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _szp], _i32),
     "krr_rpchol_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _i32, _i32, _u64, _i32, _vp,
                           _sz, _pp, _vp], _i32),
+    "krr_nystrom_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _i32, _i32, _u64, _i32, _i32,
+                           _vp, _sz, _pp, _vp], _i32),
     "krr_rpchol_factor": ([_vp, _vp, _vp], _i32),
     "krr_krill_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _szp], _i32),
     "krr_krill_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _vp, _i32, _i32, _i32, _u64,
@@ -257,6 +260,21 @@ def rpchol_build(kind, sigma, prec, X, mu, r, B=0, seed=0, m_max=1, ws=None):
     check(lib().krr_rpchol_build(kind, float(sigma), prec, _ptr(X), N, d, float(mu), int(r),
                                  int(B), ctypes.c_uint64(seed & (2 ** 64 - 1)), int(m_max), _ptr(ws),
                                  ws.numel(), ctypes.byref(h), _stream(X.device)))
+    return Precond(h, ws, X, m_max, kind)
+
+
+def nystrom_build(kind, sigma, prec, X, mu, r, rule, B=0, seed=0, m_max=1, ws=None):
+    """Nystrom preconditioner with pivot rule PIVOT_RPCHOL, PIVOT_UNIFORM or
+    PIVOT_GREEDY (same workspace as rpchol_build)."""
+    _f64(X)
+    N, d = X.shape
+    if ws is None:
+        ws = workspace(rpchol_ws(kind, prec, N, d, r, B, m_max), X.device)
+    h = ctypes.c_void_p(0)
+    check(lib().krr_nystrom_build(kind, float(sigma), prec, _ptr(X), N, d, float(mu), int(r),
+                                  int(B), ctypes.c_uint64(seed & (2 ** 64 - 1)), int(rule),
+                                  int(m_max), _ptr(ws), ws.numel(), ctypes.byref(h),
+                                  _stream(X.device)))
     return Precond(h, ws, X, m_max, kind)
 
 

@@ -83,11 +83,16 @@ extern "C" int krr_rpchol_ws(krr_kernel_kind kind, krr_precision prec, int64_t N
   return KRR_OK;
 }
 
-extern "C" int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec,
-                                const double* X, int64_t N, int32_t d, double mu, int32_t r,
-                                int32_t B, uint64_t seed, int32_t m_max, void* ws,
-                                size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+extern "C" int krr_nystrom_build(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                 const double* X, int64_t N, int32_t d, double mu, int32_t r,
+                                 int32_t B, uint64_t seed, krr_pivot_rule rule, int32_t m_max,
+                                 void* ws, size_t ws_bytes, krr_precond* out,
+                                 hipStream_t stream) {
   KRR_TRY(check_kernel(kind, sigma, prec));
+  if (rule != KRR_PIVOT_RPCHOL && rule != KRR_PIVOT_UNIFORM && rule != KRR_PIVOT_GREEDY) {
+    set_error("unknown pivot rule %d", (int)rule);
+    return KRR_EINVAL;
+  }
   if (!out || !X) {
     set_error("NULL argument");
     return KRR_EINVAL;
@@ -108,6 +113,8 @@ extern "C" int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precisio
     P.sigma = sigma;
     P.mu = mu;
     P.seed = seed;
+    P.rule = rule;
+    if (rule == KRR_PIVOT_GREEDY) P.B = 1;  // one pivot per step
     Arena meas;
     rc = rpchol_layout(meas, P);
     if (rc == KRR_OK) rc = finish_carve(P, ws, ws_bytes, meas.used);
@@ -123,6 +130,14 @@ extern "C" int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precisio
   }
   *out = h;
   return KRR_OK;
+}
+
+extern "C" int krr_rpchol_build(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                const double* X, int64_t N, int32_t d, double mu, int32_t r,
+                                int32_t B, uint64_t seed, int32_t m_max, void* ws,
+                                size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+  return krr_nystrom_build(kind, sigma, prec, X, N, d, mu, r, B, seed, KRR_PIVOT_RPCHOL, m_max, ws,
+                           ws_bytes, out, stream);
 }
 
 namespace {

@@ -15,6 +15,11 @@
 //  * after each block the drawn entries of the residual diagonal are set to
 //    zero and the diagonal is clamped at zero;
 //  * the loop stops early once the residual trace is <= eps * tr(A).
+// The uniform and greedy pivot rules (Sec. 3.1) change only the block's
+// draws: uniform draws through the same prefix rule on 0/1 pool weights
+// (indices never drawn) and budgets r distinct draws; greedy takes the one
+// index of the largest residual diagonal entry (smallest index among equal
+// maxima) and stops once that entry is <= eps * tr(A).
 #include "solver.h"
 #include "exp64.h"
 #include <algorithm>
@@ -57,6 +62,75 @@ __global__ __launch_bounds__(256) void chunk_sums(const double* __restrict__ d, 
   }
   for (; e < len; ++e) s = __dadd_rn(s, v[e]);
   S[c] = s;
+}
+
+// Largest d_i of each 1024-entry chunk and its index (the smallest among
+// equal maxima): V[c], I[c].  The maximum is exact, so the result does not
+// depend on the reduction order.
+__device__ __forceinline__ bool arg_better(double v, int64_t i, double bv, int64_t bi) {
+  return v > bv || (v == bv && i < bi);
+}
+__global__ __launch_bounds__(256) void chunk_argmax(const double* __restrict__ d, int64_t n,
+                                                    double* __restrict__ V,
+                                                    int64_t* __restrict__ I) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int64_t c = blockIdx.x;
+  const int64_t i0 = c * kChunk;
+  const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+  double bv = -1.0;
+  int64_t bi = n;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+    if (arg_better(d[i], i, bv, bi)) {
+      bv = d[i];
+      bi = i;
+    }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w && arg_better(sv[threadIdx.x + w], si[threadIdx.x + w], sv[threadIdx.x],
+                                      si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + w];
+      si[threadIdx.x] = si[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    V[c] = sv[0];
+    I[c] = si[0];
+  }
+}
+
+// Over the chunks: out[0] = index of the largest d, vmax[0] = its value.
+__global__ __launch_bounds__(256) void argmax_final(const double* __restrict__ V,
+                                                    const int64_t* __restrict__ I, int64_t nch,
+                                                    int64_t* __restrict__ out,
+                                                    double* __restrict__ vmax) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  double bv = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t c = threadIdx.x; c < nch; c += blockDim.x)
+    if (arg_better(V[c], I[c], bv, bi)) {
+      bv = V[c];
+      bi = I[c];
+    }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w && arg_better(sv[threadIdx.x + w], si[threadIdx.x + w], sv[threadIdx.x],
+                                      si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + w];
+      si[threadIdx.x] = si[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = si[0];
+    vmax[0] = sv[0];
+  }
 }
 
 // O[0] = 0, O[c+1] = O[c] + S[c] (sequential, one thread).
@@ -390,6 +464,11 @@ int rpchol_layout(Arena& a, Precond& P) {
   w.acc = a.take<int>(kBmax);
   w.ints = a.take<int>(4);
   w.spx = a.take<double>((size_t)kBmax * 64);
+  w.pool = a.take<double>(N);
+  w.S2 = a.take<double>(nch);
+  w.O2 = a.take<double>(nch + 1);
+  w.gi = a.take<int64_t>(nch);
+  w.vmax = a.take<double>(1);
   // scratch for products, split-K GEMMs of the build and of the applies
   const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max);
   const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, N, P.m_max),
@@ -422,6 +501,11 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   // d = diag(A): both kernels equal exp(0) = 1 on the diagonal
   fill_d<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(w.d, 1.0, N);
   KRR_LAUNCH_CHECK("fill_d");
+  const int rule = P.rule;
+  if (rule == KRR_PIVOT_UNIFORM) {
+    fill_d<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(w.pool, 1.0, N);
+    KRR_LAUNCH_CHECK("fill_d pool");
+  }
   const double trA = (double)N;
   const double thresh = kEps * trA;
   const uint64_t kpiv = sm64(P.seed, kTagPivot);
@@ -438,22 +522,49 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
   int* hacc = hints + 16;
   int64_t* hsp = reinterpret_cast<int64_t*>(w.hstage + 128 + 8 * kBmax + 4 * kBmax);
   static_assert(128 + 8 * kBmax + 4 * kBmax + 8 * kBmax <= kHostStage, "staging bytes");
-  while (i < P.r_req && b <= N) {
+  int64_t ndrawn = 0;  // uniform rule: distinct indices drawn so far
+  while ((rule == KRR_PIVOT_UNIFORM ? ndrawn : i) < P.r_req && b <= N) {
     // prefix tables, then the block's draws (they read the total on the
-    // device); one readback of the total and the draws
+    // device); one readback of the total(s) and the draws
     chunk_sums<<<(unsigned)nch, 256, 0, s>>>(w.d, N, nch, w.S);
     KRR_LAUNCH_CHECK("chunk_sums");
     chunk_offsets<<<1, 1, 0, s>>>(w.S, nch, w.O);
     KRR_LAUNCH_CHECK("chunk_offsets");
-    const int cnt = (int)std::min<int64_t>(P.B, P.r_req - i);
-    draw_pivots<<<(unsigned)cnt, 256, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
-                                                           cnt, w.draws);
-    KRR_LAUNCH_CHECK("draw_pivots");
+    const int cnt = rule == KRR_PIVOT_GREEDY
+                        ? 1
+                        : (int)std::min<int64_t>(P.B, P.r_req - (rule == KRR_PIVOT_UNIFORM ? ndrawn : i));
+    const double* aux = nullptr;  // pool total (uniform) or largest d (greedy)
+    if (rule == KRR_PIVOT_UNIFORM) {
+      chunk_sums<<<(unsigned)nch, 256, 0, s>>>(w.pool, N, nch, w.S2);
+      KRR_LAUNCH_CHECK("chunk_sums pool");
+      chunk_offsets<<<1, 1, 0, s>>>(w.S2, nch, w.O2);
+      KRR_LAUNCH_CHECK("chunk_offsets pool");
+      draw_pivots<<<(unsigned)cnt, 256, 0, s>>>(w.pool, N, w.O2, nch, sm64(kpiv, (uint64_t)b),
+                                                             cnt, w.draws);
+      KRR_LAUNCH_CHECK("draw_pivots pool");
+      aux = w.O2 + nch;
+    } else if (rule == KRR_PIVOT_GREEDY) {
+      // w.S is free again once the offsets are formed
+      chunk_argmax<<<(unsigned)nch, 256, 0, s>>>(w.d, N, w.S, w.gi);
+      KRR_LAUNCH_CHECK("chunk_argmax");
+      argmax_final<<<1, 256, 0, s>>>(w.S, w.gi, nch, w.draws, w.vmax);
+      KRR_LAUNCH_CHECK("argmax_final");
+      aux = w.vmax;
+    } else {
+      draw_pivots<<<(unsigned)cnt, 256, 0, s>>>(w.d, N, w.O, nch, sm64(kpiv, (uint64_t)b),
+                                                             cnt, w.draws);
+      KRR_LAUNCH_CHECK("draw_pivots");
+    }
     KRR_TRY(hip_check(hipMemcpyAsync(hT, w.O + nch, sizeof(double), hipMemcpyDeviceToHost, s), "T"));
+    if (aux)
+      KRR_TRY(hip_check(hipMemcpyAsync(hT + 1, aux, sizeof(double), hipMemcpyDeviceToHost, s),
+                        "rule total"));
     KRR_TRY(hip_check(hipMemcpyAsync(hdraws, w.draws, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, s),
                       "draws"));
     KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
-    if (!(*hT > thresh)) break;  // residual exhausted (exact recovery): the draws are unused
+    if (!(hT[0] > thresh)) break;  // residual exhausted (exact recovery): the draws are unused
+    if (rule == KRR_PIVOT_UNIFORM && !(hT[1] > 0.0)) break;     // every index drawn
+    if (rule == KRR_PIVOT_GREEDY && !(hT[1] > thresh)) break;   // no pivot can be accepted
     sp.assign(hdraws, hdraws + cnt);
     std::sort(sp.begin(), sp.end());
     sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
@@ -495,8 +606,13 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
     }
     zero_at<<<1, kBmax, 0, s>>>(w.d, w.sp, bp);
     KRR_LAUNCH_CHECK("zero_at");
+    if (rule == KRR_PIVOT_UNIFORM) {
+      zero_at<<<1, kBmax, 0, s>>>(w.pool, w.sp, bp);
+      KRR_LAUNCH_CHECK("zero_at pool");
+    }
     for (int a2 = 0; a2 < na; ++a2) P.pivots.push_back(sp[hacc[a2]]);
     i += na;
+    ndrawn += bp;
     ++b;
   }
   P.rank = (int32_t)i;

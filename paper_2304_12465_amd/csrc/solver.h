@@ -63,6 +63,13 @@ struct RPWork {
   int* ints = nullptr;      // [0] accepted count, [1] Cholesky info
   double* spx = nullptr;    // pivot points, kBmax x dpad
   char* hstage = nullptr;   // pinned host staging of the per-block readbacks (kHostStage bytes)
+  // uniform rule: pool weights (1 = never drawn), their chunk totals and
+  // offsets; greedy rule: per-chunk argmax indices and the maximum
+  double* pool = nullptr;   // N
+  double* S2 = nullptr;     // chunk totals of pool
+  double* O2 = nullptr;     // chunk offsets of pool
+  int64_t* gi = nullptr;    // per-chunk index of the largest d
+  double* vmax = nullptr;   // largest d (one double)
 };
 
 // Build-time buffers of KRILL.
@@ -102,6 +109,7 @@ struct Precond {
   // RPCholesky: Q^T (rank x N, row-major) with Q Q^T = F (mu I + F^T F)^{-1} F^T,
   // and the lower Cholesky factor L of mu I + F^T F (rank x rank).
   int32_t r_req = 0, B = 0, rank = 0;
+  int32_t rule = KRR_PIVOT_RPCHOL;  // pivot rule of the block loop
   uint64_t seed = 0;
   double* QT = nullptr;
   double* core = nullptr;
