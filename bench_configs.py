@@ -7,7 +7,11 @@
 * c4 — 2,000,000-point restricted problem with KRILL (k=10,000): build,
   restricted product rate, whole solve to 1e-6;
 * c5 — served stream: p50/p99 latency and solves/s, continuously batched on
-  the MIXED path vs the same trace one at a time on the FP64 path.
+  the MIXED path vs the same trace one at a time on the FP64 path;
+* ranks — pivot rules against the approximation rank on the 100,000-point
+  Laplace workload (Sec. 3.1's rules; the iterations-to-1e-3 against rank
+  study of Sec. 4.1): build time and PCG iterations to a relative residual
+  of 1e-3 for RPCholesky, uniform and greedy pivots at r = 125 .. 4000.
 
 Each prints one JSON line in the same shape as the headline line.
 """
@@ -216,8 +220,50 @@ def c5(a, b, torch, synth):
           result=out)
 
 
+def ranks(a, b, torch, synth):
+    p = synth.c2(n=a.n)
+    N, d = p.X.shape
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(p.Y).cuda()
+    tol = 1e-3
+    rules = (("rpcholesky", b.PIVOT_RPCHOL), ("uniform", b.PIVOT_UNIFORM),
+             ("greedy", b.PIVOT_GREEDY))
+    table = []
+    # the workload's ridge and one 100x smaller, where the preconditioner
+    # has more of the spectrum to capture
+    for mu_n in (1e-4, 1e-6):
+        for r in (125, 250, 500, 1000, 2000, 4000):
+            ws = b.workspace(b.rpchol_ws(p.kind, b.FP32, N, d, r, 0, 1), X.device)
+            for name, rule in rules:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P = b.nystrom_build(p.kind, p.sigma, b.FP32, X, mu_n * N, r, rule,
+                                    seed=p.algo_seed, ws=ws)
+                tb = time.perf_counter() - t0
+                beta, info = P.solve(Y, tol, 2000)
+                torch.cuda.synchronize()
+                row = {"mu_over_N": mu_n, "rule": name, "r": r, "rank": P.dims()[0],
+                       "build_s": round(tb, 4), "iters": info["iters"],
+                       "solve_s": round(time.perf_counter() - t0 - tb, 4),
+                       "relres_true": info["relres_true"]}
+                table.append(row)
+                print(json.dumps(row), file=sys.stderr, flush=True)
+                del P
+            del ws
+            torch.cuda.empty_cache()
+    ref = next(t for t in table
+               if t["rule"] == "rpcholesky" and t["r"] == 1000 and t["mu_over_N"] == 1e-4)
+    _line(value=ref["iters"], unit="PCG iterations to relative residual 1e-3 (RPCholesky, r=1000)",
+          steps=1, warmup=0, ms_per_step=(ref["build_s"] + ref["solve_s"]) * 1e3, dtype="f32",
+          higher_is_better=False,
+          config={"workload": f"pivot rules vs rank: full-data KRR, l1 Laplace, N={N}, d={d}, "
+                              "10-component Gaussian mixture, sigma=20, mu=1e-4 N and 1e-6 N, "
+                              "FP32 tiles, PCG to 1e-3, r = 125 .. 4000"},
+          result={"table": table})
+
+
 def run(a):
     import torch
     import synth
     from paper_2304_12465_amd import binding as b
-    {"c1": c1, "c3": c3, "c4": c4, "c5": c5}[a.config](a, b, torch, synth)
+    {"c1": c1, "c3": c3, "c4": c4, "c5": c5, "ranks": ranks}[a.config](a, b, torch, synth)
