@@ -164,6 +164,23 @@ int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec, cons
                     int64_t N, int32_t d, double mu, const int64_t* centers, int32_t k,
                     int32_t sketch_rows, int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
                     size_t ws_bytes, krr_precond* out, hipStream_t stream);
+/* Direct solve of the restricted system (Sec. 2.2, eq. restricted_krr_eqn)
+ * with the shifted regulariser of Alg. 2, for comparison with KRILL
+ * (Sec. 4.2): M = A(S,:) A(:,S) + mu A(S,S) + N eps tr(A(S,S)) I is formed
+ * in FP64 over row blocks of K(X, S) (O(N k^2) flops), factored M = L L^T,
+ * and beta = L^{-T} L^{-1} A(S,:) y.  X: N x d FP64 device points;
+ * `centers`: device int64[k] in [0, N) (checked); Y: N x m FP64 device,
+ * row-major; beta: k x m FP64 device, row-major.  1 <= k <= min(N, 32768),
+ * 1 <= m <= 64, mu > 0.  Workspace: krr_restricted_direct_ws (about
+ * 2 k^2 + min(N, 2^27 / k) k doubles plus the point layouts).  Synchronises
+ * `stream`; KRR_ENOTSPD if M cannot be factored.                           */
+int krr_restricted_direct_ws(krr_kernel_kind kind, int64_t N, int32_t d, int32_t k, int32_t m,
+                             size_t* bytes);
+int krr_restricted_direct(krr_kernel_kind kind, double sigma, const double* X, int64_t N,
+                          int32_t d, double mu, const int64_t* centers, int32_t k,
+                          const double* Y, int32_t m, double* beta, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
 /* Copies a KRILL build product into a caller device buffer of `bytes`:
  * what = 0: sketch rows, int32 N x zeta (column j's rows in draw order);
  * 1: sketch signs, int32 N x zeta (+1 / -1); 2: B, FP64 sketch_rows x k;

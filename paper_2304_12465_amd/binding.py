@@ -45,6 +45,9 @@ _SIGS = {
                           _sz, _pp, _vp], _i32),
     "krr_nystrom_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _i32, _i32, _u64, _i32, _i32,
                            _vp, _sz, _pp, _vp], _i32),
+    "krr_restricted_direct_ws": ([_i32, _i64, _i32, _i32, _i32, _szp], _i32),
+    "krr_restricted_direct": ([_i32, _dbl, _vp, _i64, _i32, _dbl, _vp, _i32, _vp, _i32, _vp, _vp,
+                               _sz, _vp], _i32),
     "krr_rpchol_factor": ([_vp, _vp, _vp], _i32),
     "krr_krill_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _szp], _i32),
     "krr_krill_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _vp, _i32, _i32, _i32, _u64,
@@ -276,6 +279,27 @@ def nystrom_build(kind, sigma, prec, X, mu, r, rule, B=0, seed=0, m_max=1, ws=No
                                   int(m_max), _ptr(ws), ws.numel(), ctypes.byref(h),
                                   _stream(X.device)))
     return Precond(h, ws, X, m_max, kind)
+
+
+def restricted_direct(kind, sigma, X, mu, centers, Y, ws=None):
+    """beta (k x m) of the restricted system by forming and factoring
+    A(S,:)A(:,S) + H in FP64; `centers` is a device int64 tensor."""
+    _f64(X)
+    _f64(Y)
+    if centers.dtype != torch.int64 or not centers.is_contiguous():
+        raise TypeError("centers must be a contiguous int64 tensor")
+    N, d = X.shape
+    Y2 = Y.reshape(-1, 1) if Y.dim() == 1 else Y
+    k, m = centers.numel(), Y2.shape[1]
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        check(lib().krr_restricted_direct_ws(kind, N, d, k, m, ctypes.byref(b)))
+        ws = workspace(b.value, X.device)
+    beta = torch.empty(k, m, dtype=torch.float64, device=X.device)
+    check(lib().krr_restricted_direct(kind, float(sigma), _ptr(X), N, d, float(mu), _ptr(centers),
+                                      k, _ptr(Y2), m, _ptr(beta), _ptr(ws), ws.numel(),
+                                      _stream(X.device)))
+    return beta
 
 
 def timing_enable(on=True):

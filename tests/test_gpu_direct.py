@@ -1,0 +1,89 @@
+"""The direct restricted solve (the comparison method of Sec. 4.2: form
+A(S,:)A(:,S) + H, factor, solve) against the oracle.
+
+Tolerances (backward-stable Cholesky solve in FP64):
+* backward error ||M beta - b|| <= 100 k eps (||M||_2 ||beta|| + ||b||);
+* forward error ||beta - beta_oracle|| / ||beta_oracle|| <= 100 k eps kappa(M)
+  (small case only, where the oracle forms M).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kernels as OK
+from oracle import krill as OKR
+from oracle import direct as ODR
+import synth
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -52
+DEV = torch.device("cuda:0")
+
+
+def B():
+    from paper_2304_12465_amd import binding
+    return binding
+
+
+def T(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to(DEV)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_matches_oracle_direct_solve(kind):
+    p = synth.c4(n=4_000, k=300)
+    sigma = p.sigma if kind == 0 else 6.0
+    S = OKR.sample_centers(4_000, 300, 5)
+    Y = np.column_stack([p.Y[:, 0], np.random.default_rng(1).standard_normal(4_000)])
+    beta = B().restricted_direct(kind, sigma, T(p.X), p.mu, T(S, np.int64), T(Y))
+    beta = beta.cpu().numpy()
+    kr = OKR.Krill(p.X, kind, sigma, p.mu, S)
+    M = kr.restricted_matrix()
+    b = kr.rhs(Y)
+    bo = ODR.restricted_krr(M, b)
+    k = len(S)
+    res = np.linalg.norm(M @ beta - b)
+    assert res <= 100 * k * EPS * (np.linalg.norm(M, 2) * np.linalg.norm(beta) + np.linalg.norm(b))
+    kap = np.linalg.cond(M)
+    rel = np.linalg.norm(beta - bo) / np.linalg.norm(bo)
+    assert rel <= 100 * k * EPS * kap, (rel, kap)
+
+
+def test_several_row_blocks_backward_error():
+    # N = k = 12,000: the 2^30-byte kernel block holds 11,184 rows, so the
+    # Gram matrix and A(S,:) y accumulate over two row blocks.  The oracle
+    # checks the residual (K^T (K beta - y) + H beta) streaming over row
+    # blocks of K = A(:, S), without forming M.
+    n = 12_000
+    p = synth.c4(n=n, k=n)
+    S = np.arange(n, dtype=np.int64)
+    beta = B().restricted_direct(p.kind, p.sigma, T(p.X), p.mu, T(S, np.int64), T(p.Y))
+    beta = beta.cpu().numpy()
+    Xs = p.X[S]
+    r = np.zeros_like(beta)
+    fro2 = 0.0
+    for r0 in range(0, n, 1000):
+        Kb = OK.block(p.X[r0:r0 + 1000], Xs, p.kind, p.sigma)
+        r += Kb.T @ (Kb @ beta - p.Y[r0:r0 + 1000])
+        fro2 += float(np.sum(Kb * Kb))
+    Ass = OK.block(Xs, Xs, p.kind, p.sigma)
+    shift = n * EPS * np.trace(Ass)
+    r += p.mu * (Ass @ beta) + shift * beta
+    bnorm = 0.0
+    for r0 in range(0, n, 1000):
+        Kb = OK.block(p.X[r0:r0 + 1000], Xs, p.kind, p.sigma)
+        bnorm += float(np.sum((Kb.T @ p.Y[r0:r0 + 1000]) ** 2))
+    Mnorm = fro2 + p.mu * np.linalg.norm(Ass) + shift  # >= ||M||_2
+    assert np.linalg.norm(r) <= 100 * n * EPS * (Mnorm * np.linalg.norm(beta) + np.sqrt(bnorm))
+
+
+def test_errors():
+    b = B()
+    X = T(np.random.default_rng(0).standard_normal((50, 3)))
+    Y = T(np.ones(50))
+    with pytest.raises(b.KrrError):
+        b.restricted_direct(0, 1.0, X, 1e-3, T(np.array([0, 60]), np.int64), Y)  # out of range
+    with pytest.raises(b.KrrError):
+        b.restricted_direct(0, 1.0, X, -1.0, T(np.array([0, 1]), np.int64), Y)  # mu <= 0
+    with pytest.raises(b.KrrError):
+        b.restricted_direct(0, 1.0, X, 1e-3, T(np.arange(51) % 50, np.int64), Y)  # k > N
