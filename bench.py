@@ -61,10 +61,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-tile variant")
     ap.add_argument("--no-predict", action="store_true", help="skip the held-out prediction")
     ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "ranks"],
+    ap.add_argument("--config", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c5", "ranks", "crossover"],
                     help="c2 (default): the full-data Laplace solve; c1, c3, c4, c5: the "
                          "other workloads, one JSON line each; ranks: pivot rules against "
-                         "the approximation rank")
+                         "the approximation rank; crossover: KRILL against the direct "
+                         "restricted solve")
     ap.add_argument("--requests", type=int, default=64, help="c5: number of served requests")
     ap.add_argument("--no-baseline", action="store_true", help="c5: skip the one-at-a-time run")
     ap.add_argument("--order", default="fifo", choices=["fifo", "sjf"],

@@ -8,6 +8,10 @@
   restricted product rate, whole solve to 1e-6;
 * c5 — served stream: p50/p99 latency and solves/s, continuously batched on
   the MIXED path vs the same trace one at a time on the FP64 path;
+* crossover — KRILL (FP64 tiles, PCG to 1e-4) against the direct method
+  (form A(S,:)A(:,S) + H, factor, solve) on 500,000 points of the restricted
+  workload's distribution for k = 250 .. 16,000 centres (Sec. 4.2's
+  runtime-against-centres comparison);
 * ranks — pivot rules against the approximation rank on the 100,000-point
   Laplace workload (Sec. 3.1's rules; the iterations-to-1e-3 against rank
   study of Sec. 4.1): build time and PCG iterations to a relative residual
@@ -262,8 +266,52 @@ def ranks(a, b, torch, synth):
           result={"table": table})
 
 
+def crossover(a, b, torch, synth):
+    n = 500_000
+    tol = 1e-4
+    rows = []
+    for k in (250, 500, 1000, 2000, 4000, 8000, 16000):
+        p = synth.c4(n=n, k=k)
+        N, d = p.X.shape
+        X = torch.from_numpy(p.X).cuda()
+        Y = torch.from_numpy(p.Y).cuda()
+        ws = b.workspace(b.krill_ws(p.kind, b.FP64, N, d, k, p.sketch_rows, p.zeta, 1), X.device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = b.krill_build(p.kind, p.sigma, b.FP64, X, p.mu, k, sketch_rows=p.sketch_rows,
+                          zeta=p.zeta, seed=p.algo_seed, ws=ws)
+        beta_k, info = P.solve(Y, tol, 500)
+        torch.cuda.synchronize()
+        t_krill = time.perf_counter() - t0
+        centres = torch.tensor(P.pivots(), dtype=torch.int64, device=X.device)
+        del P, ws
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        beta_d = b.restricted_direct(p.kind, p.sigma, X, p.mu, centres, Y)
+        torch.cuda.synchronize()
+        t_direct = time.perf_counter() - t0
+        gap = float(torch.linalg.norm(beta_k - beta_d) / torch.linalg.norm(beta_d))
+        row = {"k": k, "krill_s": round(t_krill, 4), "krill_iters": info["iters"],
+               "krill_relres_true": info["relres_true"], "direct_s": round(t_direct, 4),
+               "coef_gap": gap}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        del X, Y, beta_k, beta_d, centres
+        torch.cuda.empty_cache()
+    cross = next((r["k"] for r in rows if r["krill_s"] < r["direct_s"]), None)
+    last = rows[-1]
+    _line(value=last["direct_s"] / last["krill_s"], unit="direct time / KRILL time at k=16000",
+          steps=1, warmup=0, ms_per_step=last["krill_s"] * 1e3, dtype="f64",
+          config={"workload": "restricted KRR, KRILL vs direct: N=500,000 points of the "
+                              "restricted workload's distribution (d=16, Gaussian sigma=4, "
+                              "mu=1e-5 N), k = 250 .. 16000, FP64 tiles, PCG to 1e-4"},
+          result={"table": rows, "krill_faster_from_k": cross})
+
+
 def run(a):
     import torch
     import synth
     from paper_2304_12465_amd import binding as b
-    {"c1": c1, "c3": c3, "c4": c4, "c5": c5, "ranks": ranks}[a.config](a, b, torch, synth)
+    {"c1": c1, "c3": c3, "c4": c4, "c5": c5, "ranks": ranks,
+     "crossover": crossover}[a.config](a, b, torch, synth)
