@@ -458,7 +458,6 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       continue;
     }
     S.gap_read = true;
-    ++S.gap_checks;
   }
   // 2. post-product kernels and scalar read-back
   for (int q = 0; q < n; ++q) {

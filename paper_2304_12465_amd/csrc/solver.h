@@ -187,7 +187,6 @@ struct Solve {
   // arrive with this step's scalars
   double gap_next = 0.0;
   bool gap_pending = false, gap_read = false;
-  int gap_checks = 0;
   std::chrono::steady_clock::time_point t0;
 };
 int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter,
