@@ -259,8 +259,20 @@ struct GTable {
   int64_t total;
 };
 
+// FP64 tiles up to 48 padded dimensions are held to 168 VGPRs, i.e. 3 waves
+// per SIMD instead of 2, at the price of a register spill (at d = 32, 168-280
+// bytes per lane and about 25 scratch accesses per 64-column chunk).
+// Measured on N = 200,000: d = 32 with 1 / 8 right-hand sides 26% / 9%
+// faster, d = 24 and 48 5-13%; at d = 64 the spill passes 800 bytes and
+// costs 20%, so those keep the compiler's choice.
+template <typename T, int D>
+constexpr int g_waves_per_eu() {
+  return std::is_same<T, double>::value && D <= 48 ? 3 : 1;
+}
+
 template <typename T, int D, int MV>
-__global__ __launch_bounds__(256) void tile_gauss_mfma(const GTable<T> tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g_waves_per_eu<T, D>())))
+void tile_gauss_mfma(const GTable<T> tab) {
   __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 tiles)
   if constexpr (std::is_same<T, double>::value) {
     exp64_table_fill(etab);
