@@ -259,15 +259,17 @@ struct GTable {
   int64_t total;
 };
 
-// FP64 tiles up to 48 padded dimensions are held to 168 VGPRs, i.e. 3 waves
-// per SIMD instead of 2, at the price of a register spill (at d = 32, 168-280
-// bytes per lane and about 25 scratch accesses per 64-column chunk).
-// Measured on N = 200,000: d = 32 with 1 / 8 right-hand sides 26% / 9%
-// faster, d = 24 and 48 5-13%; at d = 64 the spill passes 800 bytes and
-// costs 20%, so those keep the compiler's choice.
+// Occupancy floors.  FP64 tiles up to 48 padded dimensions are held to 168
+// VGPRs, i.e. 3 waves per SIMD instead of 2, at the price of a register spill
+// (at d = 32, 168-280 bytes per lane and about 25 scratch accesses per
+// 64-column chunk); measured on N = 200,000: d = 32 with 1 / 8 right-hand
+// sides 26% / 9% faster, d = 24 and 48 5-13%; at d = 64 the spill passes 800
+// bytes and costs 20%, so those keep the compiler's choice.  FP32 tiles up to
+// 32 padded dimensions are held to 128 VGPRs (4 waves instead of 3; d = 32
+// spills 52-184 bytes): 2-12% faster over 1-8 right-hand sides.
 template <typename T, int D>
 constexpr int g_waves_per_eu() {
-  return std::is_same<T, double>::value && D <= 48 ? 3 : 1;
+  return std::is_same<T, double>::value ? (D <= 48 ? 3 : 1) : (D <= 32 ? 4 : 1);
 }
 
 template <typename T, int D, int MV>
