@@ -18,6 +18,7 @@
 #include "exp64.h"
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 namespace krr {
@@ -142,8 +143,32 @@ __device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
   }
 }
 
+// Occupancy floors for the VALU tiles (waves per SIMD the register budget
+// must allow), set where the compiler's own budget leaves 1-2 waves and a
+// same-box A/B on 100,000 points showed the floor to pay despite a register
+// spill of 12-292 bytes per lane:
+//   quantised Laplace, 16 right-hand sides, d = 16-24: 1 -> 2 waves, 46-49%
+//   faster; d = 8 and 32 with 16, d = 16 with 8: 2 -> 3 waves, 10-21%;
+//   FP64 Laplace, 16 right-hand sides, d >= 32: 1 -> 2 waves, 48%; d = 16
+//   with 16 and d = 32 with 4: 2 -> 3 waves, 14-18%.
+// Other shapes keep the compiler's budget (FP64 d = 8 with 16 measured no
+// gain; FP64 d = 32 with 8 would spill 676 bytes).
+template <int D, int M>
+constexpr int lapq_waves() {
+  if ((D == 32 && M == 16) || (D == 16 && M == 8) || (D == 8 && M == 16)) return 3;
+  if (M == 16 && D >= 16 && D <= 24) return 2;
+  return 1;
+}
+template <typename T, int D, int M>
+constexpr int valu_waves() {
+  if (!std::is_same<T, double>::value) return 1;
+  if (M == 16) return D >= 32 ? 2 : D == 16 ? 3 : 1;
+  return D == 32 && M == 4 ? 3 : 1;
+}
+
 template <int KIND, typename T, int D, int M, int R>
-__global__ __launch_bounds__(256) void tile_valu(const JobTable<T> tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(valu_waves<T, D, M>())))
+void tile_valu(const JobTable<T> tab) {
   __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 tiles)
   if constexpr (sizeof(T) == 8) {
     exp64_table_fill(etab);
@@ -246,7 +271,8 @@ __device__ __forceinline__ void tile_item_q(const uint32_t* __restrict__ Qr, int
 }
 
 template <int D, int M, int R>
-__global__ __launch_bounds__(256) void tile_lapq(const JobTable<float> tab) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lapq_waves<D, M>())))
+void tile_lapq(const JobTable<float> tab) {
   for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
