@@ -147,6 +147,13 @@ __global__ void lower_copy(const double* __restrict__ L, int64_t n, double* __re
   const int64_t i = t / n, j = t % n;
   out[t] = j <= i ? L[t] : 0.0;
 }
+
+// Clears the strict upper triangle of an n x n row-major matrix.
+__global__ void zero_upper(double* __restrict__ L, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  if (t % n > t / n) L[t] = 0.0;
+}
 }  // namespace
 
 extern "C" int krr_rpchol_factor(krr_precond h, double* FT, hipStream_t stream) {
@@ -162,22 +169,12 @@ extern "C" int krr_rpchol_factor(krr_precond h, double* FT, hipStream_t stream) 
     set_error("NULL output");
     return KRR_EINVAL;
   }
-  const size_t mark = P.scratch.used;
-  double* L = P.scratch.take<double>((size_t)rk * rk);
-  if (!P.scratch.ok()) {
-    P.scratch.used = mark;
-    // fall back to the PCG direction vectors as staging (rank^2 <= N m_max)
-    if ((size_t)rk * rk > (size_t)P.N * P.m_max) {
-      set_error("no staging space for the factor export");
-      return KRR_EWORKSPACE;
-    }
-    L = P.pcg.p;
-  }
-  lower_copy<<<(unsigned)ceil_div(rk * rk, 256), 256, 0, stream>>>(P.core, rk, L);
-  KRR_LAUNCH_CHECK("lower_copy");
-  int rc = gemm_f64(false, rk, P.N, rk, 1.0, L, rk, P.QT, P.N, 0.0, FT, P.N, stream);
-  P.scratch.used = mark;
-  return rc;
+  // L (the lower Cholesky factor of mu I + F^T F) lives in P.core, whose
+  // strict upper triangle holds values of no meaning and is read by nothing
+  // after the build: clear it in place, then F^T = L Q^T
+  zero_upper<<<(unsigned)ceil_div(rk * rk, 256), 256, 0, stream>>>(P.core, rk);
+  KRR_LAUNCH_CHECK("zero_upper");
+  return gemm_f64(false, rk, P.N, rk, 1.0, P.core, rk, P.QT, P.N, 0.0, FT, P.N, stream);
 }
 
 extern "C" int krr_precond_dims(krr_precond h, int32_t* rank, int64_t* n) {

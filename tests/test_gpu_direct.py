@@ -87,3 +87,18 @@ def test_errors():
         b.restricted_direct(0, 1.0, X, -1.0, T(np.array([0, 1]), np.int64), Y)  # mu <= 0
     with pytest.raises(b.KrrError):
         b.restricted_direct(0, 1.0, X, 1e-3, T(np.arange(51) % 50, np.int64), Y)  # k > N
+
+
+@pytest.mark.parametrize("k", [1, 150])
+def test_one_centre_and_all_points(k):
+    g = np.random.default_rng(40 + k)
+    X = g.standard_normal((150, 4))
+    Y = g.standard_normal((150, 3))
+    S = np.sort(g.choice(150, k, replace=False)).astype(np.int64)
+    mu = 0.05
+    beta = B().restricted_direct(1, 2.0, T(X), mu, T(S, np.int64), T(Y)).cpu().numpy()
+    kr = OKR.Krill(X, 1, 2.0, mu, S)
+    M = kr.restricted_matrix()
+    b = kr.rhs(Y)
+    res = np.linalg.norm(M @ beta - b)
+    assert res <= 100 * k * EPS * (np.linalg.norm(M, 2) * np.linalg.norm(beta) + np.linalg.norm(b))

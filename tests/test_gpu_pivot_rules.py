@@ -98,3 +98,31 @@ def test_unknown_rule_rejected():
     ws = b.workspace(b.rpchol_ws(0, 0, 10, 2, 2, 0, 1), X.device)
     with pytest.raises(b.KrrError):
         b.nystrom_build(0, 1.0, 0, X, 1e-3, 2, 7, ws=ws)
+
+
+@pytest.mark.parametrize("rule", ["uniform", "greedy"])
+def test_full_rank_and_ragged_blocks(rule):
+    # r = N: every index is drawn (uniform) or the residual is exhausted
+    # (greedy); F F^T reproduces A, and the pivots equal the oracle's.  B = 7
+    # leaves a ragged last block.
+    # (a narrow bandwidth keeps A well conditioned, so no residual diagonal
+    # sits near the drop threshold and greedy's maxima are well separated)
+    g = np.random.default_rng(31)
+    X = g.standard_normal((150, 3))
+    P = build(X, 0, 0.3, 1e-2, 150, rule, B_=7, seed=4)
+    F_o, piv_o = ORP.rpcholesky(X, 0, 0.3, 150, B=7, seed=4, rule=rule)
+    assert P.pivots() == piv_o
+    F = P.factor().cpu().numpy().T
+    A = OK.block(X, X, 0, 0.3)
+    assert np.max(np.abs(F @ F.T - A)) <= 1e-8
+    if rule == "uniform":
+        assert len(set(piv_o)) == len(piv_o)
+
+
+def test_invalid_rank_rejected():
+    b = B()
+    X = T(np.random.default_rng(0).standard_normal((20, 2)))
+    for r in (0, 21):
+        with pytest.raises(b.KrrError):
+            b.nystrom_build(0, 1.0, 0, X, 1e-3, r, RULES["greedy"],
+                            ws=b.workspace(1 << 20, X.device))
