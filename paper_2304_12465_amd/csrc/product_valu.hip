@@ -150,9 +150,11 @@ __device__ __forceinline__ void tile_item(const T* __restrict__ Xr, int64_t nr,
 //   quantised Laplace, 16 right-hand sides, d = 16-24: 1 -> 2 waves, 46-49%
 //   faster; d = 8 and 32 with 16, d = 16 with 8: 2 -> 3 waves, 10-21%;
 //   FP64 Laplace, 16 right-hand sides, d >= 32: 1 -> 2 waves, 48%; d = 16
-//   with 16 and d = 32 with 4: 2 -> 3 waves, 14-18%.
-// Other shapes keep the compiler's budget (FP64 d = 8 with 16 measured no
-// gain; FP64 d = 32 with 8 would spill 676 bytes).
+//   with 16 and d = 32 with 4: 2 -> 3 waves, 14-18%; d = 16 with 8: 3 -> 4
+//   waves, 5%.
+// Other shapes keep the compiler's budget (FP64 d = 8 with 16 and quantised
+// d = 8 with 8 measured no gain; FP64 d = 32 with 8 would spill 676 bytes,
+// with 1-2 over 560).
 template <int D, int M>
 constexpr int lapq_waves() {
   if ((D == 32 && M == 16) || (D == 16 && M == 8) || (D == 8 && M == 16)) return 3;
@@ -163,6 +165,7 @@ template <typename T, int D, int M>
 constexpr int valu_waves() {
   if (!std::is_same<T, double>::value) return 1;
   if (M == 16) return D >= 32 ? 2 : D == 16 ? 3 : 1;
+  if (D == 16 && M == 8) return 4;
   return D == 32 && M == 4 ? 3 : 1;
 }
 
