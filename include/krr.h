@@ -155,7 +155,8 @@ int krr_rpchol_factor(krr_precond P, double* FT, hipStream_t stream);
  * (H in place of mu A(S,S)); the right-hand side A(S,:) y is formed in FP64.
  * `centers`: device int64[k] of distinct indices in [0, N), or NULL to draw
  * k centres uniformly without replacement with SplitMix64 keyed by `seed`.
- * Limits: 1 <= k <= min(N, 65536), 1 <= zeta <= sketch_rows.
+ * Limits: 1 <= k <= min(N, 65536), 1 <= zeta <= sketch_rows; `prec` is
+ * KRR_FP64 or KRR_FP32 (KRR_MIXED returns KRR_EINVAL before any launch).
  * The build synchronises `stream`.  Returns KRR_ENOTSPD if P cannot be
  * factored.                                                                */
 int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d, int32_t k,

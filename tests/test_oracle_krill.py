@@ -121,3 +121,66 @@ def test_sparse_sign_embedding_kappa_near_gaussian_model():
         kappas.append(ev.max() / ev.min())
     km = float(np.median(kappas))
     assert 0.5 * target < km < 2.0 * target, kappas
+
+
+def singular_centre_problem(n=2000, k=100, mu=1e-9):
+    """The restricted workload with two pairs of centres made identical, so
+    A(S,S) is singular with null vectors e_0 - e_1 and e_2 - e_3, and a ridge
+    small enough that the shift of Alg. 2 is what keeps H nonsingular."""
+    p = c4(n=n, k=k)
+    X = p.X.copy()
+    S = KR.sample_centers(n, k, p.algo_seed)
+    X[S[1]] = X[S[0]]
+    X[S[3]] = X[S[2]]
+    return KR.Krill(X, p.kind, p.sigma, mu, S, seed=p.algo_seed), n, k
+
+
+def test_krill_shift_on_singular_centres():
+    """Alg. 2, steps 1-2: H = mu A_SS + N eps_mach tr(A_SS) I, with eps_mach
+    about 2e-16 in double precision.  Both kernels have a unit diagonal, so
+    tr(A_SS) = k.  Two identical centres give A_SS an exact null vector u:
+    then H u is exactly the shift times u, and the shift is lambda_min(H)
+    because mu A_SS is positive semidefinite."""
+    kr, n, k = singular_centre_problem()
+    eps_paper = golden("eps_mach_approx")
+    assert abs(KR.EPS / eps_paper - 1.0) < 0.15
+    for i, j in ((0, 1), (2, 3)):
+        u = np.zeros(k)
+        u[i], u[j] = 1.0, -1.0
+        Hu = kr.H @ u
+        lam = Hu[i]
+        np.testing.assert_array_equal(Hu, lam * u)
+        # the shift the paper prints, with its own approximate eps
+        assert abs(lam / (n * eps_paper * k) - 1.0) < 0.15, lam
+        # the same with eps = 2**-52 (the reading), to rounding
+        assert abs(lam - n * 2.0 ** -52 * k) <= 4 * np.spacing(lam)
+    ev = np.linalg.eigvalsh(kr.H)
+    assert abs(ev[0] / lam - 1.0) < 1e-9 and abs(ev[1] / lam - 1.0) < 1e-9
+    assert ev[2] > lam                                  # the other directions carry mu A_SS
+    # H minus its shift is mu A_SS: symmetric, zero on the null vectors
+    Hm = kr.H - lam * np.eye(k)
+    np.testing.assert_array_equal(Hm, Hm.T)
+    assert np.all(np.abs(np.diag(Hm) - kr.mu) <= 4 * np.spacing(kr.mu))
+
+
+def test_krill_kappa_on_a_restricted_system_as_mu_vanishes():
+    """Sec. 2.2.3: with a sketch of d = 2k rows and mu -> 0 the preconditioned
+    restricted matrix behaves like the Gram matrix of a 2k x k Gaussian
+    matrix, condition number (1 + 1/sqrt 2)^2 / (1 - 1/sqrt 2)^2 ~ 34.0,
+    while the unpreconditioned system is badly conditioned (the paper's
+    example sets mu/N = 1e-12).  Checked on the restricted workload's
+    distribution (sigma = 4) through the generalised eigenvalues of (M, P)."""
+    import scipy.linalg as sl
+    target = golden("krill_gaussian_kappa")
+    n, k = 6000, 200
+    p = c4(n=n, k=k)
+    S = KR.sample_centers(n, k, p.algo_seed)
+    kappas = []
+    for s in range(3):
+        kr = KR.Krill(p.X, p.kind, p.sigma, 1e-12 * n, S, seed=s)
+        M = kr.restricted_matrix()
+        ev = sl.eigh(M, kr.P, eigvals_only=True)
+        kappas.append(ev.max() / ev.min())
+    assert np.linalg.cond(M) > 1e10
+    km = float(np.median(kappas))
+    assert 0.5 * target < km < 2.0 * target, kappas

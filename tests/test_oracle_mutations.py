@@ -117,7 +117,7 @@ def test_wrong_pcg_sign_is_caught(monkeypatch):
     must_fail(TP.test_rpcholesky_pcg_matches_dense_cholesky_solve)
 
 
-def test_missing_krill_shift_or_transposed_sketch_is_caught(monkeypatch):
+def test_wrong_restricted_block_in_product_is_caught(monkeypatch):
     orig_init = KR.Krill.__init__
 
     def bad_init(self, *a, **kw):
@@ -125,6 +125,50 @@ def test_missing_krill_shift_or_transposed_sketch_is_caught(monkeypatch):
         self.AnS = self.AnS + 1e-3  # a wrong A(:,S) in the product
     monkeypatch.setattr(KR.Krill, "__init__", bad_init)
     must_fail(TKR.test_all_points_as_centres_reduce_to_full_data_krr)
+
+
+def _plant_shift(monkeypatch, bad_shift):
+    """Replaces the diagonal shift of H (Alg. 2, step 2) by bad_shift(N, k, tr(A_SS))."""
+    orig_init = KR.Krill.__init__
+
+    def bad_init(self, *a, **kw):
+        orig_init(self, *a, **kw)
+        trace = float(np.trace(K.block(self.X[self.S], self.X[self.S], self.kind, self.sigma)))
+        wrong = bad_shift(self.N, self.k, trace)
+        self.H = self.H + (wrong - self.shift) * np.eye(self.k)
+        self.P = self.B.T @ self.B + self.H
+        try:
+            self.C = np.linalg.cholesky(self.P).T
+        except np.linalg.LinAlgError:  # without the shift P can be singular here
+            self.C = None
+    monkeypatch.setattr(KR.Krill, "__init__", bad_init)
+
+
+@pytest.mark.parametrize("name,bad", [
+    ("shift left out", lambda N, k, tr: 0.0),
+    ("N dropped", lambda N, k, tr: KR.EPS * tr),
+    ("trace over all N points", lambda N, k, tr: N * KR.EPS * N),
+    ("squared trace", lambda N, k, tr: N * KR.EPS * tr * tr),
+])
+def test_krill_shift_mistakes_are_caught(monkeypatch, name, bad):
+    _plant_shift(monkeypatch, bad)
+    must_fail(TKR.test_krill_shift_on_singular_centres)
+
+
+def test_single_precision_eps_in_krill_shift_is_caught(monkeypatch):
+    monkeypatch.setattr(KR, "EPS", 2.0 ** -23)
+    must_fail(TKR.test_krill_shift_on_singular_centres)
+
+
+def test_krill_without_sketch_term_is_caught(monkeypatch):
+    orig_init = KR.Krill.__init__
+
+    def bad_init(self, *a, **kw):  # P = H: the B^T B term forgotten
+        orig_init(self, *a, **kw)
+        self.P = self.H.copy()
+        self.C = np.linalg.cholesky(self.P).T
+    monkeypatch.setattr(KR.Krill, "__init__", bad_init)
+    must_fail(TKR.test_krill_kappa_on_a_restricted_system_as_mu_vanishes)
 
 
 def test_wrong_sketch_scale_is_caught(monkeypatch):
