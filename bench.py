@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     ap.add_argument("--fp32", action="store_true",
-                    help="c3 --product-only: FP32 tiles instead of MIXED")
+                    help="c3 --product-only: FP32 tiles instead of MIXED; c4 --product-only: FP32 instead of FP64")
     ap.add_argument("--product-only", action="store_true",
                     help="only run 5 launches of the headline product (for counter runs)")
     return ap.parse_args()

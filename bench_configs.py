@@ -149,6 +149,20 @@ def c4(a, b, torch, synth):
     N, d = p.X.shape
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
+    if a.product_only:
+        # 5 launches of the restricted product's first half, K(X, X(S,:)) v
+        # (2e6 x 1e4 entries), for counter runs
+        prec = b.FP32 if a.fp32 else b.FP64
+        S = torch.from_numpy(np.sort(np.random.default_rng(2).choice(N, p.centers, replace=False)))
+        C = X[S.cuda()].contiguous()
+        V = torch.from_numpy(np.random.default_rng(0).standard_normal((p.centers, 1))).cuda()
+        ws = b.workspace(b.kernel_matvec_ws(prec, N, p.centers, d, 1), X.device)
+        W = torch.empty((N, 1), dtype=torch.float64, device=X.device)
+        for _ in range(5):
+            b.kernel_matvec(p.kind, p.sigma, prec, X, C, V, out=W, ws=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"product_launches": 5, "entries_per_launch": N * p.centers}), flush=True)
+        return
     res = {}
     for prec, name in ((b.FP32, "fp32"), (b.FP64, "fp64")):
         ws = b.workspace(b.krill_ws(p.kind, prec, N, d, p.centers, p.sketch_rows, p.zeta, 1),

@@ -96,7 +96,7 @@ typedef struct krr_precond_s* krr_precond;
 
 typedef struct {
   int32_t iters;            /* PCG iterations (max over right-hand sides) */
-  int32_t converged_cols;   /* columns with recursive relative residual <= tol */
+  int32_t converged_cols;   /* columns that met tol (see krr_pcg_solve) */
   double relres_recursive;  /* max over columns of ||r_t|| / ||b|| (recurrence) */
   double relres_true;       /* max over columns of ||b - M x|| / ||b||, FP64 product */
   double build_seconds;     /* wall time of the preconditioner build */
@@ -213,9 +213,12 @@ void krr_precond_free(krr_precond P);
  * FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG restarted
  * from the FP64 true residual, each round run to tol/10 on its recursive
  * residual) until it meets tol; relres_true reports the
- * final FP64 value.  Synchronises `stream` once per iteration.  Returns
- * KRR_NOT_CONVERGED (beta = last iterate) if a column did not converge and
- * KRR_ENAN on a NaN/Inf residual.                                          */
+ * final FP64 value.  A column counts as converged when FP64 tiles bring its
+ * recursive residual to tol with a true residual within 10 tol, and when
+ * FP32 / MIXED tiles bring its FP64 true residual itself to tol.
+ * Synchronises `stream` once per iteration.  Returns KRR_NOT_CONVERGED
+ * (beta = last iterate) if a column did not converge and KRR_ENAN on a
+ * NaN/Inf residual.                                                        */
 int krr_pcg_solve(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,
                   double* beta, krr_solve_info* info, hipStream_t stream);
 
@@ -230,7 +233,11 @@ int krr_pcg_solve(krr_precond P, const double* Y, int32_t m, double tol, int32_t
  * alone and in any mix.  state (host, n entries) receives 0 = running,
  * 1 = finished, or a negative error of that solve only (the others go on).
  * krr_solve_end writes beta (n x m, row-major) and info, frees the solve
- * and returns what krr_pcg_solve would; krr_solve_free abandons a solve.  */
+ * and returns what krr_pcg_solve would; krr_solve_free abandons a solve.
+ * While a solve is active its precond refuses (KRR_EINVAL) another
+ * krr_solve_begin, krr_pcg_solve, krr_precond_apply and
+ * krr_precond_operator, which would overwrite its vectors; free the solves
+ * of a precond before the precond itself.                                  */
 typedef struct krr_solve_s* krr_solve;
 int krr_solve_begin(krr_precond P, const double* Y, int32_t m, double tol, int32_t max_iter,
                     krr_solve* out, hipStream_t stream);

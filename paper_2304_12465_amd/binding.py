@@ -378,11 +378,15 @@ class Solve:
             d["history"] = [hist[i] for i in range(info.history_len)]
         return beta, d
 
+    def free(self):
+        """Abandons the solve (its precond is free for other calls again)."""
+        if self.h:
+            lib().krr_solve_free(self.h)
+            self.h = None
+
     def __del__(self):
         try:
-            if self.h:
-                lib().krr_solve_free(self.h)
-                self.h = None
+            self.free()
         except Exception:
             pass
 

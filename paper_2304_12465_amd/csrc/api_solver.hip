@@ -66,6 +66,17 @@ int valid_precond(krr_precond P) {
   return KRR_OK;
 }
 
+// Calls that use the PCG vectors of the workspace are refused while a
+// stepped solve holds them.
+int precond_idle(krr_precond P) {
+  KRR_TRY(valid_precond(P));
+  if (P->P.solving) {
+    set_error("the precond is running a stepped solve (end or free it first)");
+    return KRR_EINVAL;
+  }
+  return KRR_OK;
+}
+
 }  // namespace
 
 extern "C" int krr_rpchol_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
@@ -198,7 +209,7 @@ extern "C" int krr_precond_pivots(krr_precond h, int64_t* host_out, int32_t cap,
 
 extern "C" int krr_precond_apply(krr_precond h, const double* Z, int32_t m, double* OUT,
                                  hipStream_t stream) {
-  KRR_TRY(valid_precond(h));
+  KRR_TRY(precond_idle(h));
   Precond& P = h->P;
   if (m < 1 || m > P.m_max || !Z || !OUT) {
     set_error("invalid arguments (m=%d, m_max=%d)", m, P.m_max);
@@ -213,7 +224,7 @@ extern "C" int krr_precond_apply(krr_precond h, const double* Z, int32_t m, doub
 
 extern "C" int krr_precond_operator(krr_precond h, const double* V, int32_t m, double* OUT,
                                     hipStream_t stream) {
-  KRR_TRY(valid_precond(h));
+  KRR_TRY(precond_idle(h));
   Precond& P = h->P;
   if (m < 1 || m > P.m_max || !V || !OUT) {
     set_error("invalid arguments (m=%d, m_max=%d)", m, P.m_max);
@@ -235,7 +246,7 @@ extern "C" void krr_precond_free(krr_precond h) {
 extern "C" int krr_pcg_solve(krr_precond h, const double* Y, int32_t m, double tol,
                              int32_t max_iter, double* beta, krr_solve_info* info,
                              hipStream_t stream) {
-  KRR_TRY(valid_precond(h));
+  KRR_TRY(precond_idle(h));
   Precond& P = h->P;
   if (m < 1 || m > P.m_max || !Y || !beta || !(tol > 0.0) || max_iter < 0) {
     set_error("invalid arguments (m=%d, m_max=%d, tol=%g, max_iter=%d)", m, P.m_max, tol,
@@ -392,7 +403,7 @@ struct krr_solve_s {
 
 extern "C" int krr_solve_begin(krr_precond h, const double* Y, int32_t m, double tol,
                                int32_t max_iter, krr_solve* out, hipStream_t stream) {
-  KRR_TRY(valid_precond(h));
+  KRR_TRY(precond_idle(h));
   Precond& P = h->P;
   if (!out || m < 1 || m > P.m_max || !Y || !(tol > 0.0) || max_iter < 0) {
     set_error("invalid arguments (m=%d, m_max=%d, tol=%g, max_iter=%d)", m, P.m_max, tol,
@@ -410,9 +421,17 @@ extern "C" int krr_solve_begin(krr_precond h, const double* Y, int32_t m, double
     delete q;
     return rc;
   }
+  P.solving = true;
   *out = q;
   return KRR_OK;
 }
+
+namespace {
+void release_solve(krr_solve q) {
+  if (q->S.P) q->S.P->solving = false;
+  delete q;
+}
+}  // namespace
 
 extern "C" int krr_solve_step(krr_solve* solves, int32_t n, int32_t* state, hipStream_t stream) {
   if (n < 0 || (n > 0 && (!solves || !state))) {
@@ -449,11 +468,13 @@ extern "C" int krr_solve_end(krr_solve q, double* beta, krr_solve_info* info, hi
   } else {
     rc = solve_end(q->S, beta, info, stream);
   }
-  delete q;
+  release_solve(q);
   return rc;
 }
 
-extern "C" void krr_solve_free(krr_solve q) { delete q; }
+extern "C" void krr_solve_free(krr_solve q) {
+  if (q) release_solve(q);
+}
 
 // ---- out-of-sample prediction -------------------------------------------
 

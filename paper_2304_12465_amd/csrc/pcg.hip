@@ -368,6 +368,7 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
   S.t0 = std::chrono::steady_clock::now();
   S.iters.assign(m, 0);
   S.active.assign(m, 0);
+  S.true_rel.assign(m, 0.0);
   PcgState& st = P.pcg;
   const int64_t n = st.n;
   const int64_t len = n * m;
@@ -554,8 +555,10 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       bool replace = false, bad = false;
       for (int c = 0; c < S.m; ++c) {
         const double bb = h[kBB * mm + c];
+        S.true_rel[c] = 0.0;
         if (bb <= 0) continue;
         const double rt = std::sqrt(h[kTrue * mm + c] / bb);
+        S.true_rel[c] = rt;
         if (!std::isfinite(rt)) bad = true;
         S.worst_true = std::max(S.worst_true, rt);
         // FP64 tiles: replace when the recurrence drifted (> 10 tol).
@@ -608,12 +611,18 @@ int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
   const int mm = st.m_max;
   double worst_rec = 0.0;
   int conv = 0;
+  // A column has converged when the FP64 true residual confirms it: FP32 and
+  // MIXED tiles need ||b - M x|| <= tol ||b|| itself (the recurrence follows
+  // the lower-precision operator); FP64 tiles stop on the recursive residual
+  // and accept a drift of the true one up to 10 tol.
+  const bool fp64 = P.prec == KRR_FP64;
   for (int c = 0; c < S.m; ++c) {
     const double bb = st.host[kBB * mm + c];
     const double rr = st.host[kRR * mm + c];
     const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     worst_rec = std::max(worst_rec, rel);
-    if (rel <= S.tol) ++conv;
+    const double rt = S.true_rel[c];
+    if (fp64 ? (rel <= S.tol && rt <= 10.0 * S.tol) : rt <= S.tol) ++conv;
   }
   if (info) {
     info->iters = S.m > 0 ? *std::max_element(S.iters.begin(), S.iters.end()) : 0;

@@ -33,6 +33,8 @@ struct PointSet {
   const double* x64 = nullptr;  // FP64 layout (KRR_FP64)
   const float* x32 = nullptr;   // FP32 layout (KRR_FP32, Laplace under KRR_MIXED)
   // bf16 hi/lo split and FP32 squared norms (Gaussian under KRR_MIXED)
+  // (a MIXED Gaussian layout also holds the FP32 centred copy xc32 / xn32 /
+  // xmax32 below, which serves jobs the split expansion cannot)
   const uint16_t* xhi = nullptr;  // n x kpad bf16 bits
   const uint16_t* xlo = nullptr;
   const float* nrm = nullptr;     // n, ||x||^2 in FP32 of the centred point
@@ -141,9 +143,16 @@ struct MfmaJob {
   const uint16_t* vh;
   const uint16_t* vl;
   double* part;
+  // FP32 centred points (nr x dpad / nc x dpad) and the largest centred
+  // squared norms (device), for the expansion guard and its fallback tile
+  const float* xf;
+  const float* yf;
+  const float* xmax;
+  const float* ymax;
   int64_t nr, nc, per, item0;
-  float s;
-  int nsplit, M, kp;
+  float s;      // exponent scale in base 2: log2(e) / (2 sigma^2)
+  float s_nat;  // 1 / (2 sigma^2)
+  int nsplit, M, kp, dpad;
 };
 int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0,
                  int mc, Arena& scratch, MfmaJob* out, hipStream_t s);

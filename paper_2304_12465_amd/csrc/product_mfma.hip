@@ -261,6 +261,19 @@ struct MJobTable {
   int64_t total;
 };
 
+// Expansion guard.  hi + lo keeps 16 significant bits of each centred
+// coordinate (|x - hi - lo| <= 2^-16 |x|) and lo.lo is dropped, so each
+// coordinate product is off by at most 3 2^-16 |x_l||y_l|; FP32 sums of the
+// 3 kp products and the FP32 norms add about (3 kp + 2) 2^-24.  With
+// 2 |x.y| <= ||x||^2 + ||y||^2 the exponent error is at most
+//   s (max||x||^2 + max||y||^2) (3 2^-16 + (3 kp + 2) 2^-24),
+// s = 1 / (2 sigma^2).  Above 2^-9 (a relative error of 0.2% per entry)
+// the job goes to direct differences on the FP32 centred points instead.
+__device__ __forceinline__ bool mixed_too_coarse(const MfmaJob& J) {
+  const float gfac = 3.0f * 0x1p-16f + (float)(3 * J.kp + 2) * 0x1p-24f;
+  return J.s_nat * (*J.xmax + *J.ymax) * gfac > 0x1p-9f;
+}
+
 template <int KP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 32 ? 3 : 2)))
 void tile_mfma_gauss(const MJobTable tab) {
@@ -268,8 +281,75 @@ void tile_mfma_gauss(const MJobTable tab) {
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const MfmaJob& J = tab.job[jn];
+    if (mixed_too_coarse(J)) continue;  // uniform over the workgroup
     const int64_t local = item - J.item0;
     mfma_item<KP>(J, local / J.nsplit, (int)(local % J.nsplit));
+  }
+}
+
+// V(j, c) from the split copy in the V-reduction's permuted order (the
+// inverse of slot_col within each 32-column group), as hi + lo in FP32.
+__device__ __forceinline__ float vsplit_at(const MfmaJob& J, int64_t j, int c) {
+  const int jj = (int)(j & 31);
+  const int slot = 8 * ((jj & 15) >> 2) + (jj < 16 ? 0 : 4) + (jj & 3);
+  const int64_t t = (j >> 5) * 512 + c * 32 + slot;
+  return from_bf16(__builtin_bit_cast(__bf16, J.vh[t])) +
+         from_bf16(__builtin_bit_cast(__bf16, J.vl[t]));
+}
+
+// Direct-difference tile for the jobs the guard refuses: FP32 differences
+// of the centred FP32 points, v_exp_f32, FP32 sums folded into FP64 every
+// 256 columns; the same work items (256 rows x one column split) and the
+// same partial-sum slots as tile_mfma_gauss.  Thread t owns row t of the
+// item; column points and V are wave-uniform.
+template <int D>
+__global__ __launch_bounds__(256) void tile_mixed_direct(const MJobTable tab) {
+  const int tid = threadIdx.x;
+  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+    int jn = 0;
+    while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
+    const MfmaJob& J = tab.job[jn];
+    if (J.dpad != D || !mixed_too_coarse(J)) continue;  // uniform over the workgroup
+    const int64_t local = item - J.item0;
+    const int64_t rg = local / J.nsplit;
+    const int split = (int)(local % J.nsplit);
+    const int64_t nr = J.nr;
+    const int64_t i = rg * (4 * 16 * kRT) + tid;
+    const int64_t ic = i < nr ? i : nr - 1;
+    float x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = J.xf[ic * D + k];
+    double acc64[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc64[c] = 0.0;
+    const int64_t j0 = (int64_t)split * J.per;
+    int64_t j1 = j0 + J.per;
+    if (j1 > J.nc) j1 = J.nc;
+    for (int64_t jb = j0; jb < j1; jb += kFoldChunks * kCols) {
+      const int64_t je = jb + kFoldChunks * kCols < j1 ? jb + kFoldChunks * kCols : j1;
+      float acc[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] = 0.f;
+      for (int64_t j = jb; j < je; ++j) {
+        const float* __restrict__ y = J.yf + j * D;
+        float s2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float t = x[k] - y[k];
+          s2 = __builtin_fmaf(t, t, s2);
+        }
+        const float e = __builtin_amdgcn_exp2f(-J.s * s2);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < J.M) acc[c] = __builtin_fmaf(e, vsplit_at(J, j, c), acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc64[c] += (double)acc[c];
+    }
+    if (i < nr) {
+      double* __restrict__ out = J.part + (int64_t)split * nr * 16 + i * 16;
+      for (int c = 0; c < J.M; ++c) out[c] = acc64[c];
+    }
   }
 }
 
@@ -446,7 +526,17 @@ int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVi
     pack_vsplit<<<(unsigned)ceil_div(npad * 16, 256), 256, 0, s>>>(V, nc, npad, c0, mc, vh, vl);
     KRR_LAUNCH_CHECK("pack_vsplit");
   }
+  if (!rows.xc32 || !cols.xc32 || rows.dpad != cols.dpad) {
+    set_error("MIXED product: FP32 centred layouts missing or inconsistent");
+    return KRR_EINVAL;
+  }
   MfmaJob& j = *out;
+  j.xf = rows.xc32;
+  j.yf = cols.xc32;
+  j.xmax = rows.xmax32;
+  j.ymax = cols.xmax32;
+  j.s_nat = (float)(1.0 / (2.0 * sigma * sigma));
+  j.dpad = rows.dpad;
   j.xhi = rows.xhi;
   j.xlo = rows.xlo;
   j.xn = rows.nrm;
@@ -489,6 +579,28 @@ int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s) {
       if (kp == 32) tile_mfma_gauss<32><<<grid, 256, 0, s>>>(tab);
       else tile_mfma_gauss<64><<<grid, 256, 0, s>>>(tab);
       KRR_LAUNCH_CHECK("tile_mfma_gauss");
+      // the direct tile serves the jobs the guard refused (decided on the
+      // device, so the launch stays asynchronous); one launch per padded
+      // dimension present
+      int dseen[kMaxMJobs], nd = 0;
+      for (int q = 0; q < nj; ++q) {
+        bool seen = false;
+        for (int u = 0; u < nd; ++u) seen = seen || dseen[u] == tab.job[q].dpad;
+        if (!seen) dseen[nd++] = tab.job[q].dpad;
+      }
+      for (int u = 0; u < nd; ++u) {
+        switch (dseen[u]) {
+          case 4: tile_mixed_direct<4><<<grid, 256, 0, s>>>(tab); break;
+          case 8: tile_mixed_direct<8><<<grid, 256, 0, s>>>(tab); break;
+          case 16: tile_mixed_direct<16><<<grid, 256, 0, s>>>(tab); break;
+          case 20: tile_mixed_direct<20><<<grid, 256, 0, s>>>(tab); break;
+          case 24: tile_mixed_direct<24><<<grid, 256, 0, s>>>(tab); break;
+          case 32: tile_mixed_direct<32><<<grid, 256, 0, s>>>(tab); break;
+          case 48: tile_mixed_direct<48><<<grid, 256, 0, s>>>(tab); break;
+          default: tile_mixed_direct<64><<<grid, 256, 0, s>>>(tab); break;
+        }
+        KRR_LAUNCH_CHECK("tile_mixed_direct");
+      }
       tile_timer_stop(tok, s);
     }
   }

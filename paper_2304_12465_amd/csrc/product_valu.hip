@@ -571,8 +571,13 @@ int carve_points(krr_kernel_kind kind, krr_precision prec, int64_t n, int32_t d,
     if (kind == KRR_GAUSSIAN) KRR_TRY(carve_f64c(n, D, arena, out));
     return KRR_OK;
   }
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) {
+    // the bf16 split, and the FP32 centred copy (same centre) that serves
+    // the jobs whose expansion error bound is too coarse for the split
+    KRR_TRY(carve_mixed(n, d, arena, out));
+    return carve_f32c(n, D, arena, out);
+  }
   out->x32 = arena.take<float>((size_t)n * D);
-  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) KRR_TRY(carve_mixed(n, d, arena, out));
   if (prec == KRR_FP32 && kind == KRR_GAUSSIAN) KRR_TRY(carve_f32c(n, D, arena, out));
   if (kind == KRR_LAPLACE) {
     out->qbits = quant_bits(D);
@@ -621,6 +626,14 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     if (kind == KRR_GAUSSIAN) return fill_f64c(X, shared, ps, s);
     return KRR_OK;
   }
+  if (prec == KRR_MIXED && kind == KRR_GAUSSIAN) {
+    if (!ps.xhi || !ps.xc32) {
+      set_error("fill_points: layout not carved");
+      return KRR_EINVAL;
+    }
+    KRR_TRY(fill_mixed(X, shared, ps, s));
+    return fill_f32c(X, ps.centre, ps, s);
+  }
   if (!ps.x32) {
     set_error("fill_points: layout not carved");
     return KRR_EINVAL;
@@ -643,7 +656,6 @@ int fill_points(krr_kernel_kind kind, krr_precision prec, const double* X, const
     KRR_LAUNCH_CHECK("pack_quant");
     return KRR_OK;
   }
-  if (prec == KRR_MIXED) return fill_mixed(X, shared, ps, s);
   return fill_f32c(X, shared, ps, s);  // FP32 Gaussian: centred MFMA layout
 }
 

@@ -130,6 +130,7 @@ struct Precond {
   Arena scratch;
   size_t ws_used = 0;
   double build_seconds = 0.0;
+  bool solving = false;  // a stepped solve owns the PCG vectors (krr_solve_begin .. end/free)
 };
 
 // Fixed-order reductions and vector updates (pcg.hip).
@@ -181,6 +182,7 @@ struct Solve {
   std::vector<char> active;
   std::vector<double> history;
   double worst_true = 0.0;
+  std::vector<double> true_rel;  // per column: ||b - M x|| / ||b|| at the last check
   // residual-gap estimates (MIXED full-data solves): the next one is taken
   // once the worst relative recursive residual is at or below gap_next
   // (0: none); pending = its product runs in the next step, read = its sums

@@ -223,6 +223,40 @@ def test_mixed_gaussian_rectangular_rhs(m):
     check_mixed(Xr, Xc, V, 4.0)
 
 
+@pytest.mark.parametrize("d", [4, 20, 33])
+def test_mixed_guard_routes_badly_scaled_jobs_to_direct_differences(d):
+    # Tight clusters far apart: the centred norms are ~1e3 times s^-1, so the
+    # split expansion's exponent error bound s (max||x||^2 + max||y||^2)
+    # (3 2^-16 + (3 kp + 2) 2^-24) is far above the guard's 2^-9 and the
+    # expansion would miss the within-cluster entries by percents.  The direct
+    # tile on FP32 centred points keeps each exponent within
+    # |arg| (d + 2) 2^-24 + 2 s ||x - y|| (||x|| + ||y||) 2^-24, V splits to
+    # 2^-16 and at most 256 terms are summed in FP32.
+    g = np.random.default_rng(400 + d)
+    ncl, per = 12, 110
+    centres = 40.0 * g.standard_normal((ncl, d))
+    X = np.repeat(centres, per, axis=0) + 0.3 * g.standard_normal((ncl * per, d))
+    Xc = X[::2].copy()
+    V = g.standard_normal((Xc.shape[0], 3))
+    sigma = 0.5
+    s = 1.0 / (2 * sigma ** 2)
+    c = Xc.mean(axis=0)
+    R2 = max(np.sum((X - c) ** 2, axis=1).max(), np.sum((Xc - c) ** 2, axis=1).max())
+    kp = 32 * ((d + 31) // 32)
+    assert s * 2 * R2 * (3 * 2 ** -16 + (3 * kp + 2) * 2 ** -24) > 2 ** -9 * 100
+    W = run(0, 2, X, Xc, V, sigma)
+    Kb = OK.block(X, Xc, 0, sigma)
+    ref = Kb @ V
+    scale = np.abs(Kb) @ np.abs(V)
+    # within-cluster distances ~ 0.3^2 * 2d, so |arg| <= s * 4 d (generous)
+    expo = s * 4 * d * (d + 2) * 2 ** -24 + 2 * s * np.sqrt(4 * d * 0.09) * 2 * np.sqrt(R2) * 2 ** -24
+    tol = expo + 4 * 2 ** -24 + 2 * 2 ** -16 + 256 * 2 ** -24
+    err = np.abs(W - ref)
+    assert np.all(err <= tol * scale + 1e-300), (np.max(err / (scale + 1e-300)), tol)
+    # the expansion's own error would be orders larger: the tile did not use it
+    assert tol < 1e-3
+
+
 def test_mixed_laplace_is_fp32_tiles():
     g = np.random.default_rng(9)
     X = g.standard_normal((900, 12))

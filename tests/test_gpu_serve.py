@@ -100,3 +100,29 @@ def test_small_served_stream_matches_alone(workers):
         beta, info = P.solve(T(p.Y), 1e-6, 400)
         assert np.array_equal(beta.cpu().numpy(), res[req.rid].beta)
         assert res[req.rid].relres_true <= 1e-6 * 10
+
+
+def test_active_solve_guards_its_vectors():
+    """While a stepped solve is active its precond refuses the calls that
+    would overwrite the solve's vectors; the solve then ends with the result
+    it has alone, and the precond serves other calls again."""
+    p, prec = problems()[0]
+    P = build(p, prec)
+    ref, _ = P.solve(T(p.Y), 1e-8, 400)
+    S = B().Solve(P, T(p.Y), 1e-8, 400)
+    Z = torch.ones((p.X.shape[0], 1), dtype=torch.float64, device=DEV)
+    for call in (lambda: P.solve(T(p.Y), 1e-8, 400), lambda: P.apply(Z), lambda: P.operator(Z),
+                 lambda: B().Solve(P, T(p.Y), 1e-8, 400)):
+        with pytest.raises(B().KrrError) as e:
+            call()
+        assert e.value.code == -1
+    live = [S]
+    while live:
+        live = [s for s, v in zip(live, B().solve_step(live)) if v == 0]
+    beta, info = S.end()
+    assert np.array_equal(beta.cpu().numpy(), ref.cpu().numpy())
+    P.apply(Z)
+    S2 = B().Solve(P, T(p.Y), 1e-8, 400)
+    S2.free()
+    beta2, _ = P.solve(T(p.Y), 1e-8, 400)
+    assert np.array_equal(beta2.cpu().numpy(), ref.cpu().numpy())
