@@ -1,23 +1,28 @@
-"""Measurements of the workloads other than the headline one (see bench.py):
+"""Measurements beside the headline line of bench.py, and the workloads
+other than the headline one:
 
-* c1 — 2,000-point Gaussian, FP64 tiles, RPCholesky r=100, PCG to 1e-10,
+* the legs bench.py reports as extra keys of its line (functions *_leg):
+  the restricted solve with FP32 tiles, the 100,000-point Laplace problem
+  (FP32 and FP64 solves, tile rate against the FP32 VALU peak), the
+  1,000,000-point Gaussian problem (MIXED, FP32 and FP64 product rates and a
+  MIXED solve) and the served stream (batched MIXED against one request at a
+  time in MIXED and in FP64);
+* c1 -- 2,000-point Gaussian, FP64 tiles, RPCholesky r=100, PCG to 1e-10,
   checked against a dense Cholesky solve;
-* c3 — 1,000,000-point Gaussian (d=32, 8 right-hand sides) on the bf16-split
-  MFMA tiles: per-launch product rate and a whole solve to 1e-6;
-* c4 — 2,000,000-point restricted problem with KRILL (k=10,000): build,
-  restricted product rate, whole solve to 1e-6;
-* c5 — served stream: p50/p99 latency and solves/s, continuously batched on
-  the MIXED path vs the same trace one at a time on the FP64 path;
-* crossover — KRILL (FP64 tiles, PCG to 1e-4) against the direct method
+* c2 -- the 100,000-point Laplace problem alone;
+* c3 -- the 1,000,000-point Gaussian problem alone (--product-only for
+  counter runs);
+* c5 -- the served stream alone (--requests, --order, --no-baseline);
+* crossover -- KRILL (FP64 tiles, PCG to 1e-4) against the direct method
   (form A(S,:)A(:,S) + H, factor, solve) on 500,000 points of the restricted
   workload's distribution for k = 250 .. 16,000 centres (Sec. 4.2's
   runtime-against-centres comparison);
-* ranks — pivot rules against the approximation rank on the 100,000-point
+* ranks -- pivot rules against the approximation rank on the 100,000-point
   Laplace workload (Sec. 3.1's rules; the iterations-to-1e-3 against rank
   study of Sec. 4.1): build time and PCG iterations to a relative residual
   of 1e-3 for RPCholesky, uniform and greedy pivots at r = 125 .. 4000.
 
-Each prints one JSON line in the same shape as the headline line.
+The standalone configurations print one JSON line each.
 """
 import json
 import sys
@@ -89,34 +94,116 @@ def c1(a, b, torch, synth):
                         "kind": "oracle", "cores": 1, "sample": "whole problem"})
 
 
-def c3(a, b, torch, synth):
+F32_PEAK_TFLOPS = 157.3     # MI355X, published FP32 vector / matrix peak
+BF16_PEAK_TFLOPS = 2500.0   # MI355X, published dense bf16 matrix peak
+FP64_PEAK_TFLOPS = 78.6     # MI355X, published FP64 vector / matrix peak
+
+
+def c4_fp32_leg(a, b, torch, synth, ctx):
+    """The headline restricted solve with FP32 tiles (FP64 refinement rounds)."""
+    p = ctx["p"]
+    X = ctx["X"]
+    N, d = p.X.shape
+    Y = torch.from_numpy(p.Y).to(X.device)
+    ws = b.workspace(b.krill_ws(p.kind, b.FP32, N, d, p.centers, p.sketch_rows, p.zeta, 1),
+                     X.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = b.krill_build(p.kind, p.sigma, b.FP32, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
+                      zeta=p.zeta, seed=p.algo_seed, ws=ws)
+    tb = time.perf_counter() - t0
+    beta, info = P.solve(Y, p.tol, 400)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    del P, ws
+    return {"build_s": tb, "time_to_solution_s": tt, "iters": info["iters"],
+            "products": info["products"], "relres_true": info["relres_true"],
+            "converged": info["converged"],
+            "entries_per_s": N * p.centers * (1 + 2 * info["products"]) / tt}
+
+
+def c2_leg(a, b, torch, synth, ctx=None, n=100_000, steps=3):
+    """The 100,000-point Laplace problem: FP32-tile and FP64-tile solves
+    (RPCholesky r = 1000 + PCG to 1e-6 + the FP64 true residual) and the
+    FP32 quantised tile's rate against the published FP32 peak."""
+    p = synth.c2(n=n)
+    N, d = p.X.shape
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(p.Y).cuda()
+    out = {}
+    for name, prec, reps in (("fp32", b.FP32, steps), ("fp64", b.FP64, 1)):
+        ws = b.workspace(b.rpchol_ws(p.kind, prec, N, d, p.rank, 0, 1), X.device)
+        P = b.rpchol_build(p.kind, p.sigma, prec, X, p.mu, p.rank, seed=p.algo_seed, ws=ws)
+        P.solve(Y, p.tol, 1000)
+        del P
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P = b.rpchol_build(p.kind, p.sigma, prec, X, p.mu, p.rank, seed=p.algo_seed, ws=ws)
+            beta, info = P.solve(Y, p.tol, 1000)
+            infos.append(info)
+            del P
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        info = infos[-1]
+        out[name] = {"time_to_solution_s": t, "build_s": info["build_seconds"],
+                     "iters": info["iters"], "products": info["products"],
+                     "relres_true": max(i["relres_true"] for i in infos),
+                     "converged": all(i["converged"] for i in infos),
+                     "entries_per_s": N * N * info["products"] / t}
+        del ws
+    ms = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, 1, launches=5)
+    # the method's VALU work per l1 entry: d differences, d absolute-value
+    # accumulations, one scale, one exp (4 slots) and m = 1 multiply-add,
+    # counted as FP32 operations against the published FP32 peak
+    ops = 2 * d + 5 + 1
+    out["fp32_tile"] = {"kernel": "tile_lapq<20, 1, 4> (quantised l1, v_sad_u32, FP32 exp)",
+                        "launch_ms": ms, "entries_per_launch": N * N, "ops_per_entry": ops,
+                        "tops": ops * N * N / (ms * 1e-3) / 1e12,
+                        "frac_of_fp32_peak": ops * N * N / (ms * 1e-3) / 1e12 / F32_PEAK_TFLOPS}
+    return out
+
+
+def c2(a, b, torch, synth):
+    res = c2_leg(a, b, torch, synth, n=a.n, steps=a.steps)
+    _line(value=res["fp32"]["entries_per_s"], unit="kernel entries/s", steps=a.steps, warmup=1,
+          ms_per_step=res["fp32"]["time_to_solution_s"] * 1e3, dtype="f32",
+          config={"workload": f"full-data KRR, l1 Laplace, N={a.n}, d=20, 10-component Gaussian "
+                              "mixture, sigma=20, mu=1e-4 N, RPCholesky r=1000, PCG to 1e-6 "
+                              "(FP32 tiles, FP64 CG)"},
+          result=res)
+
+
+def c3_leg(a, b, torch, synth, ctx=None, solve=True):
+    """The 1,000,000-point Gaussian problem (d = 32, 8 right-hand sides):
+    product rates of the MIXED, FP32 and FP64 tiles and a MIXED solve to an
+    FP64 true residual of 1e-6."""
     p = synth.c3()
     N, d = p.X.shape
     X = torch.from_numpy(p.X).cuda()
     Y = torch.from_numpy(p.Y).cuda()
     m = p.Y.shape[1]
-    if a.product_only:
-        prec = b.FP32 if a.fp32 else b.MIXED
-        ms = _product_rate(b, torch, p.kind, p.sigma, prec, X, m)
-        print(json.dumps({"product_ms": ms, "entries_per_launch": N * N}), flush=True)
-        return
+    out = {}
     ms = _product_rate(b, torch, p.kind, p.sigma, b.MIXED, X, m)
     rate = N * N / (ms * 1e-3)
-    # executed MFMA work per entry: 3 split products of K=32 for the distance
-    # and 3 of K=16-column V tiles, 2 flops per multiply-add
+    # executed MFMA work per entry: 3 split products of K = 32 for the
+    # distance and 3 of the 16-column V tiles, 2 flops per multiply-add
     mfma_flops = (3 * 2 * 32) + (3 * 2 * 16)
-    out = {"product_ms": ms, "entries_per_s": rate,
-           "mfma_tflops_executed": rate * mfma_flops / 1e12,
-           "mfma_frac_of_bf16_peak": rate * mfma_flops / 2.5e15}
+    out["mixed_product"] = {"launch_ms": ms, "entries_per_s": rate,
+                            "mfma_tflops_executed": rate * mfma_flops / 1e12,
+                            "frac_of_bf16_peak_executed": rate * mfma_flops / 1e12 / BF16_PEAK_TFLOPS}
     ms32 = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, m, launches=2)
-    # FP32 tiles: distance (K = 32) and E.V (16 rhs columns) on
-    # v_mfma_f32_16x16x4f32, 2 flops per multiply-add
-    f32_flops = 2 * 32 + 2 * 16
-    out.update(fp32_product_ms=ms32, fp32_entries_per_s=N * N / (ms32 * 1e-3),
-               fp32_mfma_tflops=N * N * f32_flops / (ms32 * 1e-3) / 1e12,
-               fp32_mfma_frac_of_peak=N * N * f32_flops / (ms32 * 1e-3) / 157.3e12)
-    steps = []
-    if a.steps > 0:
+    f32_flops = 2 * 32 + 2 * 16   # distance (K = 32) and E.V (16 columns) on the f32 MFMA
+    out["fp32_product"] = {"launch_ms": ms32, "entries_per_s": N * N / (ms32 * 1e-3),
+                           "frac_of_fp32_peak": N * N * f32_flops / (ms32 * 1e-3) / 1e12 /
+                           F32_PEAK_TFLOPS}
+    ms64 = _product_rate(b, torch, p.kind, p.sigma, b.FP64, X, m, launches=2)
+    f64_flops = 2 * 32 + 2 + 2 * m  # distance, norms, E.V on the VALU
+    out["fp64_product"] = {"launch_ms": ms64, "entries_per_s": N * N / (ms64 * 1e-3),
+                           "frac_of_fp64_peak": N * N * f64_flops / (ms64 * 1e-3) / 1e12 /
+                           FP64_PEAK_TFLOPS}
+    if solve:
         ws = b.workspace(b.rpchol_ws(p.kind, b.MIXED, N, d, p.rank, 0, m), X.device)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -132,78 +219,41 @@ def c3(a, b, torch, synth):
                       flush=True)
         beta, info = S.end()
         torch.cuda.synchronize()
-        steps.append(time.perf_counter() - t0)
-        out.update(solve_s=steps[0], build_s=info["build_seconds"], iters=info["iters"],
-                   relres_true=info["relres_true"], relres_recursive=info["relres_recursive"],
-                   rank=P.dims()[0], converged=info["converged"])
-    _line(value=rate, unit="kernel entries/s", steps=len(steps), warmup=0,
-          ms_per_step=(steps[0] * 1e3 if steps else None), dtype="bf16x3/f32",
+        out["mixed_solve"] = {"time_to_solution_s": time.perf_counter() - t0,
+                              "build_s": info["build_seconds"], "iters": info["iters"],
+                              "products": info["products"], "relres_true": info["relres_true"],
+                              "relres_recursive": info["relres_recursive"],
+                              "rank": P.dims()[0], "converged": info["converged"]}
+        del P, S, ws
+    return out
+
+
+def c3(a, b, torch, synth):
+    if a.product_only:
+        p = synth.c3()
+        X = torch.from_numpy(p.X).cuda()
+        prec = b.FP32 if a.fp32 else b.MIXED
+        ms = _product_rate(b, torch, p.kind, p.sigma, prec, X, p.Y.shape[1])
+        print(json.dumps({"product_ms": ms, "entries_per_launch": p.X.shape[0] ** 2}), flush=True)
+        return
+    res = c3_leg(a, b, torch, synth, solve=a.steps > 0)
+    sol = res.get("mixed_solve", {})
+    _line(value=res["mixed_product"]["entries_per_s"], unit="kernel entries/s",
+          steps=1 if sol else 0, warmup=0,
+          ms_per_step=sol["time_to_solution_s"] * 1e3 if sol else None, dtype="bf16x3/f32",
           config={"workload": "full-data KRR, Gaussian, N=1e6, d=32, uniform [0,1]^32 with 5% "
                               "near-duplicates, 8 RHS, sigma=1.5, mu=1e-6 N, RPCholesky r=2000, "
                               "bf16-split MFMA tiles, PCG to 1e-6"},
-          result=out)
-
-
-def c4(a, b, torch, synth):
-    p = synth.c4()
-    N, d = p.X.shape
-    X = torch.from_numpy(p.X).cuda()
-    Y = torch.from_numpy(p.Y).cuda()
-    if a.product_only:
-        # 5 launches of the restricted product's first half, K(X, X(S,:)) v
-        # (2e6 x 1e4 entries), for counter runs
-        prec = b.FP32 if a.fp32 else b.FP64
-        S = torch.from_numpy(np.sort(np.random.default_rng(2).choice(N, p.centers, replace=False)))
-        C = X[S.cuda()].contiguous()
-        V = torch.from_numpy(np.random.default_rng(0).standard_normal((p.centers, 1))).cuda()
-        ws = b.workspace(b.kernel_matvec_ws(prec, N, p.centers, d, 1), X.device)
-        W = torch.empty((N, 1), dtype=torch.float64, device=X.device)
-        for _ in range(5):
-            b.kernel_matvec(p.kind, p.sigma, prec, X, C, V, out=W, ws=ws)
-        torch.cuda.synchronize()
-        print(json.dumps({"product_launches": 5, "entries_per_launch": N * p.centers}), flush=True)
-        return
-    res = {}
-    for prec, name in ((b.FP32, "fp32"), (b.FP64, "fp64")):
-        ws = b.workspace(b.krill_ws(p.kind, prec, N, d, p.centers, p.sketch_rows, p.zeta, 1),
-                         X.device)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        P = b.krill_build(p.kind, p.sigma, prec, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
-                          zeta=p.zeta, seed=p.algo_seed, ws=ws)
-        tb = time.perf_counter() - t0
-        beta, info = P.solve(Y, p.tol, 200)
-        torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
-        # restricted operator timing (two products of N x k entries each)
-        V = torch.from_numpy(np.random.default_rng(1).standard_normal((p.centers, 1))).cuda()
-        P.operator(V)
-        torch.cuda.synchronize()
-        b.timing_read()
-        b.timing_enable(True)
-        t1 = time.perf_counter()
-        for _ in range(3):
-            P.operator(V)
-        torch.cuda.synchronize()
-        top = (time.perf_counter() - t1) / 3
-        b.timing_enable(False)
-        tms, tn = b.timing_read()
-        res[name] = {"build_s": tb, "solve_total_s": tt, "iters": info["iters"],
-                     "relres_true": info["relres_true"], "operator_ms": top * 1e3,
-                     "tile_ms_per_launch": tms / max(tn, 1),
-                     "entries_per_s": 2 * N * p.centers / top}
-        del P, ws
-        torch.cuda.empty_cache()
-    _line(value=res["fp32"]["entries_per_s"], unit="kernel entries/s", steps=1, warmup=0,
-          ms_per_step=res["fp32"]["solve_total_s"] * 1e3, dtype="f32",
-          config={"workload": "restricted KRR with KRILL, Gaussian sigma=4, N=2e6, d=16, "
-                              "k=10000 centres, sketch 20000 x 8 nonzeros, mu=1e-5 N, PCG to 1e-6"},
           result=res)
 
 
-def c5(a, b, torch, synth):
+def c5_leg(a, b, torch, synth, ctx=None, requests=None, baselines=True):
+    """The served stream: batched MIXED (continuous batching, builds on a
+    worker thread), then the same arrival trace one request at a time in
+    MIXED and in FP64."""
     from paper_2304_12465_amd.serve import Server, GpuBackend, serve_one_at_a_time, summarize
-    stream = synth.c5_stream(count=a.requests)
+    count = requests or a.requests
+    stream = synth.c5_stream(count=count)
     # the requests' arrays are generated before the clock starts: they stand
     # for data that arrives with each request, not for serving work
     probs = {}
@@ -212,30 +262,37 @@ def c5(a, b, torch, synth):
         if (i + 1) % 32 == 0:
             print(f"c5: generated {i + 1} of {len(stream)} requests", file=sys.stderr, flush=True)
     make = lambda req: probs[req.rid]
-    be = GpuBackend(b.MIXED, tol=1e-6, max_iter=500)
 
     def progress(tag):
         def f(r):
             print(f"c5 {tag}: request {r.rid} {r.status} latency {r.latency:.2f} s",
                   file=sys.stderr, flush=True)
         return f
+    be = GpuBackend(b.MIXED, tol=1e-6, max_iter=500)
     srv = Server(be, hbm_budget=160 << 30, max_active=64, on_finish=progress("batched"),
                  build_workers=a.build_workers, order=a.order)
     t0 = time.perf_counter()
     res = srv.run(stream, make)
-    tmix = time.perf_counter() - t0
-    s_mix = summarize(res)
-    out = {"batched_mixed": s_mix, "batched_wall_s": tmix, "admission_order": a.order}
-    if not a.no_baseline:
-        be64 = GpuBackend(b.FP64, tol=1e-6, max_iter=500)
-        res64 = serve_one_at_a_time(be64, stream, make, on_finish=progress("fp64"))
-        out["one_at_a_time_fp64"] = summarize(res64)
+    out = {"requests": count, "batched_mixed": summarize(res),
+           "batched_wall_s": time.perf_counter() - t0, "admission_order": a.order}
+    if baselines:
+        for tag, prec in (("one_at_a_time_mixed", b.MIXED), ("one_at_a_time_fp64", b.FP64)):
+            torch.cuda.empty_cache()
+            res1 = serve_one_at_a_time(GpuBackend(prec, tol=1e-6, max_iter=500), stream, make,
+                                       on_finish=progress(tag))
+            out[tag] = summarize(res1)
+    return out
+
+
+def c5(a, b, torch, synth):
+    res = c5_leg(a, b, torch, synth, baselines=not a.no_baseline)
+    s_mix = res["batched_mixed"]
     _line(value=s_mix["solves_per_s"], unit="solves/s", steps=1, warmup=0,
-          ms_per_step=tmix * 1e3, dtype="bf16x3/f32 (Gaussian), f32 (Laplace)",
+          ms_per_step=res["batched_wall_s"] * 1e3, dtype="bf16x3/f32 (Gaussian), f32 (Laplace)",
           config={"workload": f"served stream: {a.requests} requests, Poisson 20/s, N log-uniform "
                               "[1e4, 3e5], d in {8,16,32}, Gaussian/Laplace, 1-16 RHS, "
                               "r=min(1000, N/50), PCG to 1e-6"},
-          result=out)
+          result=res)
 
 
 def ranks(a, b, torch, synth):
@@ -327,5 +384,5 @@ def run(a):
     import torch
     import synth
     from paper_2304_12465_amd import binding as b
-    {"c1": c1, "c3": c3, "c4": c4, "c5": c5, "ranks": ranks,
+    {"c1": c1, "c2": c2, "c3": c3, "c5": c5, "ranks": ranks,
      "crossover": crossover}[a.config](a, b, torch, synth)

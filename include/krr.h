@@ -104,6 +104,8 @@ typedef struct {
   double* history;          /* host, optional: max relative residual per iteration */
   int32_t history_cap;      /* capacity of history (in entries) */
   int32_t history_len;      /* entries written */
+  int32_t products;         /* system-operator applications: one per PCG step
+                               plus one per FP64 true-residual check */
 } krr_solve_info;
 
 /* Full-data KRR (eq. exact_eqn): (A + mu I) beta = y with A_ij = K(x_i, x_j),

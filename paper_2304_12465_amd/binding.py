@@ -29,7 +29,7 @@ class SolveInfo(ctypes.Structure):
                 ("relres_recursive", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("build_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
-                ("history_len", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("products", ctypes.c_int32)]
 
 
 _pp = ctypes.POINTER(ctypes.c_void_p)
@@ -241,7 +241,7 @@ class Precond:
         d = dict(iters=info.iters, converged_cols=info.converged_cols,
                  relres_recursive=info.relres_recursive, relres_true=info.relres_true,
                  build_seconds=info.build_seconds, solve_seconds=info.solve_seconds,
-                 converged=(rc == 0))
+                 products=info.products, converged=(rc == 0))
         if hist is not None:
             d["history"] = [hist[i] for i in range(info.history_len)]
         return (beta.reshape(-1) if Y.dim() == 1 else beta), d
@@ -373,7 +373,7 @@ class Solve:
         d = dict(iters=info.iters, converged_cols=info.converged_cols,
                  relres_recursive=info.relres_recursive, relres_true=info.relres_true,
                  build_seconds=info.build_seconds, solve_seconds=info.solve_seconds,
-                 converged=(rc == 0))
+                 products=info.products, converged=(rc == 0))
         if hist is not None:
             d["history"] = [hist[i] for i in range(info.history_len)]
         return beta, d

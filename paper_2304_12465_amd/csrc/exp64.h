@@ -39,4 +39,33 @@ __device__ __forceinline__ double exp64(double x, const double* __restrict__ tab
   return ldexp(__builtin_fma(t, p, t), k >> 6);
 }
 
+// The same exponential for an argument given in units of ln2/64:
+// exp64_u(a * 64/ln2) = exp(a).  Callers fold the factor 64/ln2 into the
+// multiply-add that forms the exponent, so the reduction is n = rint(u),
+// v = u - n (exact, |v| <= 1/2) and e^r - 1 with r = v ln2/64 comes from a
+// degree-5 polynomial in v whose coefficients carry the powers of ln2/64
+// (truncation below 3.6e-17, as above).  Forming u rounds it to about
+// 3 eps |a| more than the exponent itself carries, well inside the error
+// the kernel tiles allow per entry for the |a| where exp(a) is not
+// negligible.  Precondition: |u| < 2^30 or u = NaN (no clamp: callers whose
+// exponents are bounded use this form); larger magnitudes saturate the
+// conversion and are not supported.
+__device__ __forceinline__ double exp64_u(double u, const double* __restrict__ tab) {
+  constexpr double kC1 = 0x1.62e42fefa39efp-7;   // (ln2/64)
+  constexpr double kC2 = 0x1.ebfbdff82c58fp-15;  // (ln2/64)^2 / 2
+  constexpr double kC3 = 0x1.c6b08d704a0cp-23;   // (ln2/64)^3 / 6
+  constexpr double kC4 = 0x1.3b2ab6fba4e77p-31;  // (ln2/64)^4 / 24
+  constexpr double kC5 = 0x1.5d87fe78a6731p-40;  // (ln2/64)^5 / 120
+  const double n = __builtin_rint(u);
+  const double v = u - n;
+  const int k = (int)n;
+  const double t = tab[k & (kExpTable - 1)];
+  double p = __builtin_fma(v, kC5, kC4);
+  p = __builtin_fma(v, p, kC3);
+  p = __builtin_fma(v, p, kC2);
+  p = __builtin_fma(v, p, kC1);
+  return ldexp(__builtin_fma(t, p * v, t), k >> 6);
+}
+constexpr double kExpUScale = 92.33248261689366;  // 64 / ln2
+
 }  // namespace krr

@@ -629,6 +629,7 @@ int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
     info->converged_cols = conv;
     info->relres_recursive = worst_rec;
     info->relres_true = S.worst_true;
+    info->products = S.it + S.restarts + 1;
     info->build_seconds = P.build_seconds;
     info->solve_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();

@@ -4,8 +4,9 @@
 // ||x - y||^2 = ||x||^2 + ||y||^2 - 2 x.y with the contraction on the MFMA
 // over centred points (centring keeps the expansion's cancellation at
 // ~eps ||x||^2).  The distance MFMA starts from -||x||^2 / 2, so one FMA
-// gives the exponent; exp runs on the VALU (FP64: the table-driven exp64;
-// FP32: v_exp_f32 on an exponent scaled by log2 e).  The reduction against V
+// gives the exponent; exp runs on the VALU (FP64: the table-driven exp64_u
+// on an exponent scaled by 64/ln2; FP32: v_exp_f32 on an exponent scaled by
+// log2 e).  The reduction against V
 // is a second MFMA for more than 4 right-hand sides: the distance output
 // layout (lane l holds, for t = 0..3, column col(t, l/16) of row l % 16) is
 // the A-operand layout of K-step t of the 16x16x4 MFMA with K index l / 16
@@ -338,7 +339,10 @@ __global__ __launch_bounds__(256) void tile_gauss_direct(const GTable<T> tab) {
           const T t = x[k] - y[k];
           s = fma_g(t, t, s);
         }
-        const T e = GT<T>::ex(-J.s * s, etab);
+        // direct differences serve unbounded exponents: the clamped exp64
+        T e;
+        if constexpr (kF32) e = GT<T>::ex(-J.s * s, etab);
+        else e = exp64(-J.s_nat * s, etab);
         const T* __restrict__ v = J.v + j * 16;
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[c] = fma_g(e, v[c], acc[c]);
@@ -513,8 +517,9 @@ int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T*
   j.nc = nc;
   j.per = sp.per;
   j.item0 = 0;
-  // FP32 exponents are in base 2 (v_exp_f32)
-  j.s = std::is_same<T, float>::value ? (T)(1.4426950408889634 * s_nat) : (T)s_nat;
+  // exponents in the units of the tile's exp: base 2 for FP32 (v_exp_f32),
+  // ln2/64 for FP64 (exp64_u)
+  j.s = (T)(GT<T>::kExpScale * s_nat);
   j.s_nat = s_nat;
   j.nsplit = sp.nsplit;
   j.M = mc;

@@ -39,7 +39,7 @@ struct SketchJob {
   const int* row_of;       // sketch row of every entry
   int64_t ds;
   int rows_per_wg;
-  T s;           // exponent scale: s_nat (FP64) or log2(e) s_nat (FP32, exp2)
+  T s;           // exponent scale: 64/ln2 s_nat (FP64, exp64_u) or log2(e) s_nat (FP32, exp2)
   double s_nat;  // 1 / (2 sigma^2)
   int dpad;
   double inv_sqrt_zeta;
@@ -265,7 +265,7 @@ int launch_sketch(double sigma, int dpad, const T* cc, const T* cn, const T* cma
   J.ds = ds;
   J.rows_per_wg = (int)std::max<int64_t>(8, ceil_div(ds, 65535));
   J.s_nat = 1.0 / (2.0 * sigma * sigma);
-  J.s = std::is_same<T, float>::value ? (T)(1.4426950408889634 * J.s_nat) : (T)J.s_nat;
+  J.s = (T)(GT<T>::kExpScale * J.s_nat);
   J.dpad = dpad;
   J.inv_sqrt_zeta = inv_sqrt_zeta;
   J.B = B;

@@ -38,6 +38,7 @@ class Result:
     status: str = "pending"   # done | failed | rejected
     iters: int = 0
     relres_true: float = float("nan")
+    converged: bool = False   # the solve met tol (on the FP64 true residual for FP32 / MIXED)
     error: str = ""
     beta: object = None
 
@@ -231,6 +232,7 @@ class Server:
                         r.status = "done"
                         r.iters = info["iters"]
                         r.relres_true = info["relres_true"]
+                        r.converged = info["converged"]
                         r.beta = beta
                     except Exception as e:
                         r.status, r.error = "failed", str(e)
@@ -268,6 +270,7 @@ def serve_one_at_a_time(backend, stream, make_problem, clock=time.perf_counter,
                 beta, info = backend.finish(h)
                 r.status, r.iters, r.relres_true, r.beta = "done", info["iters"], \
                     info["relres_true"], beta
+                r.converged = info["converged"]
         except Exception as e:
             r.status, r.error = "failed", str(e)
         r.finished = clock() - t0
@@ -287,6 +290,9 @@ def summarize(results):
         "done": done,
         "failed": sum(r.status == "failed" for r in results.values()),
         "rejected": sum(r.status == "rejected" for r in results.values()),
+        "not_converged": sum(r.status == "done" and not r.converged for r in results.values()),
+        "max_relres_true": max((r.relres_true for r in results.values() if r.status == "done"),
+                               default=None),
         "p50_s": float(np.percentile(lat, 50)) if done else None,
         "p99_s": float(np.percentile(lat, 99)) if done else None,
         "mean_s": float(lat.mean()) if done else None,

@@ -230,16 +230,35 @@ def test_full_size_laplace_solve(prec):
     P = build(p, prec)
     beta, info = P.solve(T(p.Y), p.tol, max_iter=500)
     assert info["converged"], info
-    if prec == 0:
-        assert info["relres_true"] <= 10 * p.tol, info
+    # FP64 tiles: recursive residual to tol, true residual within 10 tol;
+    # FP32 tiles: refinement brings the FP64 true residual itself to tol
+    assert info["relres_true"] <= (10 * p.tol if prec == 0 else p.tol), info
     beta = beta.cpu().numpy()
     g = np.random.default_rng(1)
     rows = np.sort(g.choice(p.X.shape[0], 256, replace=False))
     res = p.Y[rows] - (OK.matvec(p.X[rows], p.X, beta, p.kind, p.sigma) + p.mu * beta[rows])
     est = np.sqrt(p.X.shape[0] / 256) * np.linalg.norm(res) / np.linalg.norm(p.Y)
-    assert est <= 20 * p.tol if prec == 0 else est <= 1e-4, est
+    assert est <= 20 * p.tol, est
     # first block of pivots: diag(A) = 1, so they follow the closed form of the sampler
     from oracle.rng import sm, key, u53, TAG_PIVOT
     kb = sm(key(p.algo_seed, TAG_PIVOT), 0)
     first = sorted(set(int(u53(sm(kb, t)) * p.X.shape[0]) for t in range(100)))
     assert P.pivots()[:len(first)] == first
+
+
+def test_full_size_mixed_gaussian_solve():
+    # 1,000,000 points in [0,1]^32 with 5% near-duplicates, 8 right-hand
+    # sides, rank 2000, MIXED tiles with FP64 refinement: the reported FP64
+    # true residual meets tol, and the oracle re-checks it on 96 sampled rows
+    # (mean squared row residual scaled to all N rows, per column).
+    p = synth.c3()
+    m = p.Y.shape[1]
+    P = build(p, 2, m_max=m)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=400)
+    assert info["converged"] and info["relres_true"] <= p.tol, info
+    beta = beta.cpu().numpy()
+    N = p.X.shape[0]
+    rows = np.sort(np.random.default_rng(6).choice(N, 96, replace=False))
+    res = p.Y[rows] - (OK.matvec(p.X[rows], p.X, beta, p.kind, p.sigma) + p.mu * beta[rows])
+    est = np.sqrt((res ** 2).sum(axis=0) * N / rows.size) / np.linalg.norm(p.Y, axis=0)
+    assert np.all(est <= 20 * p.tol), est

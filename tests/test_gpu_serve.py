@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import synth
+from oracle import kernels as OK
 from paper_2304_12465_amd.serve import Server, GpuBackend, summarize
 
 pytestmark = pytest.mark.gpu
@@ -99,7 +100,14 @@ def test_small_served_stream_matches_alone(workers):
                              m_max=p.Y.shape[1])
         beta, info = P.solve(T(p.Y), 1e-6, 400)
         assert np.array_equal(beta.cpu().numpy(), res[req.rid].beta)
-        assert res[req.rid].relres_true <= 1e-6 * 10
+        # MIXED solves meet tol on the FP64 true residual; the oracle re-checks
+        # it on 128 sampled rows (scaled to all rows, per right-hand side)
+        assert res[req.rid].converged and res[req.rid].relres_true <= 1e-6
+        bh = res[req.rid].beta
+        rows = np.sort(np.random.default_rng(req.rid).choice(p.X.shape[0], 128, replace=False))
+        r = p.Y[rows] - (OK.matvec(p.X[rows], p.X, bh, p.kind, p.sigma) + p.mu * bh[rows])
+        est = np.sqrt((r ** 2).sum(axis=0) * p.X.shape[0] / 128) / np.linalg.norm(p.Y, axis=0)
+        assert np.all(est <= 20e-6), est
 
 
 def test_active_solve_guards_its_vectors():

@@ -110,3 +110,43 @@ def test_shifted_product_and_diag():
     w = K.matvec(X, X, v, K.GAUSSIAN, 1.0, shift=0.5)
     np.testing.assert_allclose(w, brute(X, X, K.GAUSSIAN, 1.0) @ v + 0.5 * v, rtol=1e-13)
     np.testing.assert_array_equal(K.diag(X, K.LAPLACE, 1.0), np.ones(20))
+
+
+def test_fast_expansion_mode_matches_direct_differences():
+    """The oracle's BLAS-expansion timing mode against its exact mode: each
+    exponent of the expansion carries at most about (d + 4) eps s
+    (||x - c||^2 + ||y - c||^2) (rounding of the two norms, the d-term dot
+    product and the sum; c = column mean), so entries agree to that relative
+    amount; Laplace blocks are the direct form itself."""
+    g = np.random.default_rng(77)
+    eps = 2.0 ** -52
+    for d, sigma, shift in ((3, 0.7, 0.0), (16, 4.0, 2.0), (32, 1.5, 0.5)):
+        Xr = g.standard_normal((300, d)) + shift
+        Xc = g.standard_normal((500, d)) + shift
+        Ke = K.block(Xr, Xc, K.GAUSSIAN, sigma)
+        Kf = K.block_fast(Xr, Xc, K.GAUSSIAN, sigma)
+        c = Xc.mean(axis=0)
+        nr = np.sum((Xr - c) ** 2, axis=1)[:, None]
+        nc = np.sum((Xc - c) ** 2, axis=1)[None, :]
+        bound = 2 * (d + 4) * eps * (nr + nc) / (2 * sigma ** 2) * np.maximum(Ke, Kf) + 1e-300
+        assert np.all(np.abs(Kf - Ke) <= bound), np.max(np.abs(Kf - Ke) / bound)
+        V = g.standard_normal((500, 2))
+        np.testing.assert_allclose(K.matvec(Xr, Xc, V, K.GAUSSIAN, sigma, fast=True),
+                                   K.matvec(Xr, Xc, V, K.GAUSSIAN, sigma),
+                                   rtol=1e-12, atol=1e-13 * np.abs(Ke).sum(axis=1).max())
+    Xr = g.standard_normal((50, 5))
+    np.testing.assert_array_equal(K.block_fast(Xr, Xr, K.LAPLACE, 2.0),
+                                  K.block(Xr, Xr, K.LAPLACE, 2.0))
+
+
+def test_fast_mode_dropped_factor_is_caught():
+    """A plausible mistake in the fast mode (sigma^2 instead of 2 sigma^2)
+    trips the cross-check above."""
+    import pytest
+    orig = K.block_fast
+    try:
+        K.block_fast = lambda Xr, Xc, kind, sigma: orig(Xr, Xc, kind, sigma / np.sqrt(2.0))
+        with pytest.raises(AssertionError):
+            test_fast_expansion_mode_matches_direct_differences()
+    finally:
+        K.block_fast = orig

@@ -59,7 +59,7 @@ class FakeBackend:
 
     def finish(self, h):
         self.used -= h["p"]["fp"]
-        return None, {"iters": h["p"]["steps"], "relres_true": 1e-7}
+        return None, {"iters": h["p"]["steps"], "relres_true": 1e-7, "converged": True}
 
     def cancel(self, h):
         self.used -= h["p"]["fp"]
