@@ -79,6 +79,25 @@ int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precision prec,
                       void* ws, size_t ws_bytes, hipStream_t stream);
 
 
+/* The same product for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the point layouts and partial sums live
+ * in a fixed scratch array of 256 MiB that the library keeps in device
+ * memory, one per GPU, for the life of the process.  The call performs no
+ * hipMalloc, hipFree or other allocation (tile timing, when enabled with
+ * krr_timing_enable, creates HIP events: leave it off in such callers).
+ * Arguments, layouts, limits and results are those of krr_kernel_matvec
+ * (bitwise the same output).  A product whose krr_kernel_matvec_ws size
+ * exceeds 256 MiB returns KRR_EWORKSPACE before any launch.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must be serialised by the
+ * caller; the array keeps the last call's contents, none of which a later
+ * call reads.                                                             */
+int krr_kernel_matvec_noalloc(krr_kernel_kind kind, double sigma, krr_precision prec,
+                              const double* Xr, int64_t nr, const double* Xc, int64_t nc,
+                              int32_t d, const double* V, int32_t m, double shift, double* W,
+                              hipStream_t stream);
+
 /* Timing of the fused product tiles (the dominant kernel): when enabled,
  * every tile launch is bracketed by HIP events recorded on the stream it
  * runs on.  krr_timing_read waits for the recorded launches, returns their

@@ -68,6 +68,8 @@ _SIGS = {
     "krr_kernel_matvec_ws": ([_i32, _i64, _i64, _i32, _i32, _szp], _i32),
     "krr_kernel_matvec": ([_i32, _dbl, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _i32, _dbl, _vp,
                            _vp, _sz, _vp], _i32),
+    "krr_kernel_matvec_noalloc": ([_i32, _dbl, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _i32,
+                                   _dbl, _vp, _vp], _i32),
 }
 
 
@@ -144,6 +146,22 @@ def kernel_matvec(kind, sigma, prec, Xr, Xc, V, shift=0.0, out=None, ws=None):
     check(lib().krr_kernel_matvec(kind, float(sigma), prec, _ptr(Xr), nr, _ptr(Xc), nc, d,
                                   _ptr(V2), m, float(shift), _ptr(W), _ptr(ws), ws.numel(),
                                   _stream(Xr.device)))
+    return W.reshape(-1) if squeeze else W
+
+
+def kernel_matvec_noalloc(kind, sigma, prec, Xr, Xc, V, shift=0.0, out=None):
+    """W = K(Xr, Xc) V + shift V through the allocation-free entry point (the
+    library's fixed device scratch; `out` may be preallocated)."""
+    _f64(Xr), _f64(Xc), _f64(V)
+    squeeze = V.dim() == 1
+    V2 = V.reshape(-1, 1) if squeeze else V
+    nr, d = Xr.shape
+    nc = Xc.shape[0]
+    m = V2.shape[1]
+    W = out if out is not None else torch.empty((nr, m), dtype=torch.float64, device=Xr.device)
+    check(lib().krr_kernel_matvec_noalloc(kind, float(sigma), prec, _ptr(Xr), nr, _ptr(Xc), nc,
+                                          d, _ptr(V2), m, float(shift), _ptr(W),
+                                          _stream(Xr.device)))
     return W.reshape(-1) if squeeze else W
 
 

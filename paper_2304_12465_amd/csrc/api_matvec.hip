@@ -2,6 +2,7 @@
 #include "product.h"
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace krr {
 
@@ -125,6 +126,61 @@ extern "C" int krr_kernel_matvec(krr_kernel_kind kind, double sigma, krr_precisi
                                  int32_t d, const double* V, int32_t m, double shift, double* W,
                                  void* ws, size_t ws_bytes, hipStream_t stream) {
   return matvec_impl(kind, sigma, prec, Xr, nr, Xc, nc, d, V, m, shift, W, ws, ws_bytes, stream);
+}
+
+// ---- allocation-free product ------------------------------------------------
+// A fixed scratch array in device memory for krr_kernel_matvec_noalloc: every
+// GPU the library runs on holds its own copy for the life of the process.
+// Host code never uses the array's name as an address: the device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and kept per device.
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int device_scratch(void** out) {
+  int dev = -1;
+  KRR_TRY(hip_check(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d out of range for the fixed scratch table", dev);
+    return KRR_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    KRR_TRY(hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                      "hipGetSymbolAddress(scratch)"));
+    if (!p) {
+      set_error("hipGetSymbolAddress(scratch) returned NULL");
+      return KRR_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return KRR_OK;
+}
+}  // namespace
+
+extern "C" int krr_kernel_matvec_noalloc(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                         const double* Xr, int64_t nr, const double* Xc,
+                                         int64_t nc, int32_t d, const double* V, int32_t m,
+                                         double shift, double* W, hipStream_t stream) {
+  KRR_TRY(validate_matvec(kind, sigma, prec, nr, nc, d, m));
+  const size_t need = matvec_bytes(kind, prec, nr, nc, d, m);
+  if (need > kNoAllocScratchBytes) {
+    set_error("product needs %zu bytes of scratch; the fixed scratch holds %zu "
+              "(use krr_kernel_matvec with a workspace)", need, kNoAllocScratchBytes);
+    return KRR_EWORKSPACE;
+  }
+  if (nr == 0) return KRR_OK;
+  void* ws = nullptr;
+  KRR_TRY(device_scratch(&ws));
+  return matvec_impl(kind, sigma, prec, Xr, nr, Xc, nc, d, V, m, shift, W, ws,
+                     kNoAllocScratchBytes, stream);
 }
 
 extern "C" int krr_timing_enable(int on) {

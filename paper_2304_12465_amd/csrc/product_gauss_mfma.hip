@@ -224,7 +224,8 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
     }
   }
   if (row0 >= nr) return;
-  double* __restrict__ out = J.part + (int64_t)split * nr * 16;
+  // partial slots: split-major, rows of J.M values (the product's columns)
+  double* __restrict__ out = J.part + (int64_t)split * nr * J.M;
   if constexpr (MV == 0) {
 #pragma unroll
     for (int rt = 0; rt < kRTg; ++rt)
@@ -234,7 +235,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
         const int64_t i = row0 + rt * 16 + GT<T>::col(t, g);
         const double w = kF32 ? fold[rt][t] + ((double)acc[rt][0][t] + (double)acc[rt][1][t])
                               : (double)acc[rt][0][t] + (double)acc[rt][1][t];
-        if (i < nr && li < J.M) out[i * 16 + li] = w;
+        if (i < nr && li < J.M) out[i * J.M + li] = w;
       }
   } else {
 #pragma unroll
@@ -247,7 +248,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
         a += __shfl_xor(a, 16);
         a += __shfl_xor(a, 32);
         const int64_t i = row0 + rt * 16 + li;
-        if (g == 0 && i < nr && c < J.M) out[i * 16 + c] = a;
+        if (g == 0 && i < nr && c < J.M) out[i * J.M + c] = a;
       }
   }
 }
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(256) void tile_gauss_direct(const GTable<T> tab) {
     }
     __syncthreads();
     if (h == 0 && i < nr) {
-      double* __restrict__ out = J.part + (int64_t)split * nr * 16 + i * 16;
+      double* __restrict__ out = J.part + ((int64_t)split * nr + i) * J.M;
       for (int c = 0; c < J.M; ++c) out[c] = acc64[c] + sW[r][c];
     }
   }

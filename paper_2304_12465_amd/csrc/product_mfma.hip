@@ -241,7 +241,8 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
     }
   }
   if (row0 >= nr) return;
-  double* __restrict__ out = J.part + (int64_t)split * nr * 16;
+  // partial slots: split-major, rows of J.M values (the product's columns)
+  double* __restrict__ out = J.part + (int64_t)split * nr * J.M;
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt) {
 #pragma unroll
@@ -249,7 +250,7 @@ __device__ __forceinline__ void mfma_item(const MfmaJob& J, int64_t rg, int spli
       // E.V output: lane l holds W[i0 + 4g + u][c = li]
       const int64_t i = row0 + rt * 16 + 4 * g + u;
       if (i < nr && li < J.M)
-        out[i * 16 + li] = sAcc[wave][rt * 4 + u][lane] + (double)acc[rt][u];
+        out[i * J.M + li] = sAcc[wave][rt * 4 + u][lane] + (double)acc[rt][u];
     }
   }
 }
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256) void tile_mixed_direct(const MJobTable tab) {
       for (int c = 0; c < 16; ++c) acc64[c] += (double)acc[c];
     }
     if (i < nr) {
-      double* __restrict__ out = J.part + (int64_t)split * nr * 16 + i * 16;
+      double* __restrict__ out = J.part + ((int64_t)split * nr + i) * J.M;
       for (int c = 0; c < J.M; ++c) out[c] = acc64[c];
     }
   }

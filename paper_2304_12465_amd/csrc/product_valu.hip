@@ -765,21 +765,21 @@ int product_group(const ProductReq* reqs, int n, hipStream_t s) {
       if (r.prec == KRR_FP64 && r.kind == KRR_GAUSSIAN) {
         F64Job fj;
         KRR_TRY(f64_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &fj, s));
-        pend.push_back(Pending{q, fj.part, nc > 0 ? fj.nsplit : 0, 16, mc, true});
+        pend.push_back(Pending{q, fj.part, nc > 0 ? fj.nsplit : 0, mc, mc, true});
         if (nc > 0) fjobs.push_back(fj);
         continue;
       }
       if (r.prec == KRR_FP32 && r.kind == KRR_GAUSSIAN) {
         F32Job gj;
         KRR_TRY(f32_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &gj, s));
-        pend.push_back(Pending{q, gj.part, nc > 0 ? gj.nsplit : 0, 16, mc, true});
+        pend.push_back(Pending{q, gj.part, nc > 0 ? gj.nsplit : 0, mc, mc, true});
         if (nc > 0) gjobs.push_back(gj);
         continue;
       }
       if (r.prec == KRR_MIXED && r.kind == KRR_GAUSSIAN) {
         MfmaJob mj;
         KRR_TRY(mfma_prepare(r.sigma, *r.rows, *r.cols, r.V, c0, mc, sc, &mj, s));
-        pend.push_back(Pending{q, mj.part, nc > 0 ? mj.nsplit : 0, 16, mc, true});
+        pend.push_back(Pending{q, mj.part, nc > 0 ? mj.nsplit : 0, mc, mc, true});
         if (nc > 0) {
           mjobs.push_back(mj);
           mreq.push_back(q);
