@@ -20,7 +20,8 @@ its launch time measured live with HIP events on its own stream; `issue`
 and `traffic` come from rocprofv3 counters in profiles/.  `cpu_baseline`
 times the FP64 oracle's restricted product on a bounded row sample on all
 host cores.  The other workloads appear beside it as extra keys: the same
-solve with FP32 tiles, the 1,000,000-point Gaussian problem (MIXED, FP32 and
+solve with FP32 tiles, the restricted operator over a stored A(:,S) against
+recomputed tiles at d = 16, 32, 64, the 1,000,000-point Gaussian problem (MIXED, FP32 and
 FP64 product rates and a MIXED solve), the 100,000-point Laplace problem
 (FP32 and FP64 solves) and the served stream (p50/p99 latency of 64
 requests, batched MIXED against one at a time in MIXED and in FP64).
@@ -81,7 +82,7 @@ def parse():
                     help="wall time of the oracle's bounded row sample")
     ap.add_argument("--n", type=int, default=100_000, help="--config c2: number of points")
     ap.add_argument("--config", default="c4",
-                    choices=["c1", "c2", "c3", "c4", "c5", "ranks", "crossover"],
+                    choices=["c1", "c2", "c3", "c4", "c5", "ranks", "crossover", "stored"],
                     help="c4 (default): the headline restricted solve with the other "
                          "workloads as extra keys; c1, c2, c3, c5: one workload each; "
                          "ranks: pivot rules against the approximation rank; crossover: "
@@ -282,8 +283,8 @@ def main():
     out, ctx = headline(a, b, torch, synth, np)
     if not a.no_extra:
         import bench_configs as BC
-        legs = (("c4_fp32", BC.c4_fp32_leg), ("c2", BC.c2_leg), ("c3", BC.c3_leg),
-                ("c5", BC.c5_leg))
+        legs = (("c4_fp32", BC.c4_fp32_leg), ("stored_vs_recomputed", BC.stored_leg),
+                ("c2", BC.c2_leg), ("c3", BC.c3_leg), ("c5", BC.c5_leg))
         for name, fn in legs:
             print(f"bench: {name}", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()

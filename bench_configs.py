@@ -17,6 +17,8 @@ other than the headline one:
   (form A(S,:)A(:,S) + H, factor, solve) on 500,000 points of the restricted
   workload's distribution for k = 250 .. 16,000 centres (Sec. 4.2's
   runtime-against-centres comparison);
+* stored -- the restricted operator over a stored A(:,S) (Sec. 4.1) against
+  recomputed tiles at d = 16, 32, 64 on the restricted workload's recipe;
 * ranks -- pivot rules against the approximation rank on the 100,000-point
   Laplace workload (Sec. 3.1's rules; the iterations-to-1e-3 against rank
   study of Sec. 4.1): build time and PCG iterations to a relative residual
@@ -295,6 +297,71 @@ def c5(a, b, torch, synth):
           result=res)
 
 
+def stored_leg(a, b, torch, synth, ctx=None, dims=(16, 32, 64), n=2_000_000):
+    """The restricted operator with A(:,S) stored (Sec. 4.1) against
+    recomputed tiles, on the restricted workload's recipe at d = 16, 32 and
+    64 (N = 2,000,000, k = 10,000): build time, time per operator application
+    (two N k products) and one solve to 1e-6, FP64 and FP32."""
+    rows = []
+    for d in dims:
+        p = synth.c4(n=n, d=d)
+        N = p.X.shape[0]
+        X = torch.from_numpy(p.X).cuda()
+        Y = torch.from_numpy(p.Y).cuda()
+        V = torch.from_numpy(np.random.default_rng(1).standard_normal((p.centers, 1))).cuda()
+        for prec, pname in ((b.FP64, "fp64"), (b.FP32, "fp32")):
+            for stored in (False, True):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P = b.krill_build(p.kind, p.sigma, prec, X, p.mu, p.centers,
+                                  sketch_rows=p.sketch_rows, zeta=p.zeta, seed=p.algo_seed,
+                                  stored=stored)
+                torch.cuda.synchronize()
+                tb = time.perf_counter() - t0
+                P.operator(V)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(3):
+                    P.operator(V)
+                torch.cuda.synchronize()
+                top = (time.perf_counter() - t1) / 3
+                t2 = time.perf_counter()
+                beta, info = P.solve(Y, p.tol, 400)
+                torch.cuda.synchronize()
+                row = {"d": d, "prec": pname, "stored": stored, "build_s": round(tb, 4),
+                       "operator_ms": round(top * 1e3, 3), "solve_s": round(time.perf_counter() - t2, 4),
+                       "iters": info["iters"], "products": info["products"],
+                       "relres_true": info["relres_true"], "converged": info["converged"]}
+                if stored:
+                    row["stored_gb"] = round(N * ((p.centers + 7) // 8 * 8) *
+                                             (8 if prec == b.FP64 else 4) / 1e9, 1)
+                    row["stream_tb_per_s"] = round(row["stored_gb"] / 1e3 / top, 3)
+                rows.append(row)
+                print(json.dumps(row), file=sys.stderr, flush=True)
+                del P, beta
+                torch.cuda.empty_cache()
+        del X, Y, V
+        torch.cuda.empty_cache()
+    cross = {}
+    for pname in ("fp64", "fp32"):
+        for d in dims:
+            r0 = next(r for r in rows if r["d"] == d and r["prec"] == pname and not r["stored"])
+            r1 = next(r for r in rows if r["d"] == d and r["prec"] == pname and r["stored"])
+            cross[f"{pname}_d{d}_recomputed_over_stored"] = round(r0["operator_ms"] / r1["operator_ms"], 3)
+    return {"table": rows, "operator_time_ratio": cross}
+
+
+def stored(a, b, torch, synth):
+    res = stored_leg(a, b, torch, synth)
+    r = next(r for r in res["table"] if r["d"] == 16 and r["prec"] == "fp64" and r["stored"])
+    _line(value=2 * 2_000_000 * 10_000 / (r["operator_ms"] * 1e-3), unit="kernel entries/s "
+          "(stored FP64 operator, d=16)", steps=3, warmup=1, ms_per_step=r["operator_ms"],
+          dtype="f64", config={"workload": "restricted KRR with KRILL, A(:,S) stored vs "
+                                           "recomputed: N=2e6, k=1e4, d=16/32/64 (recipe of the "
+                                           "restricted workload), FP64 and FP32"},
+          result=res)
+
+
 def ranks(a, b, torch, synth):
     p = synth.c2(n=a.n)
     N, d = p.X.shape
@@ -384,5 +451,5 @@ def run(a):
     import torch
     import synth
     from paper_2304_12465_amd import binding as b
-    {"c1": c1, "c2": c2, "c3": c3, "c5": c5, "ranks": ranks,
-     "crossover": crossover}[a.config](a, b, torch, synth)
+    {"c1": c1, "c2": c2, "c3": c3, "c5": c5, "ranks": ranks, "crossover": crossover,
+     "stored": stored}[a.config](a, b, torch, synth)

@@ -186,6 +186,27 @@ int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec, cons
                     int64_t N, int32_t d, double mu, const int64_t* centers, int32_t k,
                     int32_t sketch_rows, int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
                     size_t ws_bytes, krr_precond* out, hipStream_t stream);
+/* The same KRILL preconditioner with the N x k kernel block A(:,S) stored
+ * (Sec. 4.1 keeps it in memory): as krr_krill_build, and in addition A(:,S)
+ * is evaluated once by the build into the workspace, in FP64 (prec =
+ * KRR_FP64, 8 N k bytes) or FP32 (KRR_FP32, 4 N k bytes; rows padded to a
+ * multiple of 8 entries).  Every later application of the restricted
+ * operator (krr_pcg_solve, the stepped solves, krr_precond_operator) then
+ * streams the stored block instead of recomputing its entries: with one
+ * right-hand side one pass over it forms A(S,:)(A(:,S) v), otherwise two.
+ * The FP64 block also serves the right-hand side and the FP64 residual
+ * checks; with the FP32 block those use recomputed FP64 entries.  The
+ * sketch B = Phi A(:,S) recomputes its entries as in krr_krill_build.
+ * Arguments, limits, ownership and errors as krr_krill_build;
+ * krr_krill_stored_ws gives the workspace size.                            */
+int krr_krill_stored_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+                        int32_t k, int32_t sketch_rows, int32_t zeta, int32_t m_max,
+                        size_t* bytes);
+int krr_krill_build_stored(krr_kernel_kind kind, double sigma, krr_precision prec,
+                           const double* X, int64_t N, int32_t d, double mu,
+                           const int64_t* centers, int32_t k, int32_t sketch_rows, int32_t zeta,
+                           uint64_t seed, int32_t m_max, void* ws, size_t ws_bytes,
+                           krr_precond* out, hipStream_t stream);
 /* Direct solve of the restricted system (Sec. 2.2, eq. restricted_krr_eqn)
  * with the shifted regulariser of Alg. 2, for comparison with KRILL
  * (Sec. 4.2): M = A(S,:) A(:,S) + mu A(S,S) + N eps tr(A(S,S)) I is formed
@@ -207,7 +228,7 @@ int krr_restricted_direct(krr_kernel_kind kind, double sigma, const double* X, i
  * what = 0: sketch rows, int32 N x zeta (column j's rows in draw order);
  * 1: sketch signs, int32 N x zeta (+1 / -1); 2: B, FP64 sketch_rows x k;
  * 3: H, FP64 k x k; 4: the lower factor L = C^T of P, FP64 k x k (strict
- * upper triangle zero).                                                    */
+ * upper triangle zero); 5 (stored builds only): A(:,S) as FP64 N x k.     */
 int krr_krill_export(krr_precond P, int32_t what, void* dst, size_t bytes, hipStream_t stream);
 
 /* Number of pivots / centres (RPCholesky: accepted pivots, may be < r when

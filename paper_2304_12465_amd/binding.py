@@ -52,6 +52,9 @@ _SIGS = {
     "krr_krill_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _szp], _i32),
     "krr_krill_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _vp, _i32, _i32, _i32, _u64,
                          _i32, _vp, _sz, _pp, _vp], _i32),
+    "krr_krill_stored_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _szp], _i32),
+    "krr_krill_build_stored": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _vp, _i32, _i32, _i32,
+                                _u64, _i32, _vp, _sz, _pp, _vp], _i32),
     "krr_krill_export": ([_vp, _i32, _vp, _sz, _vp], _i32),
     "krr_precond_dims": ([_vp, _i32p, _i64p], _i32),
     "krr_precond_pivots": ([_vp, _i64p, _i32, _i32p], _i32),
@@ -338,20 +341,29 @@ def krill_ws(kind, prec, N, d, k, sketch_rows=0, zeta=0, m_max=1):
     return b.value
 
 
+def krill_stored_ws(kind, prec, N, d, k, sketch_rows=0, zeta=0, m_max=1):
+    b = ctypes.c_size_t(0)
+    check(lib().krr_krill_stored_ws(kind, prec, N, d, k, sketch_rows, zeta, m_max,
+                                    ctypes.byref(b)))
+    return b.value
+
+
 def krill_build(kind, sigma, prec, X, mu, k, centers=None, sketch_rows=0, zeta=0, seed=0,
-                m_max=1, ws=None):
-    """KRILL preconditioner for restricted KRR (centres sampled if None)."""
+                m_max=1, ws=None, stored=False):
+    """KRILL preconditioner for restricted KRR (centres sampled if None);
+    stored=True keeps A(:,S) in the workspace (krr_krill_build_stored)."""
     _f64(X)
     N, d = X.shape
     if ws is None:
-        ws = workspace(krill_ws(kind, prec, N, d, k, sketch_rows, zeta, m_max), X.device)
+        q = krill_stored_ws if stored else krill_ws
+        ws = workspace(q(kind, prec, N, d, k, sketch_rows, zeta, m_max), X.device)
     if centers is not None and (centers.dtype != torch.int64 or not centers.is_cuda):
         raise ValueError("centers must be an int64 CUDA tensor")
     h = ctypes.c_void_p(0)
-    check(lib().krr_krill_build(kind, float(sigma), prec, _ptr(X), N, d, float(mu), _ptr(centers),
-                                int(k), int(sketch_rows), int(zeta),
-                                ctypes.c_uint64(seed & (2 ** 64 - 1)), int(m_max), _ptr(ws),
-                                ws.numel(), ctypes.byref(h), _stream(X.device)))
+    fn = lib().krr_krill_build_stored if stored else lib().krr_krill_build
+    check(fn(kind, float(sigma), prec, _ptr(X), N, d, float(mu), _ptr(centers),
+             int(k), int(sketch_rows), int(zeta), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+             int(m_max), _ptr(ws), ws.numel(), ctypes.byref(h), _stream(X.device)))
     P = Precond(h, ws, X, m_max, kind)
     P.centers_arg = centers
     return P

@@ -296,9 +296,10 @@ __global__ void widen_signs(const int* __restrict__ neg, int64_t n, int* __restr
 
 }  // namespace
 
-extern "C" int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
-                            int32_t k, int32_t sketch_rows, int32_t zeta, int32_t m_max,
-                            size_t* bytes) {
+namespace {
+
+int krill_ws_impl(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d, int32_t k,
+                  int32_t sketch_rows, int32_t zeta, int32_t m_max, bool stored, size_t* bytes) {
   KRR_TRY(check_kernel(kind, 1.0, prec));
   if (!bytes) {
     set_error("bytes is NULL");
@@ -306,17 +307,17 @@ extern "C" int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N,
   }
   Precond P;
   KRR_TRY(krill_params(P, kind, prec, N, d, k, sketch_rows, zeta, m_max));
+  P.stored = stored;
   Arena a;
   KRR_TRY(krill_layout(a, P));
   *bytes = a.used;
   return KRR_OK;
 }
 
-extern "C" int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec,
-                               const double* X, int64_t N, int32_t d, double mu,
-                               const int64_t* centers, int32_t k, int32_t sketch_rows,
-                               int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
-                               size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+int krill_build_impl(krr_kernel_kind kind, double sigma, krr_precision prec, const double* X,
+                     int64_t N, int32_t d, double mu, const int64_t* centers, int32_t k,
+                     int32_t sketch_rows, int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
+                     size_t ws_bytes, bool stored, krr_precond* out, hipStream_t stream) {
   KRR_TRY(check_kernel(kind, sigma, prec));
   if (!out || !X) {
     set_error("NULL argument");
@@ -338,6 +339,7 @@ extern "C" int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision
     P.sigma = sigma;
     P.mu = mu;
     P.seed = seed;
+    P.stored = stored;
     Arena meas;
     rc = krill_layout(meas, P);
     if (rc == KRR_OK) rc = finish_carve(P, ws, ws_bytes, meas.used);
@@ -353,6 +355,38 @@ extern "C" int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision
   }
   *out = h;
   return KRR_OK;
+}
+
+}  // namespace
+
+extern "C" int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d,
+                            int32_t k, int32_t sketch_rows, int32_t zeta, int32_t m_max,
+                            size_t* bytes) {
+  return krill_ws_impl(kind, prec, N, d, k, sketch_rows, zeta, m_max, false, bytes);
+}
+
+extern "C" int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec,
+                               const double* X, int64_t N, int32_t d, double mu,
+                               const int64_t* centers, int32_t k, int32_t sketch_rows,
+                               int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
+                               size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+  return krill_build_impl(kind, sigma, prec, X, N, d, mu, centers, k, sketch_rows, zeta, seed,
+                          m_max, ws, ws_bytes, false, out, stream);
+}
+
+extern "C" int krr_krill_stored_ws(krr_kernel_kind kind, krr_precision prec, int64_t N,
+                                   int32_t d, int32_t k, int32_t sketch_rows, int32_t zeta,
+                                   int32_t m_max, size_t* bytes) {
+  return krill_ws_impl(kind, prec, N, d, k, sketch_rows, zeta, m_max, true, bytes);
+}
+
+extern "C" int krr_krill_build_stored(krr_kernel_kind kind, double sigma, krr_precision prec,
+                                      const double* X, int64_t N, int32_t d, double mu,
+                                      const int64_t* centers, int32_t k, int32_t sketch_rows,
+                                      int32_t zeta, uint64_t seed, int32_t m_max, void* ws,
+                                      size_t ws_bytes, krr_precond* out, hipStream_t stream) {
+  return krill_build_impl(kind, sigma, prec, X, N, d, mu, centers, k, sketch_rows, zeta, seed,
+                          m_max, ws, ws_bytes, true, out, stream);
 }
 
 extern "C" int krr_krill_export(krr_precond h, int32_t what, void* dst, size_t bytes,
@@ -371,6 +405,13 @@ extern "C" int krr_krill_export(krr_precond h, int32_t what, void* dst, size_t b
     case 2: need = sizeof(double) * (size_t)P.sketch_rows * P.k; break;
     case 3:
     case 4: need = sizeof(double) * kk; break;
+    case 5:
+      if (!P.stored) {
+        set_error("export 5 needs a stored build (krr_krill_build_stored)");
+        return KRR_EINVAL;
+      }
+      need = sizeof(double) * (size_t)P.N * P.k;
+      break;
     default:
       set_error("unknown export %d", what);
       return KRR_EINVAL;
@@ -390,6 +431,8 @@ extern "C" int krr_krill_export(krr_precond h, int32_t what, void* dst, size_t b
       return hip_check(hipMemcpyAsync(dst, P.kw.B, need, hipMemcpyDeviceToDevice, stream), "export");
     case 3:
       return hip_check(hipMemcpyAsync(dst, P.H, need, hipMemcpyDeviceToDevice, stream), "export");
+    case 5:
+      return stored_export(P, static_cast<double*>(dst), stream);
     default:
       lower_copy<<<(unsigned)ceil_div(kk, 256), 256, 0, stream>>>(P.C, P.k, (double*)dst);
       KRR_LAUNCH_CHECK("lower_copy");

@@ -343,6 +343,13 @@ int krill_layout(Arena& a, Precond& P) {
   w.tmp = a.take<int64_t>((size_t)N * P.zeta);
   w.B = a.take<double>((size_t)P.sketch_rows * k);
   w.ints = a.take<int>(4);
+  if (P.stored) {
+    P.kns_es = P.prec == KRR_FP64 ? 8 : 4;
+    size_t part = 0;
+    const size_t kb = stored_bytes(N, k, P.kns_es, P.m_max, &part);
+    P.kns = a.take<char>(kb);
+    P.kns_part = a.take<double>(part / sizeof(double));
+  }
   const size_t ps = std::max(product_scratch_bytes(P.prec, N, k, P.m_max),
                              product_scratch_bytes(P.prec, k, N, P.m_max));
   const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, k, P.m_max),
@@ -429,6 +436,9 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
   P.shift = (double)N * kEps * (double)k;
   scale_add_diag<<<(unsigned)ceil_div(k * k, 256), 256, 0, s>>>(P.H, k, P.mu, P.shift);
   KRR_LAUNCH_CHECK("scale_add_diag");
+
+  // stored mode: A(:,S) evaluated once, in the tile precision
+  if (P.stored) KRR_TRY(stored_fill(P, s));
 
   // 3. sparse sign embedding and its row lists
   const int ds = P.sketch_rows, z = P.zeta;

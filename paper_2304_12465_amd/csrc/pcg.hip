@@ -284,11 +284,16 @@ int apply_operator(Precond& P, VecBlock V, int32_t m, VecBlock W, bool force64, 
                    s);
   }
   // restricted: t = K_NS V, W = K_SN t + H V
-  const PointSet& xs = force64 ? P.pts64 : P.pts;
-  const PointSet& cs = force64 ? P.cpts64 : P.cpts;
   VecBlock t{P.pcg.tmpN, P.N};
-  KRR_TRY(product(P.kind, P.sigma, pr, xs, cs, V.view(), m, 0.0, V.view(), t.out(), P.scratch, s));
-  KRR_TRY(product(P.kind, P.sigma, pr, cs, xs, t.view(), m, 0.0, t.view(), W.out(), P.scratch, s));
+  if (P.stored && (!force64 || P.kns_es == 8)) {
+    // over the stored A(:,S) (FP64 storage serves the FP64 checks too)
+    KRR_TRY(stored_operator(P, V.p, m, t.p, W.p, s));
+  } else {
+    const PointSet& xs = force64 ? P.pts64 : P.pts;
+    const PointSet& cs = force64 ? P.cpts64 : P.cpts;
+    KRR_TRY(product(P.kind, P.sigma, pr, xs, cs, V.view(), m, 0.0, V.view(), t.out(), P.scratch, s));
+    KRR_TRY(product(P.kind, P.sigma, pr, cs, xs, t.view(), m, 0.0, t.view(), W.out(), P.scratch, s));
+  }
   // W^T (m x k) += V^T (m x k) H  (H symmetric)
   return gemm_f64(false, m, P.k, P.k, 1.0, V.p, P.k, P.H, P.k, 1.0, W.p, P.k, s, &P.scratch);
 }
@@ -323,6 +328,7 @@ int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) 
 int system_rhs(Precond& P, const double* Y, int32_t m, VecBlock B, hipStream_t s) {
   if (P.type == kRPChol) return to_colmajor(Y, P.N, m, B.p, s);
   // b = A(S,:) y, evaluated in FP64 (Alg. 2, last step)
+  if (P.stored && P.kns_es == 8) return stored_rhs(P, Y, m, B.p, s);
   VecView y{Y, m, 1};
   return product(P.kind, P.sigma, KRR_FP64, P.cpts64, P.pts64, y, m, 0.0, y, B.out(), P.scratch,
                  s);

@@ -125,6 +125,12 @@ struct Precond {
   double* Linv = nullptr;         // k x k: L^{-1} (the apply is two dense products)
   std::vector<int64_t> centers_host;
   KrillWork kw;
+  // stored mode (Sec. 4.1 keeps A(:,S) in memory): A(:,S), N x ld row-major,
+  // FP64 (kns_es = 8) or FP32 (4), and the partial column sums of its passes
+  bool stored = false;
+  void* kns = nullptr;
+  int kns_es = 8;
+  double* kns_part = nullptr;
   // PCG state and scratch
   PcgState pcg;
   Arena scratch;
@@ -195,6 +201,18 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
                 hipStream_t s);
 int solve_step(Solve* const* solves, int n, hipStream_t s);
 int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s);
+
+// Stored kernel block of restricted KRR (stored.hip): bytes of A(:,S) (and of
+// its partial sums), its evaluation at build time, the operator
+// w = A(S,:)(A(:,S) v) over it (t: N x m scratch; v, w: k x m, column-major),
+// the FP64 right-hand side B = A(S,:) Y (Y row-major N x m, FP64 storage
+// only) and its export as FP64 N x k.
+size_t stored_bytes(int64_t N, int64_t k, int es, int32_t m_max, size_t* part_bytes);
+int stored_fill(Precond& P, hipStream_t s);
+int stored_operator(const Precond& P, const double* v, int32_t m, double* t, double* w,
+                    hipStream_t s);
+int stored_rhs(const Precond& P, const double* Y, int32_t m, double* B, hipStream_t s);
+int stored_export(const Precond& P, double* dst, hipStream_t s);
 
 // Layout helpers used for both measuring and carving.
 int rpchol_layout(Arena& a, Precond& P);

@@ -98,12 +98,12 @@ def c3(n=1_000_000, seed=1003, m=8):
                    algo_seed=2003)
 
 
-def c4(n=2_000_000, seed=1004, k=10_000):
-    """x ~ N(0, I_16) with dimension j scaled by 1/(1+j); labels
+def c4(n=2_000_000, seed=1004, k=10_000, d=16):
+    """x ~ N(0, I_d) (d = 16) with dimension j scaled by 1/(1+j); labels
     y = sign(sin(sum x)); Gaussian sigma = 4; mu = 1e-5 N; k uniform centres,
-    sketch 2k rows, 8 nonzeros per column."""
+    sketch 2k rows, 8 nonzeros per column.  Other d draw the same recipe in
+    more dimensions (the stored-block comparison)."""
     g = np.random.default_rng(seed)
-    d = 16
     X = g.standard_normal((n, d)) / (1.0 + np.arange(d))[None, :]
     s = np.sin(X.sum(axis=1))
     y = np.where(s >= 0, 1.0, -1.0)

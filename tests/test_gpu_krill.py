@@ -364,3 +364,93 @@ def test_shift_on_duplicated_centres(kind):
         assert np.all(np.abs(Hu - lam * u) <= 4 * np.spacing(lam)), Hu[:4]
     kr = OKR.Krill(X, p.kind, p.sigma, p.mu, S, seed=p.algo_seed)
     np.testing.assert_allclose(Hg, kr.H, rtol=0, atol=1e-13 * np.abs(kr.H).max())
+
+
+def build_stored(p, prec, centers=None, m_max=1):
+    c = None if centers is None else T(centers, np.int64)
+    return B().krill_build(p.kind, p.sigma, prec, T(p.X), p.mu, p.centers, centers=c,
+                           sketch_rows=p.sketch_rows, zeta=p.zeta, seed=p.algo_seed,
+                           m_max=m_max, stored=True)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_block_and_operator(kind, prec):
+    # Stored mode (Sec. 4.1 keeps A(:,S) in memory): the stored block against
+    # the oracle's A(:,S) (FP64: exp within an ulp or two; FP32: FP32 direct
+    # differences, |arg| (d + 2) 2^-24 plus FP32 rounding of the exp), then the
+    # restricted operator over it for m = 1 (one pass), 2 and 6 (two passes)
+    p = small(n=3000, k=150)
+    if kind == 1:
+        p.kind, p.sigma = 1, 2.0
+    P = build_stored(p, prec, m_max=6)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    A = B().krill_export(P, 5, (p.X.shape[0], p.centers), torch.float64).cpu().numpy()
+    if prec == 0:
+        np.testing.assert_allclose(A, kr.AnS, rtol=4e-16, atol=1e-300)
+    else:
+        d = p.X.shape[1]
+        arg = -np.log(np.maximum(kr.AnS, 1e-300))
+        bound = ((arg + 1) * (d + 2) + 4) * 2.0 ** -24 * kr.AnS + 1e-38
+        assert np.all(np.abs(A - kr.AnS) <= bound), np.max(np.abs(A - kr.AnS) / bound)
+    # B, H as the recomputing build
+    Bg = B().krill_export(P, 2, (p.sketch_rows, p.centers), torch.float64).cpu().numpy()
+    tolB = 1e-12 if prec == 0 else 2e-5
+    assert np.all(np.abs(Bg - kr.B) <= tolB * (np.abs(kr.Phi) @ np.abs(kr.AnS)) + 1e-300)
+    otol = 1e-12 if prec == 0 else 4e-5
+    for m in (1, 2, 6):
+        V = np.random.default_rng(30 + m).standard_normal((p.centers, m))
+        got = P.operator(T(V)).cpu().numpy()
+        ref = kr.product(V)
+        scale = np.abs(kr.AnS).T @ (np.abs(kr.AnS) @ np.abs(V)) + np.abs(kr.H) @ np.abs(V)
+        assert np.all(np.abs(got - ref) <= otol * scale), (m, np.max(np.abs(got - ref) / scale))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_solve_matches_recomputed_and_oracle(prec):
+    # the same KRILL preconditioner (same centres and sketch) with the block
+    # stored and recomputed: FP64 iterations within one and fitted values
+    # within 1e-6 of each other and of the oracle's PCG; FP32 storage meets tol
+    # on the FP64 true residual (refinement with recomputed FP64 products)
+    p = small(n=3000, k=150)
+    Ps = build_stored(p, prec)
+    Pr = build(p, prec)
+    bs, is_ = Ps.solve(T(p.Y), p.tol, max_iter=200)
+    br, ir = Pr.solve(T(p.Y), p.tol, max_iter=200)
+    assert is_["converged"] and ir["converged"], (is_, ir)
+    S = np.array(Ps.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    if prec == 0:
+        xo, io = OPCG.pcg(kr.product, kr.precondition, kr.rhs(p.Y), p.tol, 200)
+        fit_o = kr.AnS @ xo
+        for b_ in (bs, br):
+            fit = kr.AnS @ b_.cpu().numpy()
+            assert np.linalg.norm(fit - fit_o) <= 1e-6 * np.linalg.norm(fit_o)
+        assert abs(is_["iters"] - ir["iters"]) <= 1
+    else:
+        assert is_["relres_true"] <= p.tol
+
+
+def test_stored_two_pass_for_long_rows():
+    # ld > 16,384 centres: the row does not fit the one-pass workgroup, so
+    # one right-hand side takes the two passes (rows, then column sums);
+    # against the recomputing FP64 operator of the same build
+    n = k = 16_400
+    p = synth.c4(n=n, k=k)
+    p.sketch_rows = 2 * k
+    Ps = build_stored(p, 0, centers=np.arange(n))
+    Pr = build(p, 0, centers=np.arange(n))
+    V = T(np.random.default_rng(9).standard_normal((k, 1)))
+    gs = Ps.operator(V).cpu().numpy()
+    gr = Pr.operator(V).cpu().numpy()
+    assert np.max(np.abs(gs - gr)) <= 1e-12 * np.max(np.abs(gr)), np.max(np.abs(gs - gr))
+
+
+def test_stored_export_needs_stored_build():
+    p = small(n=500, k=50)
+    P = build(p, 0)
+    with pytest.raises(B().KrrError):
+        B().krill_export(P, 5, (500, 50), torch.float64)
