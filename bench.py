@@ -94,6 +94,11 @@ def parse():
                     help="served stream: admission order (arrival, or smallest estimated work)")
     ap.add_argument("--build-workers", type=int, default=1,
                     help="served stream: preconditioner builds on this many worker threads")
+    ap.add_argument("--work-cap", type=float, default=1e11,
+                    help="served stream: admit while the admitted requests' estimated "
+                         "per-step work (N^2 (d + m) each) stays within this cap; 0: no cap")
+    ap.add_argument("--sweep", action="store_true",
+                    help="--config c5: serve the trace with several work caps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     ap.add_argument("--fp32", action="store_true",
@@ -254,6 +259,8 @@ def product_only(a, b, torch, synth, np):
 
 def main():
     a = parse()
+    if a.work_cap is not None and a.work_cap <= 0:
+        a.work_cap = None
     if a.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
               "(sharding over several GPUs is designed, not implemented)", file=sys.stderr)

@@ -249,10 +249,11 @@ def c3(a, b, torch, synth):
           result=res)
 
 
-def c5_leg(a, b, torch, synth, ctx=None, requests=None, baselines=True):
+def c5_leg(a, b, torch, synth, ctx=None, requests=None, baselines=True, caps=None):
     """The served stream: batched MIXED (continuous batching, builds on a
-    worker thread), then the same arrival trace one request at a time in
-    MIXED and in FP64."""
+    worker thread, admission capped by estimated per-step work), then the
+    same arrival trace one request at a time in MIXED and in FP64.  caps: a
+    list of work caps to serve the trace with in turn (None = no cap)."""
     from paper_2304_12465_amd.serve import Server, GpuBackend, serve_one_at_a_time, summarize
     count = requests or a.requests
     stream = synth.c5_stream(count=count)
@@ -271,12 +272,21 @@ def c5_leg(a, b, torch, synth, ctx=None, requests=None, baselines=True):
                   file=sys.stderr, flush=True)
         return f
     be = GpuBackend(b.MIXED, tol=1e-6, max_iter=500)
-    srv = Server(be, hbm_budget=160 << 30, max_active=64, on_finish=progress("batched"),
-                 build_workers=a.build_workers, order=a.order)
-    t0 = time.perf_counter()
-    res = srv.run(stream, make)
-    out = {"requests": count, "batched_mixed": summarize(res),
-           "batched_wall_s": time.perf_counter() - t0, "admission_order": a.order}
+    out = {"requests": count, "admission_order": a.order}
+    for cap in (caps if caps is not None else [a.work_cap]):
+        torch.cuda.empty_cache()
+        srv = Server(be, hbm_budget=160 << 30, max_active=64, on_finish=progress(f"cap {cap}"),
+                     build_workers=a.build_workers, order=a.order, work_cap=cap)
+        t0 = time.perf_counter()
+        res = srv.run(stream, make)
+        s_ = summarize(res)
+        s_["work_cap"] = cap
+        s_["wall_s"] = time.perf_counter() - t0
+        if "batched_mixed" not in out:
+            out["batched_mixed"] = s_
+            out["batched_wall_s"] = s_["wall_s"]
+        else:
+            out.setdefault("other_caps", []).append(s_)
     if baselines:
         for tag, prec in (("one_at_a_time_mixed", b.MIXED), ("one_at_a_time_fp64", b.FP64)):
             torch.cuda.empty_cache()
@@ -287,7 +297,8 @@ def c5_leg(a, b, torch, synth, ctx=None, requests=None, baselines=True):
 
 
 def c5(a, b, torch, synth):
-    res = c5_leg(a, b, torch, synth, baselines=not a.no_baseline)
+    caps = [a.work_cap, None, 3e10, 3e11, 1e12] if a.sweep else None
+    res = c5_leg(a, b, torch, synth, baselines=not a.no_baseline, caps=caps)
     s_mix = res["batched_mixed"]
     _line(value=s_mix["solves_per_s"], unit="solves/s", steps=1, warmup=0,
           ms_per_step=res["batched_wall_s"] * 1e3, dtype="bf16x3/f32 (Gaussian), f32 (Laplace)",

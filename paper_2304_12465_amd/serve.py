@@ -117,14 +117,22 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, hbm_budget, max_active=64, clock=time.perf_counter,
-                 sleep=time.sleep, on_finish=None, order="fifo", build_workers=0):
+                 sleep=time.sleep, on_finish=None, order="fifo", build_workers=0,
+                 work_cap=None):
         """order: "fifo" admits in arrival order; "sjf" admits the waiting
         request with the smallest estimated work (backend.cost) first.
         build_workers: 0 builds in the loop; n > 0 builds on n worker
-        threads while the admitted solves keep stepping."""
+        threads while the admitted solves keep stepping.
+        work_cap: admit a request only while the estimated per-step work of
+        the admitted ones (backend.cost summed) stays within the cap; one
+        request is always admitted.  Requests that fill the GPU alone then
+        run (nearly) one at a time, with the next build overlapping them,
+        while small ones share steps -- instead of every admitted request
+        slowing down every other (processor sharing)."""
         self.be = backend
         self.budget = hbm_budget
         self.max_active = max_active
+        self.work_cap = work_cap
         self.order = order
         self.clock = clock
         self.sleep = sleep
@@ -147,8 +155,10 @@ class Server:
         problems = {}
         waiting = deque()
         building = []  # (req, future, bytes): builds on worker threads
-        active = []  # (req, handle, bytes)
+        ready = deque()  # (req, handle, bytes): built, waiting for the work cap
+        active = []  # (req, handle, bytes): stepping
         used = 0
+        work = {}  # rid -> estimated per-step work (backend.cost) of admitted requests
         t0 = self.clock()
 
         def fail_build(req, need, e):
@@ -157,34 +167,44 @@ class Server:
             r.status, r.error = "failed", str(e)
             r.finished = self.clock() - t0
             used -= need
+            work.pop(req.rid, None)
             problems.pop(req.rid, None)
             if self.on_finish:
                 self.on_finish(r)
 
-        while pending or waiting or active or building:
+        def active_work():
+            return sum(work[q.rid] for q, _, _ in active)
+
+        while pending or waiting or active or building or ready:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 req = pending.popleft()
                 problems[req.rid] = make_problem(req)
                 waiting.append(req)
-            # finished background builds join the stepped solves
+            # finished background builds are ready to step
             still = []
             for req, fut, need in building:
                 if not fut.done():
                     still.append((req, fut, need))
                     continue
                 try:
-                    active.append((req, fut.result(), need))
+                    ready.append((req, fut.result(), need))
                 except Exception as e:  # a failed build isolates this request only
                     fail_build(req, need, e)
             building = still
             # admission while the footprint fits: arrival order, or smallest
-            # estimated work first
+            # estimated work first.  With a work cap, a request is admitted
+            # (and its build started) when the admitted work leaves room for
+            # it, or as the one build that runs ahead of the stepping ones.
             if self.order == "sjf" and len(waiting) > 1:
                 waiting = deque(sorted(waiting, key=lambda q: self.be.cost(problems[q.rid])))
-            while waiting and len(active) + len(building) < self.max_active:
+            while waiting and len(active) + len(building) + len(ready) < self.max_active:
                 req = waiting[0]
                 prob = problems[req.rid]
+                if self.work_cap is not None and (active or building or ready):
+                    ahead = pool is not None and not building and not ready
+                    if not ahead and sum(work.values()) + self.be.cost(prob) > self.work_cap:
+                        break
                 need = self.be.footprint(prob)
                 if need > self.budget:
                     waiting.popleft()
@@ -198,6 +218,7 @@ class Server:
                 r = results[req.rid]
                 r.admitted = self.clock() - t0
                 used += need
+                work[req.rid] = self.be.cost(prob)
                 if pool is not None:
                     building.append((req, pool.submit(self.be.start, prob), need))
                     continue
@@ -206,6 +227,15 @@ class Server:
                 except Exception as e:  # a failed build isolates this request only
                     fail_build(req, need, e)
                     continue
+                ready.append((req, h, need))
+            # built requests join the stepped solves within the work cap (the
+            # first one always)
+            while ready:
+                req, h, need = ready[0]
+                if (self.work_cap is not None and active and
+                        active_work() + work[req.rid] > self.work_cap):
+                    break
+                ready.popleft()
                 active.append((req, h, need))
             if not active:
                 if building:
@@ -238,6 +268,7 @@ class Server:
                         r.status, r.error = "failed", str(e)
                 r.finished = self.clock() - t0
                 used -= need
+                work.pop(req.rid, None)
                 problems.pop(req.rid, None)
                 if self.on_finish:
                     self.on_finish(r)

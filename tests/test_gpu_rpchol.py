@@ -262,3 +262,27 @@ def test_full_size_mixed_gaussian_solve():
     res = p.Y[rows] - (OK.matvec(p.X[rows], p.X, beta, p.kind, p.sigma) + p.mu * beta[rows])
     est = np.sqrt((res ** 2).sum(axis=0) * N / rows.size) / np.linalg.norm(p.Y, axis=0)
     assert np.all(est <= 20 * p.tol), est
+
+
+def test_fp32_coefficients_cannot_meet_the_fp64_residual_target():
+    # Why the CG vectors stay FP64 under MIXED tiles: on the ill-conditioned
+    # Gaussian recipe (near-duplicates, mu = 1e-6 N) the refined MIXED solution
+    # meets tol on the FP64 residual, but the same coefficients rounded to FP32
+    # (what FP32 iterates would hold) leave an FP64 residual far above tol:
+    # ||(A + mu I)(x - fl32(x))|| ~ ||A|| ||x|| 2^-24 >> tol ||b||.
+    tol = 1e-6
+    p = synth.c3(n=40_000, m=2)
+    P = build(p, 2, r=800, m_max=2)
+    beta, info = P.solve(T(p.Y), tol, 400)
+    assert info["converged"] and info["relres_true"] <= tol
+    b = B()
+    X = T(p.X)
+    res = {}
+    for name, x in (("fp64", beta), ("fp32-rounded", beta.float().double())):
+        W = b.kernel_matvec(p.kind, p.sigma, b.FP64, X, X, x, shift=p.mu)
+        r = torch.linalg.norm(T(p.Y) - W, dim=0) / torch.linalg.norm(T(p.Y), dim=0)
+        res[name] = float(r.max())
+    print(f"FP64 relative residual of the MIXED solution: {res['fp64']:.2e}; "
+          f"of its FP32-rounded coefficients: {res['fp32-rounded']:.2e}")
+    assert res["fp64"] <= tol
+    assert res["fp32-rounded"] > 10 * tol

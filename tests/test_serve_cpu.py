@@ -65,12 +65,12 @@ class FakeBackend:
         self.used -= h["p"]["fp"]
 
 
-def run(problems, arrivals, budget, max_active=64, order="fifo", build_workers=0):
+def run(problems, arrivals, budget, max_active=64, order="fifo", build_workers=0, work_cap=None):
     clk = FakeClock()
     be = FakeBackend(clk)
     reqs = [Req(i, a) for i, a in enumerate(arrivals)]
     srv = Server(be, budget, max_active=max_active, clock=clk, sleep=clk.sleep, order=order,
-                 build_workers=build_workers)
+                 build_workers=build_workers, work_cap=work_cap)
     res = srv.run(reqs, lambda r: dict(problems[r.rid], rid=r.rid))
     return res, be
 
@@ -154,3 +154,70 @@ def test_background_builds_keep_budget_and_isolate_failures():
     assert all(res[i].status == "done" for i in range(9) if i not in (4, 6))
     assert be.used == 0
     assert be.started == sorted(be.started)  # FIFO admission, one worker
+
+
+class SharingBackend(FakeBackend):
+    """A step of the GPU divides its time among the active requests: each
+    request's remaining work falls by 10 ms / (number active) per 10 ms tick
+    (processor sharing, the regime of requests that each fill the GPU)."""
+
+    def step(self, handles):
+        self.clock.t += 0.01
+        out = []
+        for h in handles:
+            h["left"] -= 1.0 / len(handles)
+            out.append(1 if h["left"] <= 1e-9 else 0)
+        return out
+
+
+def test_work_cap_keeps_large_requests_from_sharing():
+    # ten requests of equal work arrive at once: with no cap they share the
+    # GPU and all finish near the end; with a cap of one request's work they
+    # run one after another and the mean latency nearly halves, with the
+    # same makespan
+    probs = [dict(fp=1, steps=10) for _ in range(10)]
+
+    def go(cap):
+        clk = FakeClock()
+        be = SharingBackend(clk)
+        srv = Server(be, 1000, max_active=64, clock=clk, sleep=clk.sleep, work_cap=cap)
+        res = srv.run([Req(i, 0.0) for i in range(10)], lambda r: dict(probs[r.rid], rid=r.rid))
+        return res, be
+    shared, _ = go(None)
+    capped, be = go(10)
+    mean = lambda res: sum(r.latency for r in res.values()) / len(res)
+    span = lambda res: max(r.finished for r in res.values())
+    assert all(r.status == "done" for r in capped.values())
+    assert mean(capped) < 0.6 * mean(shared)
+    assert abs(span(capped) - span(shared)) < 0.05
+    assert be.started == sorted(be.started)
+
+
+def test_work_cap_batches_small_requests_and_always_admits_one():
+    # small requests share steps up to the cap; a request above the cap on
+    # its own is still admitted when nothing else runs
+    probs = [dict(fp=1, steps=2) for _ in range(6)] + [dict(fp=1, steps=50)]
+    res, be = run(probs, [0.0] * 7, budget=1000, work_cap=6)
+    assert all(r.status == "done" for r in res.values())
+    assert res[6].admitted >= max(res[i].admitted for i in range(6))
+    firsts = sorted(res[i].admitted for i in range(6))
+    assert firsts[2] == firsts[0]  # three small ones admitted together (3 x 2 <= 6)
+
+
+def test_work_cap_builds_the_next_request_ahead_but_steps_within_the_cap():
+    # with a build worker, the next request is built while the current one
+    # steps (its build is started before the current one finishes), but it
+    # joins the stepped solves only when the cap leaves room
+    probs = [dict(fp=1, steps=10) for _ in range(5)]
+    clk = FakeClock()
+    be = SharingBackend(clk)
+    srv = Server(be, 1000, max_active=64, clock=clk, sleep=clk.sleep, work_cap=10,
+                 build_workers=1)
+    res = srv.run([Req(i, 0.0) for i in range(5)], lambda r: dict(probs[r.rid], rid=r.rid))
+    assert all(r.status == "done" for r in res.values())
+    fin = sorted((r.finished, rid) for rid, r in res.items())
+    assert [rid for _, rid in fin] == list(range(5))     # one after another
+    for i in range(1, 5):
+        assert res[i].admitted < res[i - 1].finished     # built ahead
+    gaps = [fin[i][0] - fin[i - 1][0] for i in range(1, 5)]
+    assert max(gaps) < 0.12                              # ~10 steps of 10 ms each
