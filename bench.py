@@ -94,7 +94,7 @@ def parse():
                     help="served stream: admission order (arrival, or smallest estimated work)")
     ap.add_argument("--build-workers", type=int, default=1,
                     help="served stream: preconditioner builds on this many worker threads")
-    ap.add_argument("--work-cap", type=float, default=1e11,
+    ap.add_argument("--work-cap", type=float, default=3e11,
                     help="served stream: admit while the admitted requests' estimated "
                          "per-step work (N^2 (d + m) each) stays within this cap; 0: no cap")
     ap.add_argument("--sweep", action="store_true",

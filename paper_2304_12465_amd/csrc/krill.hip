@@ -531,6 +531,17 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
   KRR_LAUNCH_CHECK("set_identity");
   KRR_TRY(tri_inv_lower(k, P.C, k, P.Linv, k, s));
   KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+  // the largest centred norms on the host: the solve's products choose
+  // their tile there (no launch of the tile they do not need)
+  KRR_TRY(learn_norm_max(P.pts64, s));
+  KRR_TRY(learn_norm_max(P.cpts64, s));
+  if (P.prec != KRR_FP64) {
+    KRR_TRY(learn_norm_max(P.pts, s));
+    KRR_TRY(learn_norm_max(P.cpts, s));
+  } else {
+    P.pts = P.pts64;
+    P.cpts = P.cpts64;
+  }
   P.build_seconds = std::chrono::duration<double>(clk::now() - t0).count();
   return KRR_OK;
 }

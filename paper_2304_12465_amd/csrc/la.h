@@ -19,6 +19,13 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, hipStream_t s, Arena* scratch = nullptr, bool lower_only = false);
 
+// C[M x N] = alpha A[M x K] B[K x N] + beta Cin (C and Cin may differ or
+// coincide), for M <= 8 rows: the short-K column-sum kernel gemm_f64 uses
+// for K <= 1024, with the beta term read from Cin.
+int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double beta, const double* Cin, double* C,
+                     int64_t ldc, hipStream_t s);
+
 // In-place lower Cholesky of the n x n SPD matrix A (row-major, lda):
 // A = L L^T, L in the lower triangle (the strict upper triangle is left
 // holding values of no meaning).  `info` (device int) receives 0 or the

@@ -498,8 +498,8 @@ template <int MM>
 __global__ __launch_bounds__(256) void gemm_colsum(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const double* __restrict__ A, int64_t lda,
                                                    const double* __restrict__ B, int64_t ldb,
-                                                   double beta, double* __restrict__ C,
-                                                   int64_t ldc) {
+                                                   double beta, double* C, int64_t ldc,
+                                                   const double* Cin) {
   __shared__ double red[4][MM][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
@@ -522,13 +522,33 @@ __global__ __launch_bounds__(256) void gemm_colsum(int64_t M, int64_t N, int64_t
     for (int c = 0; c < MM; ++c)
       if (c < M) {
         const double v = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
-        const double old = beta != 0.0 ? beta * C[c * ldc + j] : 0.0;
+        const double old = beta != 0.0 ? beta * Cin[c * ldc + j] : 0.0;
         C[c * ldc + j] = alpha * v + old;
       }
   }
 }
 
 }  // namespace
+
+int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double beta, const double* Cin, double* C,
+                     int64_t ldc, hipStream_t s) {
+  if (M < 1 || M > 8 || N < 1) {
+    set_error("gemm_colsum_into: M=%lld N=%lld out of range", (long long)M, (long long)N);
+    return KRR_EINVAL;
+  }
+  const unsigned g = (unsigned)ceil_div(N, 64);
+  if (M == 1)
+    gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin);
+  else if (M <= 2)
+    gemm_colsum<2><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin);
+  else if (M <= 4)
+    gemm_colsum<4><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin);
+  else
+    gemm_colsum<8><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin);
+  KRR_LAUNCH_CHECK("gemm_colsum");
+  return KRR_OK;
+}
 
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K, bool lower_only) {
   const int z = choose_ksplit(M, N, K, lower_only);
@@ -552,13 +572,13 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
     // chip busy
     const unsigned g = (unsigned)ceil_div(N, 64);
     if (M == 1)
-      gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, C);
     else if (M <= 2)
-      gemm_colsum<2><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      gemm_colsum<2><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, C);
     else if (M <= 4)
-      gemm_colsum<4><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      gemm_colsum<4><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, C);
     else
-      gemm_colsum<8><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      gemm_colsum<8><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, C);
     KRR_LAUNCH_CHECK("gemm_colsum");
     return KRR_OK;
   }

@@ -137,6 +137,61 @@ __global__ __launch_bounds__(kThreads) void update_xr(double* __restrict__ x,
   if (threadIdx.x == 0) red_store(out, c, nblk, blk, s);
 }
 
+// One block per column (n <= 16,384 rows): p.w, the step length, x += alpha p,
+// r -= alpha w and r.r in one launch, with the same sums in the same order as
+// dot_part followed by update_xr (so the iterates are bitwise those of the
+// two launches).
+__global__ __launch_bounds__(kThreads) void pw_update_xr(double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ w, int m_max,
+                                                         int64_t n, double tol2,
+                                                         double* __restrict__ scal) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.x;
+  const int64_t off = (int64_t)c * n;
+  const bool act = scal[kActive * m_max + c] != 0.0;
+  const double rz = scal[kRZ * m_max + c];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) s += p[off + i] * w[off + i];
+  s = 0.0 + block_sum(s, sh);
+  const double alpha = act ? rz / s : 0.0;
+  double q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+    x[off + i] += alpha * p[off + i];
+    const double rv = r[off + i] - alpha * w[off + i];
+    r[off + i] = rv;
+    q += rv * rv;
+  }
+  __syncthreads();  // sh is reused
+  q = block_sum(q, sh);
+  if (threadIdx.x == 0) {
+    scal[kPW * m_max + c] = s;
+    scal[kAlpha * m_max + c] = alpha;
+    final_op(kFinRR, c, 0.0 + q, m_max, tol2, 0, scal);
+  }
+}
+
+// One block per column (n <= 16,384 rows): r.z, beta and p = z + beta p in
+// one launch (the sums and updates of dot_part + update_p, same order).
+__global__ __launch_bounds__(kThreads) void rz_update_p(const double* __restrict__ r,
+                                                        const double* __restrict__ z,
+                                                        double* __restrict__ p, int m_max,
+                                                        int64_t n, double* __restrict__ scal) {
+  __shared__ double sh[kThreads];
+  const int c = blockIdx.x;
+  const int64_t off = (int64_t)c * n;
+  const bool act = scal[kActive * m_max + c] != 0.0;
+  const double rz_old = scal[kRZ * m_max + c];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) s += r[off + i] * z[off + i];
+  s = 0.0 + block_sum(s, sh);
+  const double beta = act ? s / rz_old : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads)
+    p[off + i] = act ? z[off + i] + beta * p[off + i] : 0.0;
+  if (threadIdx.x == 0) final_op(kFinRZ, c, s, m_max, 0.0, 0, scal);
+}
+
 // p = active ? z + beta p : 0
 __global__ __launch_bounds__(kThreads) void update_p(double* __restrict__ p,
                                                      const double* __restrict__ z,
@@ -304,7 +359,9 @@ int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) 
     const int64_t N = P.N;
     const int32_t rk = P.rank;
     const double imu = 1.0 / P.mu;
-    if (Z.p != R.p)
+    // the short-K column-sum product reads R itself for its beta term
+    const bool colsum = m <= 8 && rk > 0 && (N >= 65536 || rk <= 1024);
+    if (Z.p != R.p && !colsum)
       KRR_TRY(hip_check(hipMemcpyAsync(Z.p, R.p, sizeof(double) * N * m, hipMemcpyDeviceToDevice, s),
                         "copy r"));
     if (rk == 0) {
@@ -315,6 +372,7 @@ int apply_precond(Precond& P, VecBlock R, int32_t m, VecBlock Z, hipStream_t s) 
     double* TT = P.pcg.tmpR;  // m x rank: T^T = R^T Q
     KRR_TRY(gemm_f64(true, m, rk, N, 1.0, R.p, N, P.QT, N, 0.0, TT, rk, s, &P.scratch));
     // Z^T = R^T / mu - (1/mu) T^T Q^T
+    if (colsum) return gemm_colsum_into(m, N, rk, -imu, TT, rk, P.QT, N, imu, R.p, Z.p, N, s);
     return gemm_f64(false, m, N, rk, -imu, TT, rk, P.QT, N, imu, Z.p, N, s, &P.scratch);
   }
   // KRILL: z = C^{-1} C^{-T} r with P = C^T C, C = L^T, i.e. z = L^{-T} (L^{-1} r),
@@ -474,7 +532,12 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
     const int64_t nn = st.n;
     const int mm = st.m_max;
     int rc = KRR_OK;
-    if (S.phase == kPhaseIterate) {
+    if (S.phase == kPhaseIterate && red_for(nn).nblk == 1) {
+      // short vectors: the dot product and the update in one launch
+      pw_update_xr<<<(unsigned)S.m, kThreads, 0, s>>>(st.x, st.r, st.p, st.w, mm, nn,
+                                                      S.tol_inner * S.tol_inner, st.scal);
+      rc = hip_check(hipGetLastError(), "pw_update_xr");
+    } else if (S.phase == kPhaseIterate) {
       rc = dot_cols(st, st.p, st.w, S.m, kFinPW, 0, 0, s);
       if (rc == KRR_OK) {
         const Red rd = red_for(nn);
@@ -549,11 +612,16 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       }
       VecBlock R{st.r, st.n}, Z{st.z, st.n};
       int rc = apply_precond(P, R, S.m, Z, s);
-      if (rc == KRR_OK) rc = dot_cols(st, st.r, st.z, S.m, kFinRZ, 0, 0, s);
-      if (rc == KRR_OK) {
-        update_p<<<dim3((unsigned)std::min<int64_t>(ceil_div(st.n, 256), 4096), (unsigned)S.m),
-                   kThreads, 0, s>>>(st.p, st.z, st.scal, mm, st.n);
-        rc = hip_check(hipGetLastError(), "update_p");
+      if (rc == KRR_OK && red_for(st.n).nblk == 1) {
+        rz_update_p<<<(unsigned)S.m, kThreads, 0, s>>>(st.r, st.z, st.p, mm, st.n, st.scal);
+        rc = hip_check(hipGetLastError(), "rz_update_p");
+      } else {
+        if (rc == KRR_OK) rc = dot_cols(st, st.r, st.z, S.m, kFinRZ, 0, 0, s);
+        if (rc == KRR_OK) {
+          update_p<<<dim3((unsigned)std::min<int64_t>(ceil_div(st.n, 256), 4096), (unsigned)S.m),
+                     kThreads, 0, s>>>(st.p, st.z, st.scal, mm, st.n);
+          rc = hip_check(hipGetLastError(), "update_p");
+        }
       }
       if (rc < 0) fail(S, rc);
     } else {  // check

@@ -54,7 +54,16 @@ struct PointSet {
   const double* qp = nullptr;     // [lo, S] (device), shared by rows and columns
   double* qpart = nullptr;        // 256 x 2 partial min/max
   int32_t qbits = 0;
+  // Gaussian layouts: the largest centred squared norm (the value behind
+  // xmax64 / xmax32) once it has been read back to the host, else -1; with
+  // both point sets known, products choose between the expansion tile and
+  // direct differences on the host and launch only that kernel
+  double max_host = -1.0;
 };
+
+// Reads a filled Gaussian layout's largest centred squared norm back to
+// ps.max_host (synchronises `s`); a no-op for other layouts.
+int learn_norm_max(PointSet& ps, hipStream_t s);
 
 // Quantisation range of a point set (or of two): qp[0] = lo, qp[1] = S.
 int quant_params(const double* X1, int64_t n1, const double* X2, int64_t n2, int32_t d,
@@ -143,6 +152,7 @@ struct MfmaJob {
   const uint16_t* vh;
   const uint16_t* vl;
   double* part;
+  int route;    // 0: the kernels evaluate the guard; 1: expansion tile; 2: direct differences
   // FP32 centred points (nr x dpad / nc x dpad) and the largest centred
   // squared norms (device), for the expansion guard and its fallback tile
   const float* xf;
@@ -173,6 +183,7 @@ struct GJob {
   T s;              // exponent scale (FP32: in base 2)
   double s_nat;     // 1 / (2 sigma^2)
   int nsplit, M, dpad;
+  int route;        // 0: the kernels evaluate the guard; 1: expansion tile; 2: direct differences
 };
 typedef GJob<double> F64Job;
 typedef GJob<float> F32Job;

@@ -30,6 +30,7 @@ constexpr int kFoldG = 4;    // FP32: chunks per FP64 fold (256 columns)
 
 template <typename T>
 __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
+  if (J.route) return J.route == 2;  // decided on the host from known norms
   return gauss_expansion_too_coarse<T>(J.s_nat, (double)*J.xmax, (double)*J.ymax, J.dpad);
 }
 
@@ -492,7 +493,8 @@ size_t g_scratch_bytes(int64_t nr, int64_t nc) {
 template <typename T>
 int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T* cxc,
               const T* cxn, const T* cxmax, int64_t nr, int64_t nc, int dpad, VecView V, int c0,
-              int mc, Arena& scratch, GJob<T>* out, hipStream_t s) {
+              int mc, double rmax_host, double cmax_host, Arena& scratch, GJob<T>* out,
+              hipStream_t s) {
   GSplit sp = g_split(nr, nc);
   T* v = scratch.take<T>((size_t)std::max<int64_t>(nc, 1) * 16);
   double* part = scratch.take<double>((size_t)sp.nsplit * nr * 16);
@@ -525,6 +527,11 @@ int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T*
   j.nsplit = sp.nsplit;
   j.M = mc;
   j.dpad = dpad;
+  // the device's guard on the host, in the same arithmetic, when both
+  // maxima are known
+  j.route = 0;
+  if (rmax_host >= 0.0 && cmax_host >= 0.0)
+    j.route = s_nat * (rmax_host + cmax_host) * (dpad + 3) > GT<T>::kBound ? 2 : 1;
   return KRR_OK;
 }
 
@@ -548,8 +555,14 @@ int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
         tab.total = total;
         if (total == 0) continue;
         const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+        // kernels no job of the table needs are not launched
+        bool any_mfma = false, any_direct = false;
+        for (int q = 0; q < nj; ++q) {
+          any_mfma = any_mfma || tab.job[q].route != 2;
+          any_direct = any_direct || tab.job[q].route != 1;
+        }
         void* tok = tile_timer_start(s);
-        switch (D) {
+        if (any_mfma) switch (D) {
           case 4: launch_d<T, 4>(mv, grid, tab, s); break;
           case 8: launch_d<T, 8>(mv, grid, tab, s); break;
           case 16: launch_d<T, 16>(mv, grid, tab, s); break;
@@ -561,8 +574,9 @@ int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
         }
         KRR_LAUNCH_CHECK("tile_gauss_mfma");
         // the direct tile serves the jobs the MFMA tile skipped (the choice is
-        // made on the device, so the launch stays asynchronous)
-        switch (D) {
+        // made on the device when the norms are not known on the host, so the
+        // launch stays asynchronous)
+        if (any_direct) switch (D) {
           case 4: tile_gauss_direct<T, 4><<<grid, 256, 0, s>>>(tab); break;
           case 8: tile_gauss_direct<T, 8><<<grid, 256, 0, s>>>(tab); break;
           case 16: tile_gauss_direct<T, 16><<<grid, 256, 0, s>>>(tab); break;
@@ -595,6 +609,24 @@ int fill_f32c(const double* X, const double* centre, const PointSet& ps, hipStre
   return fill_centred<float>(X, centre, ps, ps.xc32, ps.xn32, ps.xmax32, s);
 }
 
+int learn_norm_max(PointSet& ps, hipStream_t s) {
+  if (ps.n == 0) return KRR_OK;
+  if (ps.xmax64) {
+    double v = 0.0;
+    KRR_TRY(hip_check(hipMemcpyAsync(&v, ps.xmax64, sizeof(double), hipMemcpyDeviceToHost, s),
+                      "norm max"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    ps.max_host = v;
+  } else if (ps.xmax32) {
+    float v = 0.0f;
+    KRR_TRY(hip_check(hipMemcpyAsync(&v, ps.xmax32, sizeof(float), hipMemcpyDeviceToHost, s),
+                      "norm max"));
+    KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+    ps.max_host = (double)v;
+  }
+  return KRR_OK;
+}
+
 size_t product_f64mfma_scratch_bytes(int64_t nr, int64_t nc) { return g_scratch_bytes<double>(nr, nc); }
 size_t product_f32mfma_scratch_bytes(int64_t nr, int64_t nc) { return g_scratch_bytes<float>(nr, nc); }
 
@@ -605,7 +637,8 @@ int f64_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVie
     return KRR_EINVAL;
   }
   return g_prepare<double>(sigma, rows.xc64, rows.xn64, rows.xmax64, cols.xc64, cols.xn64,
-                           cols.xmax64, rows.n, cols.n, rows.dpad, V, c0, mc, scratch, out, s);
+                           cols.xmax64, rows.n, cols.n, rows.dpad, V, c0, mc, rows.max_host,
+                           cols.max_host, scratch, out, s);
 }
 int f32_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
                 Arena& scratch, F32Job* out, hipStream_t s) {
@@ -614,7 +647,8 @@ int f32_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVie
     return KRR_EINVAL;
   }
   return g_prepare<float>(sigma, rows.xc32, rows.xn32, rows.xmax32, cols.xc32, cols.xn32,
-                          cols.xmax32, rows.n, cols.n, rows.dpad, V, c0, mc, scratch, out, s);
+                          cols.xmax32, rows.n, cols.n, rows.dpad, V, c0, mc, rows.max_host,
+                          cols.max_host, scratch, out, s);
 }
 int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s) { return g_launch<double>(jobs, s); }
 int f32_launch(const std::vector<F32Job>& jobs, hipStream_t s) { return g_launch<float>(jobs, s); }

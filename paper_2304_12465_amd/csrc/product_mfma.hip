@@ -270,9 +270,14 @@ struct MJobTable {
 //   s (max||x||^2 + max||y||^2) (3 2^-16 + (3 kp + 2) 2^-24),
 // s = 1 / (2 sigma^2).  Above 2^-9 (a relative error of 0.2% per entry)
 // the job goes to direct differences on the FP32 centred points instead.
+__host__ __device__ __forceinline__ bool mixed_bound_exceeded(float s_nat, float xmax, float ymax,
+                                                              int kp) {
+  const float gfac = 3.0f * 0x1p-16f + (float)(3 * kp + 2) * 0x1p-24f;
+  return s_nat * (xmax + ymax) * gfac > 0x1p-9f;
+}
 __device__ __forceinline__ bool mixed_too_coarse(const MfmaJob& J) {
-  const float gfac = 3.0f * 0x1p-16f + (float)(3 * J.kp + 2) * 0x1p-24f;
-  return J.s_nat * (*J.xmax + *J.ymax) * gfac > 0x1p-9f;
+  if (J.route) return J.route == 2;  // decided on the host from known norms
+  return mixed_bound_exceeded(J.s_nat, *J.xmax, *J.ymax, J.kp);
 }
 
 template <int KP>
@@ -555,6 +560,9 @@ int mfma_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVi
   j.nsplit = sp.nsplit;
   j.M = mc;
   j.kp = rows.kpad;
+  j.route = 0;
+  if (rows.max_host >= 0.0 && cols.max_host >= 0.0)
+    j.route = mixed_bound_exceeded(j.s_nat, (float)rows.max_host, (float)cols.max_host, j.kp) ? 2 : 1;
   return KRR_OK;
 }
 
@@ -576,15 +584,20 @@ int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s) {
       tab.total = total;
       if (total == 0) continue;
       const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+      bool any_mfma = false;
+      for (int q = 0; q < nj; ++q) any_mfma = any_mfma || tab.job[q].route != 2;
       void* tok = tile_timer_start(s);
-      if (kp == 32) tile_mfma_gauss<32><<<grid, 256, 0, s>>>(tab);
-      else tile_mfma_gauss<64><<<grid, 256, 0, s>>>(tab);
-      KRR_LAUNCH_CHECK("tile_mfma_gauss");
+      if (any_mfma) {
+        if (kp == 32) tile_mfma_gauss<32><<<grid, 256, 0, s>>>(tab);
+        else tile_mfma_gauss<64><<<grid, 256, 0, s>>>(tab);
+        KRR_LAUNCH_CHECK("tile_mfma_gauss");
+      }
       // the direct tile serves the jobs the guard refused (decided on the
       // device, so the launch stays asynchronous); one launch per padded
       // dimension present
       int dseen[kMaxMJobs], nd = 0;
       for (int q = 0; q < nj; ++q) {
+        if (tab.job[q].route == 1) continue;  // known to stay on the expansion tile
         bool seen = false;
         for (int u = 0; u < nd; ++u) seen = seen || dseen[u] == tab.job[q].dpad;
         if (!seen) dseen[nd++] = tab.job[q].dpad;

@@ -637,6 +637,12 @@ int rpchol_build(Precond& P, const double* X, hipStream_t s) {
     KRR_TRY(trsm_lower_left(rk, N, P.core, rk, P.QT, N, s));
   }
   KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
+  // the largest centred norms on the host: the solve's products choose
+  // their tile there (no launch of the tile they do not need)
+  KRR_TRY(learn_norm_max(P.pts64, s));
+  if (P.prec != KRR_FP64) KRR_TRY(learn_norm_max(P.pts, s));
+  else P.pts = P.pts64;
+  if (P.nsamp > 0) KRR_TRY(learn_norm_max(P.spts64, s));
   P.build_seconds = std::chrono::duration<double>(clk::now() - t0).count();
   return KRR_OK;
 }
