@@ -413,10 +413,7 @@ struct GSplit {
 };
 
 GSplit g_split(int64_t nr, int64_t nc) {
-  // small products (latency-bound: few row groups) split down to one chunk
-  // per item so that more workgroups share them
-  const int64_t minc = nr * nc <= ((int64_t)1 << 24) ? kColsG : 256;
-  const int64_t ns = split_count(nr, nc, 4 * 16 * kRTg, minc);
+  const int64_t ns = split_count(nr, nc, 4 * 16 * kRTg, 256);
   int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
   per = ceil_div(per, kColsG) * kColsG;
   return {(int)ns, per};

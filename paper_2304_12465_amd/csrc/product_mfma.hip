@@ -446,10 +446,7 @@ struct MSplit {
 };
 
 MSplit mfma_split(int64_t nr, int64_t nc) {
-  // small products (latency-bound: few row groups) split down to one chunk
-  // per item so that more workgroups share them
-  const int64_t minc = nr * nc <= ((int64_t)1 << 24) ? kCols : 256;
-  const int64_t ns = split_count(nr, nc, 4 * 16 * kRT, minc);
+  const int64_t ns = split_count(nr, nc, 4 * 16 * kRT, 256);
   int64_t per = ceil_div(std::max<int64_t>(nc, 1), ns);
   per = ceil_div(per, kCols) * kCols;  // whole chunks per split
   return {(int)ns, per};
