@@ -39,33 +39,37 @@ __device__ __forceinline__ double exp64(double x, const double* __restrict__ tab
   return ldexp(__builtin_fma(t, p, t), k >> 6);
 }
 
-// The same exponential for an argument given in units of ln2/64:
-// exp64_u(a * 64/ln2) = exp(a).  Callers fold the factor 64/ln2 into the
-// multiply-add that forms the exponent, so the reduction is n = rint(u),
-// v = u - n (exact, |v| <= 1/2) and e^r - 1 with r = v ln2/64 comes from a
-// degree-5 polynomial in v whose coefficients carry the powers of ln2/64
-// (truncation below 3.6e-17, as above).  Forming u rounds it to about
-// 3 eps |a| more than the exponent itself carries, well inside the error
-// the kernel tiles allow per entry for the |a| where exp(a) is not
-// negligible.  Precondition: |u| < 2^30 or u = NaN (no clamp: callers whose
-// exponents are bounded use this form); larger magnitudes saturate the
-// conversion and are not supported.
+// The exponential for an argument given in units of ln2/1024 (the kernel
+// tiles' form): exp64_u(a * 1024/ln2) = exp(a).  Callers fold the factor
+// 1024/ln2 into the multiply-add that forms the exponent, so the reduction
+// is n = rint(u), v = u - n (exact, |v| <= 1/2); 2^(j/1024) comes from a
+// 1024-entry table in LDS (exp64u_table_fill) and e^r - 1, r = v ln2/1024,
+// from a degree-3 polynomial in v whose coefficients carry the powers of
+// ln2/1024 (truncation below 5.5e-16 on |r| <= ln2/2048, about 2.5 ulp: the
+// tiles allow 1e-13 of sum |K||V|).  Forming u rounds it to about 3 eps |a|
+// more than the exponent itself carries.  Precondition: |u| < 2^30 or u = NaN
+// (no clamp: callers whose exponents are bounded use this form); larger
+// magnitudes saturate the conversion and are not supported.
+constexpr int kExpTableU = 1024;
+constexpr double kExpUScale = 1477.3197218702985;  // 1024 / ln2
+
+// The block's threads fill the table; the caller synchronises.
+__device__ __forceinline__ void exp64u_table_fill(double* tab) {
+  for (int j = threadIdx.x; j < kExpTableU; j += blockDim.x)
+    tab[j] = exp2((double)j / kExpTableU);
+}
+
 __device__ __forceinline__ double exp64_u(double u, const double* __restrict__ tab) {
-  constexpr double kC1 = 0x1.62e42fefa39efp-7;   // (ln2/64)
-  constexpr double kC2 = 0x1.ebfbdff82c58fp-15;  // (ln2/64)^2 / 2
-  constexpr double kC3 = 0x1.c6b08d704a0cp-23;   // (ln2/64)^3 / 6
-  constexpr double kC4 = 0x1.3b2ab6fba4e77p-31;  // (ln2/64)^4 / 24
-  constexpr double kC5 = 0x1.5d87fe78a6731p-40;  // (ln2/64)^5 / 120
+  constexpr double kC1 = 0x1.62e42fefa39efp-11;  // (ln2/1024)
+  constexpr double kC2 = 0x1.ebfbdff82c58fp-23;  // (ln2/1024)^2 / 2
+  constexpr double kC3 = 0x1.c6b08d704a0cp-35;   // (ln2/1024)^3 / 6
   const double n = __builtin_rint(u);
   const double v = u - n;
   const int k = (int)n;
-  const double t = tab[k & (kExpTable - 1)];
-  double p = __builtin_fma(v, kC5, kC4);
-  p = __builtin_fma(v, p, kC3);
-  p = __builtin_fma(v, p, kC2);
+  const double t = tab[k & (kExpTableU - 1)];
+  double p = __builtin_fma(v, kC3, kC2);
   p = __builtin_fma(v, p, kC1);
-  return ldexp(__builtin_fma(t, p * v, t), k >> 6);
+  return ldexp(__builtin_fma(t, p * v, t), k >> 10);
 }
-constexpr double kExpUScale = 92.33248261689366;  // 64 / ln2
 
 }  // namespace krr

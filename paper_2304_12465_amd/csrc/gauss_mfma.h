@@ -28,10 +28,12 @@ struct GT<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int col(int t, int g) { return 4 * t + g; }
-  // exponents in units of ln2/64 (the scale 64/ln2 is folded into s); the
-  // expansion guard bounds them far inside exp64_u's range
+  // exponents in units of ln2/1024 (the scale 1024/ln2 is folded into s);
+  // the expansion guard bounds them far inside exp64_u's range
   static __device__ __forceinline__ double ex(double x, const double* tab) { return exp64_u(x, tab); }
-  static constexpr double kFar = -1.0e6;     // exponent of columns past the range (exp -> 0)
+  static constexpr double kFar = -1.0e7;     // exponent of columns past the range (2^-9766 -> 0)
+  static constexpr int kTable = kExpTableU;  // entries of the exp table in LDS
+  static __device__ __forceinline__ void fill(double* tab) { exp64u_table_fill(tab); }
   static constexpr double kExpScale = kExpUScale;
   // expansion error bound (d + 3) eps s (max||x||^2 + max||y||^2) at most
   // 400 eps = 8.9e-14, else direct differences
@@ -49,6 +51,8 @@ struct GT<float> {
   }
   static constexpr float kFar = -3.0e38f;
   static constexpr double kExpScale = 1.4426950408889634;  // log2(e): v_exp_f32 is base 2
+  static constexpr int kTable = 1;                          // no table
+  static __device__ __forceinline__ void fill(double*) {}
   // 200 eps_32 = 1.2e-5 relative per entry at most (the FP32 tile tolerance
   // is 2e-5 of sum |K||V|), else direct differences
   static constexpr double kBound = 200.0;

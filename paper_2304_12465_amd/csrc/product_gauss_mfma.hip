@@ -5,8 +5,8 @@
 // over centred points (centring keeps the expansion's cancellation at
 // ~eps ||x||^2).  The distance MFMA starts from -||x||^2 / 2, so one FMA
 // gives the exponent; exp runs on the VALU (FP64: the table-driven exp64_u
-// on an exponent scaled by 64/ln2; FP32: v_exp_f32 on an exponent scaled by
-// log2 e).  The reduction against V
+// on an exponent scaled by 1024/ln2; FP32: v_exp_f32 on an exponent scaled
+// by log2 e).  The reduction against V
 // is a second MFMA for more than 4 right-hand sides: the distance output
 // layout (lane l holds, for t = 0..3, column col(t, l/16) of row l % 16) is
 // the A-operand layout of K-step t of the 16x16x4 MFMA with K index l / 16
@@ -278,9 +278,9 @@ constexpr int g_waves_per_eu() {
 template <typename T, int D, int MV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g_waves_per_eu<T, D>())))
 void tile_gauss_mfma(const GTable<T> tab) {
-  __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32 tiles)
+  __shared__ double etab[GT<T>::kTable];  // FP64 exp table (one unused entry for FP32 tiles)
   if constexpr (std::is_same<T, double>::value) {
-    exp64_table_fill(etab);
+    GT<T>::fill(etab);
     __syncthreads();
   }
   for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
@@ -521,7 +521,7 @@ int g_prepare(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T*
   j.per = sp.per;
   j.item0 = 0;
   // exponents in the units of the tile's exp: base 2 for FP32 (v_exp_f32),
-  // ln2/64 for FP64 (exp64_u)
+  // ln2/1024 for FP64 (exp64_u)
   j.s = (T)(GT<T>::kExpScale * s_nat);
   j.s_nat = s_nat;
   j.nsplit = sp.nsplit;

@@ -39,7 +39,7 @@ struct SketchJob {
   const int* row_of;       // sketch row of every entry
   int64_t ds;
   int rows_per_wg;
-  T s;           // exponent scale: 64/ln2 s_nat (FP64, exp64_u) or log2(e) s_nat (FP32, exp2)
+  T s;           // exponent scale: 1024/ln2 s_nat (FP64, exp64_u) or log2(e) s_nat (FP32, exp2)
   double s_nat;  // 1 / (2 sigma^2)
   int dpad;
   double inv_sqrt_zeta;
@@ -57,7 +57,7 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   constexpr int KS = D / 4;
   constexpr int NT = kSkCols / 16;
   constexpr int kY = kSkCols * D / 256;
-  __shared__ double etab[kExpTable];  // FP64 exp table (unused by FP32)
+  __shared__ double etab[GT<T>::kTable];  // FP64 exp table (one unused entry for FP32)
   __shared__ T sY[kSkCols][D + 1];
   __shared__ T sAy[kSkCols];
   __shared__ T sSg[kSkCols];
@@ -65,7 +65,7 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   __shared__ int64_t sJn[kSkCols];  // points of the next chunk's nonzeros
   // the direct-difference sketch serves this problem (uniform decision)
   if (gauss_expansion_too_coarse<T>(J.s_nat, (double)*J.cmax, (double)*J.ymax, J.dpad)) return;
-  if constexpr (std::is_same<T, double>::value) exp64_table_fill(etab);
+  if constexpr (std::is_same<T, double>::value) GT<T>::fill(etab);
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
