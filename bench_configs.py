@@ -177,6 +177,18 @@ def c2(a, b, torch, synth):
           result=res)
 
 
+def _rounds(h):
+    """Refinement rounds of a residual history: a round starts where the
+    worst relative recursive residual jumps up (the restart from the FP64
+    residual).  Per round: iterations and the last recursive residual."""
+    out, start = [], 0
+    for i in range(1, len(h) + 1):
+        if i == len(h) or h[i] > 3.0 * h[i - 1]:
+            out.append({"iters": i - start, "recursive_end": h[i - 1]})
+            start = i
+    return out
+
+
 def c3_leg(a, b, torch, synth, ctx=None, solve=True):
     """The 1,000,000-point Gaussian problem (d = 32, 8 right-hand sides):
     product rates of the MIXED, FP32 and FP64 tiles and a MIXED solve to an
@@ -219,13 +231,14 @@ def c3_leg(a, b, torch, synth, ctx=None, solve=True):
             if k % 25 == 0:
                 print(f"c3: step {k}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
                       flush=True)
-        beta, info = S.end()
+        beta, info = S.end(history=2000)
         torch.cuda.synchronize()
         out["mixed_solve"] = {"time_to_solution_s": time.perf_counter() - t0,
                               "build_s": info["build_seconds"], "iters": info["iters"],
                               "products": info["products"], "relres_true": info["relres_true"],
                               "relres_recursive": info["relres_recursive"],
-                              "rank": P.dims()[0], "converged": info["converged"]}
+                              "rank": P.dims()[0], "converged": info["converged"],
+                              "rounds": _rounds(info["history"])}
         del P, S, ws
     return out
 

@@ -254,8 +254,11 @@ void krr_precond_free(krr_precond P);
  * FP64 tiles: one residual-replacement restart if it exceeds 10 tol.
  * FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG restarted
  * from the FP64 true residual, each round run to tol/10 on its recursive
- * residual) until it meets tol; relres_true reports the
- * final FP64 value.  A column counts as converged when FP64 tiles bring its
+ * residual, or to tol/2 where the previous round's contraction puts the
+ * operator's share of the coming round below tol/10; MIXED full-data rounds
+ * also stop at the operator's floor, seen on an FP64 residual of 1,024
+ * sampled rows) until it meets tol; relres_true reports the final FP64
+ * value.  A column counts as converged when FP64 tiles bring its
  * recursive residual to tol with a true residual within 10 tol, and when
  * FP32 / MIXED tiles bring its FP64 true residual itself to tol.
  * Synchronises `stream` once per iteration.  Returns KRR_NOT_CONVERGED

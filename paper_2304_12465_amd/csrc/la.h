@@ -20,8 +20,9 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
                 int64_t ldc, hipStream_t s, Arena* scratch = nullptr, bool lower_only = false);
 
 // C[M x N] = alpha A[M x K] B[K x N] + beta Cin (C and Cin may differ or
-// coincide), for M <= 8 rows: the short-K column-sum kernel gemm_f64 uses
-// for K <= 1024, with the beta term read from Cin.
+// coincide), for M <= 8 rows: the kernels gemm_f64 uses for such products
+// (the matrix-core one from N = 65536 columns, else the column-sum one),
+// with the beta term read from Cin.
 int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double beta, const double* Cin, double* C,
                      int64_t ldc, hipStream_t s);

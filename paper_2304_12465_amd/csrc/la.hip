@@ -528,6 +528,234 @@ __global__ __launch_bounds__(256) void gemm_colsum(int64_t M, int64_t N, int64_t
   }
 }
 
+// Products of at most 8 rows against a long dimension (the preconditioner
+// applies of large full-data problems: the point count N runs to millions,
+// the rank to thousands), on the FP64 matrix cores.  The A operand's 16 MFMA
+// rows hold the (zero-padded) right-hand sides; each 16-index step of the
+// contraction is four k-steps whose slot g takes the indices 4g + s
+// (s = 0..3), so each lane reads 32 contiguous bytes per operand row.  Both
+// are HBM-bound: the MFMA work (16 rows for at most 8 used) stays below the
+// time of the streamed operand.
+typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));
+constexpr int64_t kLongK = 65536;  // contraction length from which long_nt_partial runs
+constexpr int64_t kLongN = 65536;  // output width from which long_nn runs
+constexpr int kLongTiles = 4;                      // 16-column output tiles per wave
+constexpr int kLongCols = 4 * kLongTiles * 16;     // output columns per workgroup
+
+__device__ __forceinline__ d4u load4(const double* p, bool ok) {
+  if (ok) return *reinterpret_cast<const d4u*>(p);
+  return d4u{0.0, 0.0, 0.0, 0.0};
+}
+
+// part[z][c][j] = sum over k in [z kc, min(K, (z + 1) kc)) of A[c][k] B[j][k]
+// for c < M <= 8, j < N (A row-major M x K, B given as N rows of K).  A wave
+// owns 64 output columns; the workgroup's four waves share the K chunk, so
+// the chunk of A is read from L2 once per workgroup and B once overall.
+__global__ __launch_bounds__(256) void long_nt_partial(int M, int64_t N, int64_t K,
+                                                       const double* __restrict__ A, int64_t lda,
+                                                       const double* __restrict__ B, int64_t ldb,
+                                                       int64_t kc, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kLongTiles);
+  if (j0 >= N) return;
+  const int64_t z = blockIdx.y;
+  const int64_t kb = z * kc, ke = std::min<int64_t>(K, kb + kc);
+  const bool arow = li < M;
+  const double* ap = A + (arow ? (int64_t)li : 0) * lda;
+  const double* bp[kLongTiles];
+  bool bok[kLongTiles];
+#pragma unroll
+  for (int t = 0; t < kLongTiles; ++t) {
+    const int64_t j = j0 + 16 * t + li;
+    bok[t] = j < N;
+    bp[t] = B + (bok[t] ? j : 0) * ldb;
+  }
+  f64x4 acc[kLongTiles];
+#pragma unroll
+  for (int t = 0; t < kLongTiles; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  int64_t k = kb;
+#pragma unroll 2
+  for (; k + 16 <= ke; k += 16) {
+    const int64_t o = k + 4 * g;
+    const d4u a = load4(ap + o, arow);
+    d4u b[kLongTiles];
+#pragma unroll
+    for (int t = 0; t < kLongTiles; ++t) b[t] = load4(bp[t] + o, bok[t]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < kLongTiles; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[t][q], acc[t], 0, 0, 0);
+  }
+  if (k < ke) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = k + 4 * g + q;
+      const bool in = i < ke;
+      const double a = (arow && in) ? ap[i] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kLongTiles; ++t) {
+        const double b = (bok[t] && in) ? bp[t][i] : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // element r of acc[t] is D[4 r + g][li]: right-hand side 4 r + g, column
+  // j0 + 16 t + li
+  double* out = part + z * (int64_t)M * N;
+#pragma unroll
+  for (int t = 0; t < kLongTiles; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 4 * r + g;
+      const int64_t j = j0 + 16 * t + li;
+      if (c < M && j < N) out[(int64_t)c * N + j] = acc[t][r];
+    }
+}
+
+// C[c][j] = alpha * sum_z part[z][c][j] + beta C[c][j]: a workgroup takes 64
+// outputs, wave w adds the chunks of its quarter in increasing order, and
+// the quarters are added in wave order (fixed order: reproducible).
+__global__ __launch_bounds__(256) void long_nt_reduce(int M, int64_t N, int Z,
+                                                      const double* __restrict__ part,
+                                                      double alpha, double beta, double* C,
+                                                      int64_t ldc) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t MN = (int64_t)M * N;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t ii = i < MN ? i : MN - 1;
+  const int zq = (Z + 3) / 4;
+  const int zb = wave * zq, ze = std::min(Z, zb + zq);
+  double v = 0.0;
+#pragma unroll 8
+  for (int z = zb; z < ze; ++z) v += part[(int64_t)z * MN + ii];
+  red[wave][lane] = v;
+  __syncthreads();
+  if (wave == 0 && i < MN) {
+    const int64_t c = i / N, j = i - c * N;
+    const double sum = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    const double old = beta != 0.0 ? beta * C[c * ldc + j] : 0.0;
+    C[c * ldc + j] = alpha * sum + old;
+  }
+}
+
+// C[c][n] = alpha sum_k A[c][k] B[k][n] + beta Cin[c][n] for c < M <= 8 (A
+// row-major M x K, B row-major K x N).  A workgroup owns 64 output columns
+// as four tiles: lane li of tile t stands for column n0 + 4 li + t, so one
+// 32-byte load per lane and row of B feeds all four tiles and the lane's
+// outputs for one right-hand side are four adjacent columns (one 32-byte
+// store).  The four waves take the 16-row steps of K in turn (wave w: steps
+// w, w + 4, ...); wave 0 adds the others' sums in wave order (fixed order).
+__global__ __launch_bounds__(256) void long_nn(int M, int64_t N, int64_t K, double alpha,
+                                               const double* __restrict__ A, int64_t lda,
+                                               const double* __restrict__ B, int64_t ldb,
+                                               double beta, const double* Cin, double* C,
+                                               int64_t ldc) {
+  // waves 1..3: element r < 2 of each tile (right-hand sides 4 r + g < 8)
+  __shared__ double red[3][2][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t n0 = (int64_t)blockIdx.x * 64;
+  const int64_t nc = n0 + 4 * li;
+  const bool full = n0 + 64 <= N;
+  const bool arow = li < M;
+  const double* ap = A + (arow ? (int64_t)li : 0) * lda;
+  f64x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t kfull = full ? K / 16 * 16 : 0;  // steps read with 32-byte loads
+  int64_t k = 16 * (int64_t)wave;
+#pragma unroll 2
+  for (; k < kfull; k += 64) {
+    const d4u a = load4(ap + k + 4 * g, arow);
+    d4u b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = load4(B + (k + 4 * g + q) * ldb + nc, true);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q][t], acc[t], 0, 0, 0);
+  }
+  // the K tail, and every step of a workgroup whose columns run past N
+  for (; k < K; k += 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = k + 4 * g + q;
+      const bool in = row < K;
+      const double a = (arow && in) ? ap[row] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double b = (in && nc + t < N) ? B[row * ldb + nc + t] : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[wave - 1][r][t][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+  // element r of acc[t] is D[4 r + g][li]: right-hand side 4 r + g, column nc + t
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int c = 4 * r + g;
+    if (c >= M) continue;
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      v[t] = alpha * (((acc[t][r] + red[0][r][t][lane]) + red[1][r][t][lane]) + red[2][r][t][lane]);
+    double* out = C + (int64_t)c * ldc + nc;
+    const double* in = Cin + (int64_t)c * ldc + nc;
+    if (full) {
+      d4u w{v[0], v[1], v[2], v[3]};
+      if (beta != 0.0) w += beta * *reinterpret_cast<const d4u*>(in);
+      *reinterpret_cast<d4u*>(out) = w;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (nc + t < N) out[t] = v[t] + (beta != 0.0 ? beta * in[t] : 0.0);
+    }
+  }
+}
+
+// chunks of the long contraction for long_nt_partial: about 1024
+// workgroups, chunks of at least 512 indices, at most 256 of them
+int long_nt_chunks(int64_t N, int64_t K) {
+  const int64_t gx = ceil_div(N, kLongCols);
+  int64_t z = std::max<int64_t>(1, 1024 / gx);
+  z = std::min<int64_t>(z, std::max<int64_t>(1, K / 512));
+  return (int)std::min<int64_t>(z, 256);
+}
+
+int launch_long_nt(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                   double* part, int Z, hipStream_t s) {
+  const int64_t kc = ceil_div(ceil_div(K, Z), 16) * 16;
+  const int z = (int)ceil_div(K, kc);
+  long_nt_partial<<<dim3((unsigned)ceil_div(N, kLongCols), (unsigned)z), 256, 0, s>>>(
+      (int)M, N, K, A, lda, B, ldb, kc, part);
+  KRR_LAUNCH_CHECK("long_nt_partial");
+  long_nt_reduce<<<(unsigned)ceil_div(M * N, 64), 256, 0, s>>>((int)M, N, z, part, alpha, beta, C,
+                                                               ldc);
+  KRR_LAUNCH_CHECK("long_nt_reduce");
+  return KRR_OK;
+}
+
+int launch_long_nn(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, const double* Cin, double* C,
+                   int64_t ldc, hipStream_t s) {
+  long_nn<<<(unsigned)ceil_div(N, 64), 256, 0, s>>>((int)M, N, K, alpha, A, lda, B, ldb, beta,
+                                                   Cin, C, ldc);
+  KRR_LAUNCH_CHECK("long_nn");
+  return KRR_OK;
+}
+
 }  // namespace
 
 int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
@@ -537,6 +765,7 @@ int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double
     set_error("gemm_colsum_into: M=%lld N=%lld out of range", (long long)M, (long long)N);
     return KRR_EINVAL;
   }
+  if (N >= kLongN) return launch_long_nn(M, N, K, alpha, A, lda, B, ldb, beta, Cin, C, ldc, s);
   const unsigned g = (unsigned)ceil_div(N, 64);
   if (M == 1)
     gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, Cin);
@@ -552,7 +781,14 @@ int gemm_colsum_into(int64_t M, int64_t N, int64_t K, double alpha, const double
 
 size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K, bool lower_only) {
   const int z = choose_ksplit(M, N, K, lower_only);
-  return z > 1 ? align_up((size_t)z * M * N * sizeof(double)) : 0;
+  size_t need = z > 1 ? align_up((size_t)z * M * N * sizeof(double)) : 0;
+  // long_nt_chunks(n, K) * n <= min(1024 * kLongCols, 256 n) for every n <= N
+  // (at most 1024 / ceil(n / kLongCols) chunks): a product with fewer
+  // columns than this one still fits
+  if (M <= 8 && K >= kLongK && !lower_only)
+    need = std::max(need, align_up((size_t)std::min<int64_t>(1024 * kLongCols, 256 * N) * M *
+                                   sizeof(double)));
+  return need;
 }
 
 int gemm_f64(bool b_trans, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
@@ -570,6 +806,7 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
     // workgroup, where the tiled GEMM's staging and 64-row tiles cost more
     // than they save); otherwise the tiled GEMM's K split keeps more of the
     // chip busy
+    if (N >= kLongN) return launch_long_nn(M, N, K, alpha, A, lda, B, ldb, beta, C, C, ldc, s);
     const unsigned g = (unsigned)ceil_div(N, 64);
     if (M == 1)
       gemm_colsum<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, C);
@@ -583,6 +820,20 @@ int gemm_f64_ex(bool a_trans, bool b_trans, int64_t M, int64_t N, int64_t K, dou
     return KRR_OK;
   }
   if (!a_trans && b_trans && M <= 8 && !lower_only) {
+    if (K >= kLongK && scratch) {
+      // a long contraction: one workgroup per output column would stream
+      // A's rows once per column (they leave L2 at these lengths), so
+      // chunks of K go to the matrix cores instead
+      const int Z = long_nt_chunks(N, K);
+      const size_t mark = scratch->used;
+      double* part = scratch->take<double>((size_t)Z * M * N);
+      if (scratch->ok()) {
+        const int rc = launch_long_nt(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, Z, s);
+        scratch->used = mark;
+        return rc;
+      }
+      scratch->used = mark;
+    }
     const unsigned g = (unsigned)N;
     if (M == 1)
       gemm_rowdot<1><<<g, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);

@@ -458,8 +458,9 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
   }
   S.phase = (any && max_iter > 0) ? kPhaseIterate : kPhaseCheck;
   // MIXED full-data solves estimate the residual gap each time the worst
-  // relative recursive residual has fallen 4x since the last estimate
-  if (P.type == kRPChol && P.nsamp > 0) S.gap_next = 0.25;
+  // relative recursive residual has halved since the last estimate (one
+  // FP64 product of the sampled rows, ~1% of an iteration's product)
+  if (P.type == kRPChol && P.nsamp > 0) S.gap_next = 0.5;
   return KRR_OK;
 }
 
@@ -593,14 +594,16 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       }
       if (S.gap_read) {
         // The recursive residual r tracks b - A_mixed x; the FP64 residual
-        // differs from it by the sampled gap g (scaled to all N rows).  Once
-        // |r| <= |g| / 4 in every active column, further steps cannot lower
-        // the FP64 residual by more than ~3%: the round ends at this floor.
+        // differs from it by the sampled gap g (scaled to all N rows), which
+        // stays nearly constant once the round has passed it.  Once
+        // |r| <= |g| / 2 in every active column, further steps can lower the
+        // FP64 residual by ~10% (sqrt(1 + 1/4) for r and g uncorrelated):
+        // the round ends at this floor.
         S.gap_read = false;
         const double scale = (double)st.n / (double)P.nsamp;
         bool floor = true;
         for (int c = 0; c < S.m; ++c)
-          if (S.active[c] && 16.0 * h[kRR * mm + c] > scale * h[kGap * mm + c]) floor = false;
+          if (S.active[c] && 4.0 * h[kRR * mm + c] > scale * h[kGap * mm + c]) floor = false;
         if (floor) {
           S.phase = kPhaseCheck;
           continue;
@@ -608,7 +611,7 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       }
       if (S.gap_next > 0.0 && worst <= S.gap_next) {
         S.gap_pending = true;
-        S.gap_next = 0.25 * worst;
+        S.gap_next = 0.5 * worst;
       }
       VecBlock R{st.r, st.n}, Z{st.z, st.n};
       int rc = apply_precond(P, R, S.m, Z, s);
@@ -652,11 +655,20 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
         continue;
       }
       ++S.restarts;
-      // a refinement round aims below tol: the lower-precision operator
-      // leaves part of each round's correction in the true residual
-      if (P.prec != KRR_FP64) S.tol_inner = 0.1 * S.tol;
+      // A refinement round aims below tol: the lower-precision operator
+      // leaves part of each round's correction in the true residual.  That
+      // part scales with the round's starting residual; the last round's
+      // contraction of the true residual (rho, which includes it) bounds the
+      // coming round's share by rho * worst_true.  Where that is at most
+      // tol / 10 the round only has to reach tol / 2 (the true residual then
+      // ends near or below 0.6 tol); otherwise it aims at tol / 10.
+      if (P.prec != KRR_FP64) {
+        const double rho = S.prev_true > 0.0 ? S.worst_true / S.prev_true : 1.0;
+        S.tol_inner = (rho * S.worst_true <= 0.1 * S.tol ? 0.5 : 0.1) * S.tol;
+      }
+      S.prev_true = S.worst_true;
       S.gap_read = S.gap_pending = false;
-      if (P.nsamp > 0) S.gap_next = 0.25 * S.worst_true;
+      if (P.nsamp > 0) S.gap_next = 0.5 * S.worst_true;
       const int64_t len = st.n * S.m;
       int rc = hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
                          "r = true residual");

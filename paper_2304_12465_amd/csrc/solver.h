@@ -188,6 +188,7 @@ struct Solve {
   std::vector<char> active;
   std::vector<double> history;
   double worst_true = 0.0;
+  double prev_true = 1.0;  // worst true residual at the previous check (x = 0: 1)
   std::vector<double> true_rel;  // per column: ||b - M x|| / ||b|| at the last check
   // residual-gap estimates (MIXED full-data solves): the next one is taken
   // once the worst relative recursive residual is at or below gap_next
