@@ -24,6 +24,19 @@ inline int64_t split_count(int64_t nr, int64_t nc, int64_t rows_per_wg, int64_t 
 // grid-stride loop).
 constexpr int64_t kGridCap = 65536;
 
+// XCD-contiguous item order for a grid-stride loop over `total` items:
+// loop index w (w = blockIdx.x, blockIdx.x + gridDim.x, ... below
+// xcd_slots(total); gridDim.x a multiple of 8) runs on XCD w mod 8 and takes
+// item xcd_item(w, total), so XCD x works through the x-th of eight
+// contiguous runs of items (indices at or past `total` are padding, skipped).
+// With the row groups of a column split numbered consecutively, the
+// workgroups of one XCD then read the same columns at about the same time
+// and share them in that XCD's L2.
+__host__ __device__ inline int64_t xcd_slots(int64_t total) { return (total + 7) / 8 * 8; }
+__host__ __device__ inline int64_t xcd_item(int64_t w, int64_t total) {
+  return (w % 8) * ((total + 7) / 8) + w / 8;
+}
+
 // A point set in the compute layout of one precision: n x dpad, zero padded
 // from d to dpad (zero coordinates add nothing to either distance).
 struct PointSet {

@@ -41,23 +41,30 @@ __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
 // set to kFar when the norms are stored, so their kernel values are exactly
 // 0.  No value is tested when it is loaded: the loads stay in flight across
 // the current chunk's MFMAs.
-template <typename T, int D>
+template <typename T, int D, int VS>
 struct StageG {
   static constexpr int kY = kColsG * D / 256;  // point values per thread
+  // V: 64 columns x VS right-hand-side slots (16 for the MFMA reduction,
+  // the m used for the VALU one), at most one value per thread below 256
+  static constexpr int kV = (kColsG * VS + 255) / 256;
   T y[kY];
-  T v[4];      // V: 64 columns x 16 rhs / 256 threads
+  T v[kV];
   T yn;        // threads 0..63: squared norm of their column
   bool valid;  // threads 0..63: the column is in range
 };
 
-template <typename T, int D>
+template <typename T, int D, int VS>
 __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_t j1, int tid,
-                                            StageG<T, D>& st) {
+                                            StageG<T, D, VS>& st) {
+  constexpr int kVals = kColsG * VS;  // V values of a chunk
   if (jb + kColsG <= j1) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D>::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
+    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) st.v[q] = J.v[jb * 16 + tid + q * 256];
+    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
+      const int e = tid + q * 256;
+      if (e < kVals) st.v[q] = J.v[(jb + e / VS) * 16 + e % VS];
+    }
     if (tid < kColsG) {
       st.yn = J.yn[jb + tid];
       st.valid = true;
@@ -65,16 +72,16 @@ __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_
   } else {
     const int64_t last = j1 - 1;
 #pragma unroll
-    for (int q = 0; q < StageG<T, D>::kY; ++q) {
+    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) {
       const int e = tid + q * 256;
       const int64_t col = jb + e / D < last ? jb + e / D : last;
       st.y[q] = J.yc[col * D + e % D];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
       const int e = tid + q * 256;
-      const int64_t col = jb + e / 16 < last ? jb + e / 16 : last;
-      st.v[q] = J.v[col * 16 + e % 16];
+      const int64_t col = jb + e / VS < last ? jb + e / VS : last;
+      if (e < kVals) st.v[q] = J.v[col * 16 + e % VS];
     }
     if (tid < kColsG) {
       const int64_t col = jb + tid < last ? jb + tid : last;
@@ -135,27 +142,26 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   const int64_t j0 = (int64_t)split * J.per;
   int64_t j1 = j0 + J.per;
   if (j1 > nc) j1 = nc;
-  StageG<T, D> st;
-  if (j0 < j1) stage_fetch<T, D>(J, j0, j1, tid, st);
+  constexpr int VS = MV == 0 ? 16 : MV;  // V slots staged per column
+  StageG<T, D, VS> st;
+  if (j0 < j1) stage_fetch<T, D, VS>(J, j0, j1, tid, st);
   int chunk = 0;
   for (int64_t jb = j0; jb < j1; jb += kColsG, ++chunk) {
     __syncthreads();  // the previous chunk's LDS reads are done
 #pragma unroll
-    for (int q = 0; q < StageG<T, D>::kY; ++q) {
+    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) {
       const int e = tid + q * 256;
       sY[e / D][e % D] = st.y[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
       const int e = tid + q * 256;
-      sV[e / 16][e % 16] = st.v[q];
+      if (e < kColsG * VS) sV[e / VS][e % VS] = st.v[q];
     }
     if (tid < kColsG) sAy[tid] = st.valid ? -J.s * st.yn : GT<T>::kFar;
     __syncthreads();
-    if (jb + kColsG < j1) stage_fetch<T, D>(J, jb + kColsG, j1, tid, st);
+    if (jb + kColsG < j1) stage_fetch<T, D, VS>(J, jb + kColsG, j1, tid, st);
     if (row0 >= nr) continue;
-    // distance MFMAs of column tile ct + 1 are issued before the exp work
-    // of tile ct, which does not depend on them
     acc_t dot[2][kRTg];
     auto distance = [&](int ct, acc_t* dd) {
       T ya[KS];  // A operand: Y[ct*16 + li][4 ks + g]
@@ -169,10 +175,17 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
 #pragma unroll
         for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dd[rt]);
     };
-    distance(0, dot[0]);
+    // FP32: the distance MFMAs of column tile ct + 1 are issued before the
+    // exp work of tile ct, which does not depend on them (the FP32 matrix
+    // cores run beside the VALU).  FP64 matrix and vector instructions do
+    // not overlap, so the FP64 tile computes one tile's distances at a time
+    // and spends the registers on occupancy instead.
+    constexpr bool kAhead = std::is_same<T, float>::value;
+    if (kAhead) distance(0, dot[0]);
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
-      if (ct + 1 < NT) distance(ct + 1, dot[(ct + 1) & 1]);
+      if (!kAhead) distance(ct, dot[ct & 1]);
+      else if (ct + 1 < NT) distance(ct + 1, dot[(ct + 1) & 1]);
       T ay[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) ay[t] = sAy[ct * 16 + GT<T>::col(t, g)];
@@ -262,17 +275,22 @@ struct GTable {
   int64_t total;
 };
 
-// Occupancy floors.  FP64 tiles up to 48 padded dimensions are held to 168
-// VGPRs, i.e. 3 waves per SIMD instead of 2, at the price of a register spill
-// (at d = 32, 168-280 bytes per lane and about 25 scratch accesses per
-// 64-column chunk); measured on N = 200,000: d = 32 with 1 / 8 right-hand
-// sides 26% / 9% faster, d = 24 and 48 5-13%; at d = 64 the spill passes 800
-// bytes and costs 20%, so those keep the compiler's choice.  FP32 tiles up to
+// Occupancy floors.  FP64 tiles up to 16 padded dimensions are held to 128
+// VGPRs, 4 waves per SIMD (no spill up to 2 right-hand sides: the distance
+// of one column tile at a time and V staged for the m columns used; the
+// 2,000,000 x 10,000 product 17.2-18.7 -> 16.6-16.8 ms together with the
+// XCD item order; 5 waves spill 28+ registers and lose 1-50%).  Up to 48
+// padded dimensions they are held to 168 VGPRs, 3 waves instead of 2, at the
+// price of a register spill (at d = 32, up to 44 registers, outside the
+// inner loop); measured on N = 200,000: d = 32 with 1 / 8 right-hand sides
+// 26% / 9% faster, d = 24 and 48 5-13%; 4 waves at d = 32 lose 1-11%; at
+// d = 64 the spill passes 800 bytes and costs 20%, so those keep the
+// compiler's choice.  FP32 tiles up to
 // 32 padded dimensions are held to 128 VGPRs (4 waves instead of 3; d = 32
 // spills 52-184 bytes): 2-12% faster over 1-8 right-hand sides.
 template <typename T, int D>
 constexpr int g_waves_per_eu() {
-  return std::is_same<T, double>::value ? (D <= 48 ? 3 : 1) : (D <= 32 ? 4 : 1);
+  return std::is_same<T, double>::value ? (D <= 16 ? 4 : D <= 48 ? 3 : 1) : (D <= 32 ? 4 : 1);
 }
 
 template <typename T, int D, int MV>
@@ -283,13 +301,17 @@ void tile_gauss_mfma(const GTable<T> tab) {
     GT<T>::fill(etab);
     __syncthreads();
   }
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const GJob<T>& J = tab.job[jn];
     if (needs_direct(J)) continue;  // uniform over the workgroup
+    // row groups of one column split are consecutive items
     const int64_t local = item - J.item0;
-    g_item<T, D, MV>(J, local / J.nsplit, (int)(local % J.nsplit), etab);
+    const int64_t nrg = (J.nr + 4 * 16 * kRTg - 1) / (4 * 16 * kRTg);
+    g_item<T, D, MV>(J, local % nrg, (int)(local / nrg), etab);
   }
 }
 
@@ -308,14 +330,17 @@ __global__ __launch_bounds__(256) void tile_gauss_direct(const GTable<T> tab) {
   __syncthreads();
   const int tid = threadIdx.x;
   const int r = tid & 127, h = tid >> 7;
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const GJob<T>& J = tab.job[jn];
     if (!needs_direct(J)) continue;  // uniform over the workgroup
     const int64_t local = item - J.item0;
-    const int64_t rg = local / J.nsplit;
-    const int split = (int)(local % J.nsplit);
+    const int64_t nrg = (J.nr + 4 * 16 * kRTg - 1) / (4 * 16 * kRTg);
+    const int64_t rg = local % nrg;
+    const int split = (int)(local / nrg);
     const int64_t nr = J.nr;
     const int64_t i = rg * (4 * 16 * kRTg) + r;
     const int64_t ic = i < nr ? i : nr - 1;
@@ -554,7 +579,7 @@ int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
         tab.njobs = nj;
         tab.total = total;
         if (total == 0) continue;
-        const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+        const unsigned grid = (unsigned)std::min<int64_t>(xcd_slots(total), kGridCap);
         // kernels no job of the table needs are not launched
         bool any_mfma = false, any_direct = false;
         for (int q = 0; q < nj; ++q) {

@@ -46,12 +46,16 @@ struct SketchJob {
   double* B;     // ds x k
 };
 
-// The FP64 sketch up to 16 padded dimensions is held to 168 VGPRs: 3 waves
-// per SIMD instead of 2, with no spill (the 2,000,000-point, k = 10,000 FP64
-// build 0.280 -> 0.263 s on one box).
+// The FP64 sketch up to 16 padded dimensions is held to 128 VGPRs: 4 waves
+// per SIMD (2 waves: the 2,000,000-point, k = 10,000 FP64 sketch in 0.280 s
+// of build; 3 waves, no spill: 146.9 ms; 4 waves, 15 registers spilled
+// outside the inner loop: 143.6 ms).  Ordering its workgroups in XCD runs
+// (each row range's centre blocks on one XCD) doubled its time: the
+// workgroups of a row range then gather the same points at the same moment
+// through one L2.
 template <typename T, int D>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value && D <= 16 ? 3 : 1)))
+__attribute__((amdgpu_waves_per_eu(std::is_same<T, double>::value && D <= 16 ? 4 : 1)))
 void sketch_gauss_mfma(const SketchJob<T> J) {
   typedef typename GT<T>::acc_t acc_t;
   constexpr int KS = D / 4;
