@@ -283,13 +283,17 @@ __device__ __forceinline__ bool mixed_too_coarse(const MfmaJob& J) {
 template <int KP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KP == 32 ? 3 : 2)))
 void tile_mfma_gauss(const MJobTable tab) {
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const MfmaJob& J = tab.job[jn];
     if (mixed_too_coarse(J)) continue;  // uniform over the workgroup
+    // row groups of one column split are consecutive items
     const int64_t local = item - J.item0;
-    mfma_item<KP>(J, local / J.nsplit, (int)(local % J.nsplit));
+    const int64_t nrg = (J.nr + 4 * 16 * kRT - 1) / (4 * 16 * kRT);
+    mfma_item<KP>(J, local % nrg, (int)(local / nrg));
   }
 }
 
@@ -311,14 +315,17 @@ __device__ __forceinline__ float vsplit_at(const MfmaJob& J, int64_t j, int c) {
 template <int D>
 __global__ __launch_bounds__(256) void tile_mixed_direct(const MJobTable tab) {
   const int tid = threadIdx.x;
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const MfmaJob& J = tab.job[jn];
     if (J.dpad != D || !mixed_too_coarse(J)) continue;  // uniform over the workgroup
     const int64_t local = item - J.item0;
-    const int64_t rg = local / J.nsplit;
-    const int split = (int)(local % J.nsplit);
+    const int64_t nrg = (J.nr + 4 * 16 * kRT - 1) / (4 * 16 * kRT);
+    const int64_t rg = local % nrg;
+    const int split = (int)(local / nrg);
     const int64_t nr = J.nr;
     const int64_t i = rg * (4 * 16 * kRT) + tid;
     const int64_t ic = i < nr ? i : nr - 1;
@@ -583,7 +590,7 @@ int mfma_launch(const std::vector<MfmaJob>& jobs, hipStream_t s) {
       tab.njobs = nj;
       tab.total = total;
       if (total == 0) continue;
-      const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+      const unsigned grid = (unsigned)std::min<int64_t>(xcd_slots(total), kGridCap);
       bool any_mfma = false;
       for (int q = 0; q < nj; ++q) any_mfma = any_mfma || tab.job[q].route != 2;
       void* tok = tile_timer_start(s);

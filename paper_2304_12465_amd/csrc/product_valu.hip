@@ -177,13 +177,17 @@ void tile_valu(const JobTable<T> tab) {
     exp64_table_fill(etab);
     __syncthreads();
   }
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const TileJob<T>& J = tab.job[jn];
+    // row groups of one column split are consecutive items
     const int64_t local = item - J.item0;
-    const int split = (int)(local % J.nsplit);
-    const int64_t rg = local / J.nsplit;
+    const int64_t nrg = (J.nr + kWaves * 64 * R - 1) / (kWaves * 64 * R);
+    const int split = (int)(local / nrg);
+    const int64_t rg = local % nrg;
     tile_item<KIND, T, D, M, R>(J.Xr, J.nr, J.Xc, J.Vc, J.nc, J.scale, split, J.per, rg, J.part,
                                 J.nsplit, etab);
   }
@@ -276,14 +280,17 @@ __device__ __forceinline__ void tile_item_q(const uint32_t* __restrict__ Qr, int
 template <int D, int M, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(lapq_waves<D, M>())))
 void tile_lapq(const JobTable<float> tab) {
-  for (int64_t item = blockIdx.x; item < tab.total; item += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < xcd_slots(tab.total); w += gridDim.x) {
+    const int64_t item = xcd_item(w, tab.total);
+    if (item >= tab.total) continue;
     int jn = 0;
     while (jn + 1 < tab.njobs && item >= tab.job[jn + 1].item0) ++jn;
     const TileJob<float>& J = tab.job[jn];
     const int64_t local = item - J.item0;
+    const int64_t nrg = (J.nr + kWaves * 64 * R - 1) / (kWaves * 64 * R);
     const float sc = (float)((double)J.scale / J.qp[1]);
-    tile_item_q<D, M, R>(J.Qr, J.nr, J.Qc, J.Vc, J.nc, sc, (int)(local % J.nsplit), J.per,
-                         local / J.nsplit, J.part);
+    tile_item_q<D, M, R>(J.Qr, J.nr, J.Qc, J.Vc, J.nc, sc, (int)(local / nrg), J.per,
+                         local % nrg, J.part);
   }
 }
 
@@ -710,7 +717,7 @@ int launch_jobs(void* fn, const std::vector<TileJob<T>>& jobs, int R, hipStream_
     tab.njobs = nj;
     tab.total = total;
     if (total == 0) continue;
-    const unsigned grid = (unsigned)std::min<int64_t>(total, kGridCap);
+    const unsigned grid = (unsigned)std::min<int64_t>(xcd_slots(total), kGridCap);
     void* tok = tile_timer_start(s);
     reinterpret_cast<TileFn<T>>(fn)<<<grid, 256, 0, s>>>(tab);
     KRR_LAUNCH_CHECK("tile_valu");
