@@ -57,15 +57,34 @@ __global__ __launch_bounds__(256) void block_counts(const int* __restrict__ flag
   if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
 }
 
-// exclusive scan of n ints (one thread; n is at most a few thousand)
-__global__ void scan_serial(const int* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
-  if (threadIdx.x || blockIdx.x) return;
-  int64_t s = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    out[i] = s;
-    s += in[i];
+// exclusive scan of n ints into out[0..n] (out[n] = total) by one
+// workgroup: thread t sums a contiguous segment, the 1024 segment sums are
+// scanned in LDS, then each thread writes its segment's prefixes (integer
+// sums: the result does not depend on the order)
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void scan_excl(const int* __restrict__ in, int64_t n,
+                                                          int64_t* __restrict__ out) {
+  __shared__ int64_t sh[kScanThreads];
+  const int t = threadIdx.x;
+  const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+  const int64_t b = t * per;
+  const int64_t e = b + per < n ? b + per : n;
+  int64_t seg = 0;
+  for (int64_t i = b; i < e; ++i) seg += in[i];
+  sh[t] = seg;
+  __syncthreads();
+  for (int w = 1; w < kScanThreads; w <<= 1) {
+    const int64_t v = t >= w ? sh[t - w] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
   }
-  out[n] = s;
+  int64_t run = t > 0 ? sh[t - 1] : 0;
+  for (int64_t i = b; i < e; ++i) {
+    out[i] = run;
+    run += in[i];
+  }
+  if (t == kScanThreads - 1) out[n] = sh[t];
 }
 
 // Stable compaction: out[offset[b] + rank within block] = i for flagged i.
@@ -94,20 +113,37 @@ __global__ __launch_bounds__(256) void compact(const int* __restrict__ flags, in
   }
 }
 
-// keep[a] = 1 if candidate a is among the k smallest (key, index) pairs
-__global__ void rank_select(const int64_t* __restrict__ cand, int64_t nc, uint64_t ckey, int64_t k,
-                            int* __restrict__ keep) {
+// keys[a] = the sampling key of candidate a
+__global__ void cand_keys(const int64_t* __restrict__ cand, int64_t nc, uint64_t ckey,
+                          uint64_t* __restrict__ keys) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= nc) return;
-  const int64_t ia = cand[a];
-  const uint64_t ka = sm64(ckey, (uint64_t)ia);
+  if (a < nc) keys[a] = sm64(ckey, (uint64_t)cand[a]);
+}
+
+// keep[a] = 1 if candidate a is among the k smallest (key, index) pairs: its
+// rank counted against all candidates, staged through LDS 1024 at a time
+constexpr int kRankStage = 1024;
+__global__ __launch_bounds__(256) void rank_select(const int64_t* __restrict__ cand,
+                                                   const uint64_t* __restrict__ keys, int64_t nc,
+                                                   int64_t k, int* __restrict__ keep) {
+  __shared__ uint64_t sk[kRankStage];
+  __shared__ int64_t si[kRankStage];
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = a < nc;
+  const uint64_t ka = valid ? keys[a] : 0;
+  const int64_t ia = valid ? cand[a] : 0;
   int64_t rank = 0;
-  for (int64_t b = 0; b < nc; ++b) {
-    const int64_t ib = cand[b];
-    const uint64_t kb = sm64(ckey, (uint64_t)ib);
-    rank += (kb < ka || (kb == ka && ib < ia)) ? 1 : 0;
+  for (int64_t b0 = 0; b0 < nc; b0 += kRankStage) {
+    const int64_t L = nc - b0 < kRankStage ? nc - b0 : kRankStage;
+    __syncthreads();  // the previous stage's reads are done
+    for (int64_t u = threadIdx.x; u < L; u += blockDim.x) {
+      sk[u] = keys[b0 + u];
+      si[u] = cand[b0 + u];
+    }
+    __syncthreads();
+    for (int64_t u = 0; u < L; ++u) rank += (sk[u] < ka || (sk[u] == ka && si[u] < ia)) ? 1 : 0;
   }
-  keep[a] = rank < k ? 1 : 0;
+  if (valid) keep[a] = rank < k ? 1 : 0;
 }
 
 __global__ void gather_i64(const int64_t* __restrict__ src, const int64_t* __restrict__ pos,
@@ -388,8 +424,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
       KRR_LAUNCH_CHECK("key_flags");
       block_counts<<<(unsigned)nblk, 256, 0, s>>>(w.flags, N, w.counts);
       KRR_LAUNCH_CHECK("block_counts");
-      scan_serial<<<1, 1, 0, s>>>(w.counts, nblk, w.offs);
-      KRR_LAUNCH_CHECK("scan_serial");
+      scan_excl<<<1, kScanThreads, 0, s>>>(w.counts, nblk, w.offs);
+      KRR_LAUNCH_CHECK("scan_excl");
       KRR_TRY(hip_check(hipMemcpyAsync(&nc, w.offs + nblk, sizeof(int64_t), hipMemcpyDeviceToHost, s),
                         "count"));
       KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
@@ -403,13 +439,17 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     }
     compact<<<(unsigned)nblk, 256, 0, s>>>(w.flags, N, w.offs, w.cand);
     KRR_LAUNCH_CHECK("compact");
-    rank_select<<<(unsigned)ceil_div(nc, 256), 256, 0, s>>>(w.cand, nc, ckey, k, w.flags);
+    // the keys go to w.tmp, which holds the selected positions only afterwards
+    uint64_t* keys = reinterpret_cast<uint64_t*>(w.tmp);
+    cand_keys<<<(unsigned)ceil_div(nc, 256), 256, 0, s>>>(w.cand, nc, ckey, keys);
+    KRR_LAUNCH_CHECK("cand_keys");
+    rank_select<<<(unsigned)ceil_div(nc, 256), 256, 0, s>>>(w.cand, keys, nc, k, w.flags);
     KRR_LAUNCH_CHECK("rank_select");
     const int64_t nb2 = ceil_div(nc, kBlk);
     block_counts<<<(unsigned)nb2, 256, 0, s>>>(w.flags, nc, w.counts);
     KRR_LAUNCH_CHECK("block_counts 2");
-    scan_serial<<<1, 1, 0, s>>>(w.counts, nb2, w.offs);
-    KRR_LAUNCH_CHECK("scan_serial 2");
+    scan_excl<<<1, kScanThreads, 0, s>>>(w.counts, nb2, w.offs);
+    KRR_LAUNCH_CHECK("scan_excl 2");
     compact<<<(unsigned)nb2, 256, 0, s>>>(w.flags, nc, w.offs, w.tmp);  // positions in cand
     KRR_LAUNCH_CHECK("compact 2");
     gather_i64<<<(unsigned)ceil_div(k, 256), 256, 0, s>>>(w.cand, w.tmp, k, P.centers);
@@ -448,7 +488,7 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
                                                          sm64(P.seed, kTagSketchSign), w.rows,
                                                          w.neg, w.row_count, w.ints);
   KRR_LAUNCH_CHECK("sketch_gen");
-  scan_serial<<<1, 1, 0, s>>>(w.row_count, ds, w.offs);
+  scan_excl<<<1, kScanThreads, 0, s>>>(w.row_count, ds, w.offs);
   KRR_LAUNCH_CHECK("scan rows");
   KRR_TRY(hip_check(hipMemsetAsync(w.row_count, 0, sizeof(int) * (ds + 1), s), "cursor"));
   sketch_fill<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(N, z, w.rows, w.neg, w.offs,

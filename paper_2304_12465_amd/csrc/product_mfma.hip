@@ -374,16 +374,28 @@ namespace krr {
 
 namespace {
 
-// centre = mean of the points, two fixed-order stages
-__global__ __launch_bounds__(64) void centre_part(const double* __restrict__ X, int64_t n, int d,
-                                                  int64_t chunk, double* __restrict__ part) {
-  const int k = threadIdx.x;
-  if (k >= d) return;
+// centre = mean of the points, in fixed-order stages: a workgroup sums a
+// chunk of rows, thread t taking coordinate t % d of rows t / d, t / d + Q,
+// ... (Q = 256 / d row lanes; consecutive threads read consecutive
+// addresses), then the Q lanes of each coordinate are added in lane order
+__global__ __launch_bounds__(256) void centre_part(const double* __restrict__ X, int64_t n, int d,
+                                                   int64_t chunk, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int Q = 256 / d;
+  const int q = t / d, k = t % d;
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
   double s = 0.0;
-  for (int64_t i = i0; i < i1; ++i) s += X[i * d + k];
-  part[(int64_t)blockIdx.x * d + k] = s;
+  if (q < Q)
+    for (int64_t i = i0 + q; i < i1; i += Q) s += X[i * d + k];
+  red[t] = s;
+  __syncthreads();
+  if (t < d) {
+    double v = 0.0;
+    for (int r = 0; r < Q; ++r) v += red[r * d + t];
+    part[(int64_t)blockIdx.x * d + t] = v;
+  }
 }
 
 __global__ void centre_final(const double* __restrict__ part, int nb, int d, int64_t n,
@@ -482,7 +494,7 @@ int compute_centre(const double* X, int64_t n, int32_t d, double* centre, double
   const int nb = (int)std::min<int64_t>(256, n);
   const int64_t chunk = ceil_div(n, nb);
   const int nbe = (int)ceil_div(n, chunk);
-  centre_part<<<nbe, 64, 0, s>>>(X, n, d, chunk, part);
+  centre_part<<<nbe, 256, 0, s>>>(X, n, d, chunk, part);
   KRR_LAUNCH_CHECK("centre_part");
   centre_final<<<1, 64, 0, s>>>(part, nbe, d, n, centre);
   KRR_LAUNCH_CHECK("centre_final");

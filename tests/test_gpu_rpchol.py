@@ -318,6 +318,7 @@ def test_fp32_coefficients_cannot_meet_the_fp64_residual_target():
     print(f"FP64 relative residual of the MIXED solution: {res['fp64']:.2e}; "
           f"of its FP32-rounded coefficients: {res['fp32-rounded']:.2e}")
     assert res["fp64"] <= tol
-    # several times tol (7e-6 to 1e-5 measured, depending on the rounding
-    # pattern of the refined solution)
-    assert res["fp32-rounded"] > 3 * tol
+    # above tol (2e-6 to 1e-5 measured: the size depends on the rounding
+    # pattern of the refined solution, which moves with the last bits of the
+    # centring and the bf16 split)
+    assert res["fp32-rounded"] > tol
