@@ -61,8 +61,10 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
                      double* __restrict__ slots, int lower) {
   constexpr int FM = TM / 32, FN = TN / 32;  // MFMA blocks per wave
   constexpr int RA = TM / 64, RB = TN / 64;  // 64-row loader passes
-  __shared__ double As[TM][kPad];  // [m][k]
-  __shared__ double Bs[TN][kPad];  // [n][k]
+  // two LDS buffers: the next K step is stored into one while the MFMAs read
+  // the other, so each step needs one barrier
+  __shared__ double As[2][TM][kPad];  // [buffer][m][k]
+  __shared__ double Bs[2][TN][kPad];  // [buffer][n][k]
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   int64_t ty, tx;
@@ -176,17 +178,16 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
         okm |= (ok ? 1u : 0u) << (16 + kUE * r + u);
       }
   };
-  if (kb < ke) fetch(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < RA; ++r)
 #pragma unroll
       for (int u = 0; u < kUE; ++u) {
         const double v = (okm >> (kUE * r + u)) & 1u ? ra[r][u] : 0.0;
         if (!AT)
-          As[64 * r + ar][ak + u] = v;
+          As[buf][64 * r + ar][ak + u] = v;
         else
-          As[64 * r + mn + u][kk] = v;
+          As[buf][64 * r + mn + u][kk] = v;
       }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -194,26 +195,39 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
       for (int u = 0; u < kUE; ++u) {
         const double v = (okm >> (16 + kUE * r + u)) & 1u ? rb[r][u] : 0.0;
         if (BT)
-          Bs[64 * r + ar][ak + u] = v;
+          Bs[buf][64 * r + ar][ak + u] = v;
         else
-          Bs[64 * r + mn + u][kk] = v;
+          Bs[buf][64 * r + mn + u][kk] = v;
       }
+  };
+  int cur = 0;
+  if (kb < ke) {
+    fetch(kb);
+    store(0);
     __syncthreads();
-    fetch(k0 + kKStep);  // clamped addresses: harmless past the end
+    fetch(kb + kKStep);  // clamped addresses: harmless past the end
+  }
+  for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
 #pragma unroll
     for (int ks = 0; ks < kKStep; ks += 4) {
       double a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int i = 0; i < FM; ++i) a[i] = As[cur][wm + i * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][ks + (lane >> 4)];
+      for (int j = 0; j < FN; ++j) b[j] = Bs[cur][wn + j * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (k0 + kKStep < ke) {
+      store(cur ^ 1);
+      fetch(k0 + 2 * kKStep);
+    }
     __syncthreads();
+    cur ^= 1;
   }
   // epilogue, one block row at a time: the old values of C are fetched
   // together (clamped addresses) before any store
