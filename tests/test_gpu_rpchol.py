@@ -105,19 +105,21 @@ def test_apply_matches_svd_form(prec):
     assert rel <= 100 * len(piv_o) * EPS * kapP, (rel, kapP)
 
 
-@functools.lru_cache(maxsize=1)
-def _long_case():
-    # 70,000 points of the c2 recipe: both products of the Woodbury apply
-    # run over N >= 65,536 (the matrix-core kernels for a long contraction
-    # and a wide output), with a ragged last tile (70,000 = 273 x 256 + 112)
-    p = synth.c2(n=70_000)
+@functools.lru_cache(maxsize=2)
+def _long_case(n):
+    # points of the c2 recipe: both products of the Woodbury apply run over
+    # N >= 65,536 (the matrix-core kernels for a long contraction and a wide
+    # output).  70,000 = 273 x 256 + 112: a ragged last output tile; 66,001
+    # is odd, so the last contraction chunk ends inside a 16-point step
+    p = synth.c2(n=n)
     F_o, piv_o = oracle_factor(p, r=300)
     return p, piv_o, ORP.NystromPreconditioner(F_o, p.mu), F_o
 
 
-@pytest.mark.parametrize("m", [1, 3, 8, 11])
-def test_apply_matches_svd_form_long_contraction(m):
-    p, piv_o, Po, F_o = _long_case()
+@pytest.mark.parametrize("n,m", [(70_000, 1), (70_000, 3), (70_000, 8), (70_000, 11),
+                                 (66_001, 3)])
+def test_apply_matches_svd_form_long_contraction(n, m):
+    p, piv_o, Po, F_o = _long_case(n)
     P = build(p, 0, r=300, m_max=m)
     assert P.pivots() == piv_o
     Z = np.random.default_rng(50 + m).standard_normal((p.X.shape[0], m))
