@@ -388,22 +388,26 @@ __device__ __forceinline__ void stage_tri(const double* __restrict__ L, int64_t 
 }
 
 // x <- T^{-1} x by forward substitution, fully unrolled so that x stays in
-// registers; two partial sums per row halve the dependent FMA chain.  The
+// registers; four partial sums per row quarter the dependent FMA chain.  The
 // scheduling barriers keep the compiler from hoisting the whole triangle's
 // LDS reads into registers at once.
 __device__ __forceinline__ void tri_forward(const double (*T)[kNb + 1], const double* tinv,
                                             double (&x)[kNb]) {
 #pragma unroll
   for (int q = 0; q < kNb; ++q) {
-    double s0 = x[q], s1 = 0.0;
+    double s0 = x[q], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int p = 0;
 #pragma unroll
-    for (int p = 0; p + 1 < q; p += 2) {
+    for (; p + 3 < q; p += 4) {
       s0 = __builtin_fma(-T[q][p], x[p], s0);
       s1 = __builtin_fma(-T[q][p + 1], x[p + 1], s1);
-      if ((p & 15) == 14) __builtin_amdgcn_sched_barrier(0);
+      s2 = __builtin_fma(-T[q][p + 2], x[p + 2], s2);
+      s3 = __builtin_fma(-T[q][p + 3], x[p + 3], s3);
+      if ((p & 15) == 12) __builtin_amdgcn_sched_barrier(0);
     }
-    if (q & 1) s0 = __builtin_fma(-T[q][q - 1], x[q - 1], s0);
-    x[q] = (s0 + s1) * tinv[q];
+#pragma unroll
+    for (; p < q; ++p) s0 = __builtin_fma(-T[q][p], x[p], s0);
+    x[q] = ((s0 + s1) + (s2 + s3)) * tinv[q];
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -798,10 +802,12 @@ size_t gemm_scratch_bytes(int64_t M, int64_t N, int64_t K, bool lower_only) {
   size_t need = z > 1 ? align_up((size_t)z * M * N * sizeof(double)) : 0;
   // long_nt_chunks(n, K) * n <= min(1024 * kLongCols, 256 n) for every n <= N
   // (at most 1024 / ceil(n / kLongCols) chunks): a product with fewer
-  // columns than this one still fits
-  if (M <= 8 && K >= kLongK && !lower_only)
-    need = std::max(need, align_up((size_t)std::min<int64_t>(1024 * kLongCols, 256 * N) * M *
-                                   sizeof(double)));
+  // columns than this one still fits.  Sized for min(M, 8) rows, so a
+  // caller sizing for up to M > 8 right-hand sides can run its products
+  // with 8 or fewer on the long-contraction kernels.
+  if (K >= kLongK && !lower_only)
+    need = std::max(need, align_up((size_t)std::min<int64_t>(1024 * kLongCols, 256 * N) *
+                                   std::min<int64_t>(M, 8) * sizeof(double)));
   return need;
 }
 
