@@ -146,7 +146,8 @@ __global__ __launch_bounds__(kThreads) void pw_update_xr(double* __restrict__ x,
                                                          const double* __restrict__ p,
                                                          const double* __restrict__ w, int m_max,
                                                          int64_t n, double tol2,
-                                                         double* __restrict__ scal) {
+                                                         double* __restrict__ scal,
+                                                         int log_row = -1) {
   __shared__ double sh[kThreads];
   const int c = blockIdx.x;
   const int64_t off = (int64_t)c * n;
@@ -169,6 +170,11 @@ __global__ __launch_bounds__(kThreads) void pw_update_xr(double* __restrict__ x,
     scal[kPW * m_max + c] = s;
     scal[kAlpha * m_max + c] = alpha;
     final_op(kFinRR, c, 0.0 + q, m_max, tol2, 0, scal);
+    if (log_row >= 0) {
+      scal[log_row * m_max + c] = scal[kRR * m_max + c];
+      scal[(log_row + 1) * m_max + c] = scal[kActivePrev * m_max + c];
+      scal[(log_row + 2) * m_max + c] = scal[kActive * m_max + c];
+    }
   }
 }
 
@@ -728,12 +734,108 @@ int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
   return conv == S.m ? KRR_OK : KRR_NOT_CONVERGED;
 }
 
+namespace {
+
+// Products of at most this many kernel entries take well under 0.1 ms, so a
+// host round trip per iteration would cost as much as the iteration.
+constexpr double kBurstEntries = 1.6e7;
+
+bool burst_eligible(const Solve& S) {
+  const Precond& P = *S.P;
+  if (S.phase != kPhaseIterate || S.gap_next > 0.0 || S.gap_pending || S.gap_read) return false;
+  if (red_for(P.pcg.n).nblk != 1) return false;  // the one-launch short-vector kernels
+  const double entries = P.type == kRPChol ? (double)P.N * (double)P.N * S.m
+                                           : 2.0 * (double)P.N * (double)P.k * S.m;
+  return entries <= kBurstEntries && S.max_iter - S.it >= 2;
+}
+
+// Up to kBurst iterations of one solve between two host synchronisations.
+// The device already freezes a converged column (alpha = 0, then p = 0), so
+// the iterations of a burst after its last active one change neither x nor
+// r; each iteration logs ||r||^2 and the column activity (pw_update_xr), and
+// the host replays them in order, exactly as solve_step would have decided
+// one iteration at a time (same kernels, same arguments: same results).
+int solve_burst(Solve& S, hipStream_t s) {
+  Precond& P = *S.P;
+  PcgState& st = P.pcg;
+  const int mm = st.m_max;
+  const int64_t nn = st.n;
+  const int k = (int)std::min<int64_t>(kBurst, (int64_t)S.max_iter - S.it);
+  const double tol2 = S.tol_inner * S.tol_inner;
+  VecBlock Pv{st.p, nn}, Wv{st.w, nn}, R{st.r, nn}, Z{st.z, nn};
+  for (int i = 0; i < k; ++i) {
+    if (P.type == kRPChol) {
+      ProductReq r;
+      r.kind = P.kind;
+      r.sigma = P.sigma;
+      r.prec = P.prec;
+      r.rows = &P.pts;
+      r.cols = r.rows;
+      r.V = Pv.view();
+      r.m = S.m;
+      r.shift = P.mu;
+      r.Vs = Pv.view();
+      r.W = Wv.out();
+      r.scratch = &P.scratch;
+      KRR_TRY(product_group(&r, 1, s));
+    } else {
+      KRR_TRY(apply_operator(P, Pv, S.m, Wv, false, s));
+    }
+    pw_update_xr<<<(unsigned)S.m, kThreads, 0, s>>>(st.x, st.r, st.p, st.w, mm, nn, tol2,
+                                                    st.scal, kLog0 + 3 * i);
+    KRR_TRY(hip_check(hipGetLastError(), "pw_update_xr"));
+    if (i + 1 < k) {
+      KRR_TRY(apply_precond(P, R, S.m, Z, s));
+      rz_update_p<<<(unsigned)S.m, kThreads, 0, s>>>(st.r, st.z, st.p, mm, nn, st.scal);
+      KRR_TRY(hip_check(hipGetLastError(), "rz_update_p"));
+    }
+  }
+  KRR_TRY(pull_async(S, s));
+  KRR_TRY(hip_check(hipStreamSynchronize(s), "stream sync"));
+  const double* h = st.host;
+  for (int i = 0; i < k; ++i) {
+    const int row = kLog0 + 3 * i;
+    ++S.it;
+    double worst = 0.0;
+    bool any = false, bad = false;
+    for (int c = 0; c < S.m; ++c) {
+      if (h[(row + 1) * mm + c] != 0.0) S.iters[c] = S.it;
+      const double rr = h[row * mm + c], bb = h[kBB * mm + c];
+      if (!std::isfinite(rr)) bad = true;
+      if (bb > 0) worst = std::max(worst, std::sqrt(rr / bb));
+      S.active[c] = h[(row + 2) * mm + c] != 0.0;
+      any = any || S.active[c];
+    }
+    if (bad) {
+      set_error("NaN/Inf in a residual at iteration %d", S.it);
+      fail(S, KRR_ENAN);
+      return KRR_OK;
+    }
+    S.history.push_back(worst);
+    if (!any || S.it >= S.max_iter) {
+      S.phase = kPhaseCheck;
+      return KRR_OK;
+    }
+  }
+  // still iterating: the next direction, as at the end of a step
+  KRR_TRY(apply_precond(P, R, S.m, Z, s));
+  rz_update_p<<<(unsigned)S.m, kThreads, 0, s>>>(st.r, st.z, st.p, mm, nn, st.scal);
+  return hip_check(hipGetLastError(), "rz_update_p");
+}
+
+}  // namespace
+
 int run_pcg(Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter, double* beta,
             krr_solve_info* info, hipStream_t s) {
   Solve S;
   KRR_TRY(solve_begin(S, P, Y, m, tol, max_iter, s));
   Solve* one = &S;
-  while (S.phase != kPhaseDone) KRR_TRY(solve_step(&one, 1, s));
+  while (S.phase != kPhaseDone) {
+    if (burst_eligible(S))
+      KRR_TRY(solve_burst(S, s));
+    else
+      KRR_TRY(solve_step(&one, 1, s));
+  }
   return solve_end(S, beta, info, s);
 }
 

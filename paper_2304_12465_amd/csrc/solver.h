@@ -139,13 +139,15 @@ struct Precond {
   bool solving = false;  // a stepped solve owns the PCG vectors (krr_solve_begin .. end/free)
 };
 
-// Fixed-order reductions and vector updates (pcg.hip).
-constexpr int kScalars = 12;
+// Fixed-order reductions and vector updates (pcg.hip).  The rows from kLog0
+// hold, for each iteration of a burst (several iterations between host
+// synchronisations, short solves only), its ||r||^2, previous and new
+// activity per column: rows kLog0 + 3 i + {0, 1, 2}.
+constexpr int kBurst = 8;
 enum ScalarSlot {
-  kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp, kActivePrev, kGap
+  kRZ = 0, kPW, kAlpha, kBeta, kRR, kBB, kActive, kRZnew, kTrue, kTmp, kActivePrev, kGap, kLog0
 };
-
-static_assert(kGap < kScalars, "scalar slots");
+constexpr int kScalars = kLog0 + 3 * kBurst;
 
 // Rows sampled for the residual-gap estimate of MIXED solves: at most
 // kGapRows, evenly strided over the N rows.

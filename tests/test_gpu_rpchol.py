@@ -326,3 +326,43 @@ def test_fp32_coefficients_cannot_meet_the_fp64_residual_target():
     # pattern of the refined solution, which moves with the last bits of the
     # centring and the bf16 split)
     assert res["fp32-rounded"] > tol
+
+
+def _stepped(P, Y, tol, max_iter):
+    S = B().Solve(P, Y, tol, max_iter)
+    while B().solve_step([S])[0] == 0:
+        pass
+    return S.end(history=4000)
+
+
+@pytest.mark.parametrize("prec,m", [(0, 1), (0, 3), (1, 3)])
+def test_burst_iterations_match_stepped_solve(prec, m):
+    # krr_pcg_solve runs short solves in bursts of iterations between host
+    # synchronisations (converged columns stay frozen on the device); the
+    # stepped calls decide after every iteration.  Same kernels, same
+    # arguments: bitwise the same solution, iteration counts, residual
+    # history and product count, also with columns converging at different
+    # iterations and across FP32 refinement rounds.
+    p = synth.c1()
+    cols = [p.Y[:, 0], 0.5 * p.Y[:, 0] ** 2, np.cos(p.X[:, 0])][:m]
+    Y = T(np.stack(cols, axis=1))
+    P = build(p, prec, m_max=m)
+    beta1, info1 = P.solve(Y, p.tol if prec == 0 else 1e-6, 600, history=4000)
+    beta2, info2 = _stepped(P, Y, p.tol if prec == 0 else 1e-6, 600)
+    assert torch.equal(beta1, beta2)
+    for key in ("iters", "products", "relres_true", "relres_recursive", "history", "converged"):
+        assert info1[key] == info2[key], key
+
+
+def test_burst_iterations_match_stepped_restricted_solve():
+    p = synth.c4(n=20_000, k=300)
+    b = B()
+    X = T(p.X)
+    P = b.krill_build(p.kind, p.sigma, b.FP64, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
+                      zeta=p.zeta, seed=p.algo_seed)
+    Y = T(p.Y)
+    beta1, info1 = P.solve(Y, p.tol, 400, history=4000)
+    beta2, info2 = _stepped(P, Y, p.tol, 400)
+    assert torch.equal(beta1, beta2)
+    for key in ("iters", "products", "relres_true", "history", "converged"):
+        assert info1[key] == info2[key], key
