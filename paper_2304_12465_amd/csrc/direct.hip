@@ -159,7 +159,9 @@ extern "C" int krr_restricted_direct(krr_kernel_kind kind, double sigma, const d
   const double shift = (double)N * kEps * (double)k;
   add_regulariser<<<(unsigned)ceil_div((int64_t)k * k, 256), 256, 0, s>>>(D.M, D.Linv, k, mu, shift);
   KRR_LAUNCH_CHECK("add_regulariser");
-  KRR_TRY(potrf_lower(k, D.M, k, D.info, s));
+  set_identity<<<(unsigned)ceil_div((int64_t)k * k, 256), 256, 0, s>>>(D.Linv, k);
+  KRR_LAUNCH_CHECK("set_identity");
+  KRR_TRY(potrf_inverse_lower(k, D.M, k, D.info, D.Linv, k, s));
   int info = 0;
   KRR_TRY(hip_check(hipMemcpyAsync(&info, D.info, sizeof(int), hipMemcpyDeviceToHost, s), "info"));
   KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
@@ -167,9 +169,6 @@ extern "C" int krr_restricted_direct(krr_kernel_kind kind, double sigma, const d
     set_error("Cholesky of the restricted matrix failed at column %d", info);
     return KRR_ENOTSPD;
   }
-  set_identity<<<(unsigned)ceil_div((int64_t)k * k, 256), 256, 0, s>>>(D.Linv, k);
-  KRR_LAUNCH_CHECK("set_identity");
-  KRR_TRY(tri_inv_lower(k, D.M, k, D.Linv, k, s));
   // beta = L^{-T} (L^{-1} b)
   KRR_TRY(gemm_f64(false, k, m, k, 1.0, D.Linv, k, D.b, m, 0.0, D.t, m, s, &D.scratch));
   KRR_TRY(gemm_f64_ex(true, false, k, m, k, 1.0, D.Linv, k, D.t, m, 0.0, beta, m, s, &D.scratch));

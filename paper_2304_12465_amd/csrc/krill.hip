@@ -556,7 +556,13 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
                     "P = H"));
   // lower-triangle tiles only: the Cholesky reads nothing above the diagonal
   KRR_TRY(gemm_f64_ex(true, false, k, k, ds, 1.0, w.B, k, w.B, k, 1.0, P.C, k, s, &P.scratch, true));
-  KRR_TRY(potrf_lower(k, P.C, k, w.ints + 1, s));
+  // 7. with L^{-1} by a right-looking blocked solve on the identity, each
+  // block row formed as soon as its block column of L is final (a second
+  // stream): each apply of P^{-1} = L^{-T} L^{-1} is then two dense k x k
+  // products streamed from HBM instead of two sequential triangular solves
+  set_identity<<<(unsigned)ceil_div(k * k, 256), 256, 0, s>>>(P.Linv, k);
+  KRR_LAUNCH_CHECK("set_identity");
+  KRR_TRY(potrf_inverse_lower(k, P.C, k, w.ints + 1, P.Linv, k, s));
   int info = 0;
   KRR_TRY(hip_check(hipMemcpyAsync(&info, w.ints + 1, sizeof(int), hipMemcpyDeviceToHost, s), "info"));
   KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
@@ -564,13 +570,6 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
     set_error("Cholesky of the KRILL matrix failed at column %d", info);
     return KRR_ENOTSPD;
   }
-  // 7. L^{-1} by a right-looking blocked solve on the identity: each apply of
-  // P^{-1} = L^{-T} L^{-1} is then two dense k x k products streamed from
-  // HBM instead of two sequential triangular solves
-  set_identity<<<(unsigned)ceil_div(k * k, 256), 256, 0, s>>>(P.Linv, k);
-  KRR_LAUNCH_CHECK("set_identity");
-  KRR_TRY(tri_inv_lower(k, P.C, k, P.Linv, k, s));
-  KRR_TRY(hip_check(hipStreamSynchronize(s), "sync"));
   // the largest centred norms on the host: the solve's products choose
   // their tile there (no launch of the tile they do not need)
   KRR_TRY(learn_norm_max(P.pts64, s));

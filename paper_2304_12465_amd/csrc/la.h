@@ -38,6 +38,14 @@ int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s);
 int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ldx,
                   hipStream_t s);
 
+// potrf_lower and tri_inv_lower together: A = L L^T in place and X <- L^{-1}
+// (X holds the identity on entry).  Block row k of the inverse is formed on
+// a second stream as soon as block column k of L is final, overlapping the
+// rest of the factorisation; returns once both are complete (it
+// synchronises the second stream; s is joined behind it).
+int potrf_inverse_lower(int64_t n, double* A, int64_t lda, int* info, double* X, int64_t ldx,
+                        hipStream_t s);
+
 // Solves L X = B in place for lower-triangular L (n x n, lda) and B
 // (n x ncols, ldb): B <- L^{-1} B.
 int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,

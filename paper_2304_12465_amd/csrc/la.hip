@@ -4,6 +4,7 @@
 // solves that apply them.  GEMM runs on the FP64 matrix cores.
 #include "la.h"
 #include <algorithm>
+#include <vector>
 
 namespace krr {
 
@@ -1007,22 +1008,84 @@ int potrf_lower(int64_t n, double* A, int64_t lda, int* info, hipStream_t s) {
   return KRR_OK;
 }
 
+namespace {
+
+// Block row k (nb rows) of the right-looking blocked forward substitution
+// on X = I: solve it against L_kk, then update the rows below at once (one
+// GEMM with many tiles).  Block row k of L^{-1} is zero right of column
+// k + nb, so the step touches only columns 0 .. k + nb, and it reads only
+// block column k of L.
+int tri_inv_step(int64_t n, int64_t k, const double* L, int64_t lda, double* X, int64_t ldx,
+                 hipStream_t s) {
+  const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
+  const int64_t ncols = k + nb;
+  KRR_TRY(trsm_block(nb, ncols, L + k * lda + k, lda, X + k * ldx, ldx, s));
+  const int64_t below = n - k - nb;
+  if (below > 0)
+    KRR_TRY(gemm_f64(false, below, ncols, nb, -1.0, L + (k + nb) * lda + k, lda, X + k * ldx,
+                     ldx, 1.0, X + (k + nb) * ldx, ldx, s));
+  return KRR_OK;
+}
+
+// A second stream for potrf_inverse_lower and its events, released on
+// every path (the stream is synchronised first).
+struct SideStream {
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> ev;
+  ~SideStream() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+}  // namespace
+
 int tri_inv_lower(int64_t n, const double* L, int64_t lda, double* X, int64_t ldx,
                   hipStream_t s) {
-  // right-looking blocked forward substitution on X = I: after block row k
-  // is solved, the rows below are updated at once (one GEMM with many
-  // tiles).  Block row k of L^{-1} is zero right of column k + nb, so every
-  // step touches only columns 0 .. k + nb.
-  for (int64_t k = 0; k < n; k += kNbOuter) {
-    const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
-    const int64_t ncols = k + nb;
-    KRR_TRY(trsm_block(nb, ncols, L + k * lda + k, lda, X + k * ldx, ldx, s));
-    const int64_t below = n - k - nb;
-    if (below > 0)
-      KRR_TRY(gemm_f64(false, below, ncols, nb, -1.0, L + (k + nb) * lda + k, lda, X + k * ldx,
-                       ldx, 1.0, X + (k + nb) * ldx, ldx, s));
-  }
+  for (int64_t k = 0; k < n; k += kNbOuter) KRR_TRY(tri_inv_step(n, k, L, lda, X, ldx, s));
   return KRR_OK;
+}
+
+int potrf_inverse_lower(int64_t n, double* A, int64_t lda, int* info, double* X, int64_t ldx,
+                        hipStream_t s) {
+  // The factorisation runs on s; block row k of the inverse needs only block
+  // column k of L, final once the factorisation's panel of step k is
+  // solved, so it runs on a second stream behind an event recorded there,
+  // while s goes on with the trailing update and the later block columns.
+  // Both are chains of small latency-bound launches that leave most of the
+  // chip idle; the two overlap.
+  const int64_t nblk = ceil_div(n, kNbOuter);
+  if (nblk <= 1) {  // one block: nothing to overlap
+    KRR_TRY(potrf_lower(n, A, lda, info, s));
+    return tri_inv_lower(n, A, lda, X, ldx, s);
+  }
+  SideStream side;
+  KRR_TRY(hip_check(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking), "side stream"));
+  side.ev.assign((size_t)nblk + 2, nullptr);
+  for (hipEvent_t& e : side.ev)
+    KRR_TRY(hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event"));
+  KRR_TRY(hip_check(hipMemsetAsync(info, 0, sizeof(int), s), "potrf info reset"));
+  // the side stream starts behind everything queued on s so far (A, X = I)
+  KRR_TRY(hip_check(hipEventRecord(side.ev[nblk], s), "event record"));
+  KRR_TRY(hip_check(hipStreamWaitEvent(side.st, side.ev[nblk], 0), "stream wait"));
+  for (int64_t b = 0, k = 0; k < n; ++b, k += kNbOuter) {
+    const int64_t nb = std::min<int64_t>(kNbOuter, n - k);
+    double* Akk = A + k * lda + k;
+    KRR_TRY(potrf_block(nb, Akk, lda, info, k, s));
+    const int64_t rest = n - k - nb;
+    double* L21 = A + (k + nb) * lda + k;
+    if (rest > 0) KRR_TRY(panel_trsm(rest, nb, Akk, lda, L21, lda, s));
+    KRR_TRY(hip_check(hipEventRecord(side.ev[b], s), "event record"));
+    if (rest > 0)
+      KRR_TRY(gemm_f64_ex(false, true, rest, rest, nb, -1.0, L21, lda, L21, lda, 1.0,
+                          A + (k + nb) * lda + (k + nb), lda, s, nullptr, true));
+    KRR_TRY(hip_check(hipStreamWaitEvent(side.st, side.ev[b], 0), "stream wait"));
+    KRR_TRY(tri_inv_step(n, k, A, lda, X, ldx, side.st));
+  }
+  KRR_TRY(hip_check(hipEventRecord(side.ev[nblk + 1], side.st), "event record"));
+  return hip_check(hipStreamWaitEvent(s, side.ev[nblk + 1], 0), "stream join");
 }
 
 int trsm_lower_left(int64_t n, int64_t ncols, const double* L, int64_t lda, double* B,
