@@ -10,7 +10,8 @@ kernel tiles.
 One step = one whole solve with the inputs resident in HBM: the KRILL build
 (centres, H, the sketch, B = Phi A(:,S), B^T B + H, its Cholesky factor and
 L^{-1}) plus PCG (two restricted products per iteration, the preconditioner
-apply, FP64 recurrences) plus the FP64 true-residual check.
+apply, FP64 recurrences) and the FP64 true residual at exit (carried by the
+converging iteration, whose products also multiply x).
 
 `value` is the number of kernel entries the fused restricted products
 evaluate (A(S,:) y: N k; each operator application: 2 N k) per second of
@@ -139,10 +140,12 @@ def headline(a, b, torch, synth, np):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     b.timing_enable(False)
-    tile_ms, launches = b.timing_read()
+    # every tile launch, and those of the one-vector tile (the roofline's
+    # kernel; the iteration that carries x beside p runs the two-vector one)
+    tile_ms, launches, one_ms, one_launches = b.timing_read_vectors(1)
     # fused-product entries: A(S,:) y (N k) and 2 N k per operator application
     entries = sum(N * k * (1 + 2 * i["products"]) for i in infos)
-    launch_ms = tile_ms / max(launches, 1)
+    launch_ms = one_ms / max(one_launches, 1)
     # algorithmic FP64 flops of one kernel entry: the distance contraction
     # (d multiply-adds), adding the two squared norms, and the reduction
     # against V (m = 1 multiply-add); the exp is not counted
@@ -156,7 +159,7 @@ def headline(a, b, torch, synth, np):
                 "traffic_unit": "bytes per launch",
                 "kernel": "tile_gauss_mfma<double, 16, 1> (FP64 Gaussian MFMA tile, exp on the VALU)",
                 "flops_per_entry": flops_entry, "entries_per_launch": N * k,
-                "launch_ms": round(launch_ms, 4), "launches_timed": launches,
+                "launch_ms": round(launch_ms, 4), "launches_timed": one_launches,
                 "algorithmic_bytes_per_launch": 8 * (N * d + k * d + N + k)}
     if issue:
         # FP64 MFMA and FP64 VALU instructions do not overlap on this tile

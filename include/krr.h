@@ -104,6 +104,13 @@ int krr_kernel_matvec_noalloc(krr_kernel_kind kind, double sigma, krr_precision 
  * summed duration (ms) and count, and clears the record.                   */
 int krr_timing_enable(int on);
 int krr_timing_read(double* total_ms, int64_t* launches);
+/* As krr_timing_read, and also the summed duration and count of the launches
+ * whose FP64 / FP32 Gaussian matrix-core tile carries `vectors` (1, 2, 4 or
+ * 8) right-hand-side vectors (0: the form for 9-16 vectors, which reduces
+ * them on the matrix cores).  Launches of other tiles match no `vectors`.
+ * Returns KRR_EINVAL for vectors < 0.                                      */
+int krr_timing_read_vectors(int32_t vectors, double* total_ms, int64_t* launches,
+                            double* match_ms, int64_t* match_launches);
 
 /* ---------------------------------------------------------------------
  * Preconditioned solves.  A krr_precond is an opaque host object holding
@@ -124,7 +131,8 @@ typedef struct {
   int32_t history_cap;      /* capacity of history (in entries) */
   int32_t history_len;      /* entries written */
   int32_t products;         /* system-operator applications: one per PCG step
-                               plus one per FP64 true-residual check */
+                               plus one per FP64 true-residual check that
+                               was not carried by a step (see krr_pcg_solve) */
 } krr_solve_info;
 
 /* Full-data KRR (eq. exact_eqn): (A + mu I) beta = y with A_ij = K(x_i, x_j),
@@ -251,7 +259,12 @@ void krr_precond_free(krr_precond P);
  * ||r|| <= tol ||b|| on the recursive residual, or max_iter.  Y is N x m
  * (targets, row-major, device); beta receives n x m (N for full-data, k for
  * restricted).  At exit the true residual is evaluated with an FP64 product.
- * FP64 tiles: one residual-replacement restart if it exceeds 10 tol.
+ * FP64 tiles: one residual-replacement restart if it exceeds 10 tol.  With
+ * FP64 tiles, m up to 4, more than 1.6e7 kernel entries per operator
+ * application and no stored block, the step whose recursive residual is
+ * predicted within 5 tol (and the last step allowed) also multiplies x in
+ * the same launches; if it ends the solve, its true residual
+ * (b - M x) - alpha (M p) is the exit check and no further product runs.
  * FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG restarted
  * from the FP64 true residual, each round run to tol/10 on its recursive
  * residual, or to tol/2 where the previous round's contraction puts the

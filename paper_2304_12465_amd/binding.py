@@ -40,6 +40,8 @@ _SIGS = {
     "krr_last_error": ([], _c.c_char_p),
     "krr_timing_enable": ([_i32], _i32),
     "krr_timing_read": ([ctypes.POINTER(ctypes.c_double), _i64p], _i32),
+    "krr_timing_read_vectors": ([_i32, ctypes.POINTER(ctypes.c_double), _i64p,
+                                 ctypes.POINTER(ctypes.c_double), _i64p], _i32),
     "krr_rpchol_ws": ([_i32, _i32, _i64, _i32, _i32, _i32, _i32, _szp], _i32),
     "krr_rpchol_build": ([_i32, _dbl, _i32, _vp, _i64, _i32, _dbl, _i32, _i32, _u64, _i32, _vp,
                           _sz, _pp, _vp], _i32),
@@ -333,6 +335,16 @@ def timing_read():
     n = ctypes.c_int64(0)
     check(lib().krr_timing_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def timing_read_vectors(vectors):
+    """(total ms, launches) of product tiles since the last read, and the
+    same for the Gaussian matrix-core tiles carrying `vectors` vectors."""
+    ms, n = ctypes.c_double(0), ctypes.c_int64(0)
+    mms, mn = ctypes.c_double(0), ctypes.c_int64(0)
+    check(lib().krr_timing_read_vectors(int(vectors), ctypes.byref(ms), ctypes.byref(n),
+                                        ctypes.byref(mms), ctypes.byref(mn)))
+    return ms.value, n.value, mms.value, mn.value
 
 
 def krill_ws(kind, prec, N, d, k, sketch_rows=0, zeta=0, m_max=1):

@@ -191,3 +191,12 @@ extern "C" int krr_timing_enable(int on) {
 extern "C" int krr_timing_read(double* total_ms, int64_t* launches) {
   return tile_timing_read(total_ms, launches);
 }
+
+extern "C" int krr_timing_read_vectors(int32_t vectors, double* total_ms, int64_t* launches,
+                                       double* match_ms, int64_t* match_launches) {
+  if (vectors < 0) {
+    set_error("krr_timing_read_vectors: vectors must be >= 0");
+    return KRR_EINVAL;
+  }
+  return tile_timing_read(total_ms, launches, vectors, match_ms, match_launches);
+}

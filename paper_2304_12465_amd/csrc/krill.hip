@@ -364,7 +364,8 @@ int krill_layout(Arena& a, Precond& P) {
   P.H = a.take<double>((size_t)k * k);
   P.C = a.take<double>((size_t)k * k);
   P.Linv = a.take<double>((size_t)k * k);
-  pcg_carve(a, P.pcg, k, P.m_max, N, 0);
+  P.spec_m = spec_columns(P);
+  pcg_carve(a, P.pcg, k, P.m_max, N, 0, P.spec_m);
   KrillWork& w = P.kw;
   const int64_t nblk = ceil_div(N, kBlk);
   w.flags = a.take<int>(N);
@@ -386,12 +387,14 @@ int krill_layout(Arena& a, Precond& P) {
     P.kns = a.take<char>(kb);
     P.kns_part = a.take<double>(part / sizeof(double));
   }
-  const size_t ps = std::max(product_scratch_bytes(P.prec, N, k, P.m_max),
-                             product_scratch_bytes(P.prec, k, N, P.m_max));
+  // operator products take up to m_max + spec_m columns
+  const int32_t mc = P.m_max + P.spec_m;
+  const size_t ps = std::max(product_scratch_bytes(P.prec, N, k, mc),
+                             product_scratch_bytes(P.prec, k, N, mc));
   const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, k, P.m_max),
                                product_scratch_bytes(KRR_FP64, k, N, P.m_max));
   const size_t gs = std::max(gemm_scratch_bytes(k, k, P.sketch_rows, true),
-                             gemm_scratch_bytes(P.m_max, k, k));
+                             gemm_scratch_bytes(mc, k, k));
   const size_t sb = std::max(std::max(ps, ps64), gs) + kAlign;
   char* sc = a.take<char>(sb);
   P.scratch = Arena(sc, sb);

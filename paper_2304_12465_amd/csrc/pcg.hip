@@ -19,6 +19,25 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxRefine = 6;  // refinement rounds for FP32 / MIXED tiles
+// A step carries x beside p (FP64 tiles) when its recursive residual is
+// predicted at most this many times the target.  A step that carries x and
+// does not converge costs one more vector in the product (the FP64 Gaussian
+// tile over 2,000,000 x 10,000 entries: 18.0 ms with two vectors against
+// 16.9 ms with one); a converging one that does not carry it costs a whole
+// operator product for the true residual, 15 times more.  The generous
+// margin absorbs a contraction that slows from one step to the next (the
+// 2,000,000-point KRILL solve to 1e-6: 0.02, 0.04, 0.08, 0.17, 0.16).
+constexpr double kSpecReach = 5.0;
+
+// Products of at most this many kernel entries take well under 0.1 ms, so a
+// host round trip per iteration would cost as much as the iteration: such
+// solves run in bursts, and their exit check is no cheaper carried.
+constexpr double kBurstEntries = 1.6e7;
+
+// Kernel entries of one operator application to m vectors.
+double operator_entries(const Precond& P, int m) {
+  return P.type == kRPChol ? (double)P.N * (double)P.N * m : 2.0 * (double)P.N * (double)P.k * m;
+}
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -236,6 +255,21 @@ __global__ void axpby(double* __restrict__ y, const double* __restrict__ x, doub
   if (t < len) y[t] = a * x[t] + b * y[t];
 }
 
+// True residual of x + alpha p from the product of x and of p taken in the
+// same step: wx <- (b - M x) - alpha (M p), column c at offset c n (wx holds
+// M x on entry; alpha = 0 for a column that was not active, whose x did not
+// move).
+__global__ void carried_residual(const double* __restrict__ b, const double* __restrict__ w,
+                                 double* __restrict__ wx, const double* __restrict__ scal,
+                                 int m_max, int64_t n) {
+  const int c = blockIdx.y;
+  const double alpha = scal[kAlpha * m_max + c];
+  const int64_t off = (int64_t)c * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    wx[off + i] = (b[off + i] - wx[off + i]) - alpha * w[off + i];
+}
+
 __global__ void fill(double* __restrict__ y, double v, int64_t len) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < len) y[t] = v;
@@ -312,28 +346,30 @@ int to_rowmajor(const double* src, int64_t n, int32_t m, double* dst, hipStream_
   return KRR_OK;
 }
 
-size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_restricted, int32_t rank) {
+size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_restricted, int32_t rank, int32_t spec_m) {
   Arena a;
   PcgState st;
-  pcg_carve(a, st, n, m_max, N_restricted, rank);
+  pcg_carve(a, st, n, m_max, N_restricted, rank, spec_m);
   return a.used;
 }
 
 void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_restricted,
-               int32_t rank) {
+               int32_t rank, int32_t spec_m) {
   st.m_max = m_max;
   st.n = n;
   const size_t v = (size_t)std::max<int64_t>(n, 1) * m_max;
+  // p and w also hold the columns of x (and of M x) that a product may carry
+  const size_t v2 = (size_t)std::max<int64_t>(n, 1) * (m_max + spec_m);
   st.x = a.take<double>(v);
   st.r = a.take<double>(v);
   st.z = a.take<double>(v);
-  st.p = a.take<double>(v);
-  st.w = a.take<double>(v);
+  st.p = a.take<double>(v2);
+  st.w = a.take<double>(v2);
   st.b = a.take<double>(v);
   st.scal = a.take<double>((size_t)kScalars * m_max);
   st.nblk = blocks_for(n);
   st.part = a.take<double>((size_t)st.nblk * m_max);
-  st.tmpN = N_restricted > 0 ? a.take<double>((size_t)N_restricted * m_max) : nullptr;
+  st.tmpN = N_restricted > 0 ? a.take<double>((size_t)N_restricted * (m_max + spec_m)) : nullptr;
   st.tmpR = rank > 0 ? a.take<double>((size_t)rank * m_max) : nullptr;
 }
 
@@ -470,6 +506,70 @@ int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, in
   return KRR_OK;
 }
 
+namespace {
+
+// The decision after a true residual (wres: b - M x, column c at offset
+// c n): done, or a restart of the recurrence from it.
+void check_decision(Solve& S, const double* h, const double* wres, hipStream_t s) {
+  Precond& P = *S.P;
+  PcgState& st = P.pcg;
+  const int mm = st.m_max;
+  S.worst_true = 0.0;
+  bool replace = false, bad = false;
+  for (int c = 0; c < S.m; ++c) {
+    const double bb = h[kBB * mm + c];
+    S.true_rel[c] = 0.0;
+    if (bb <= 0) continue;
+    const double rt = std::sqrt(h[kTrue * mm + c] / bb);
+    S.true_rel[c] = rt;
+    if (!std::isfinite(rt)) bad = true;
+    S.worst_true = std::max(S.worst_true, rt);
+    // FP64 tiles: replace when the recurrence drifted (> 10 tol).
+    // FP32 / MIXED tiles: iterative refinement with the FP64 residual
+    // until it meets tol (the lower-precision operator limits the
+    // recurrence).
+    if (rt > (P.prec == KRR_FP64 ? 10.0 * S.tol : S.tol)) replace = true;
+  }
+  if (bad) {
+    set_error("NaN/Inf in the true residual");
+    fail(S, KRR_ENAN);
+    return;
+  }
+  const int max_restarts = P.prec == KRR_FP64 ? 1 : kMaxRefine;
+  if (!replace || S.restarts >= max_restarts || S.it >= S.max_iter) {
+    S.phase = kPhaseDone;
+    return;
+  }
+  ++S.restarts;
+  // A refinement round aims below tol: the lower-precision operator
+  // leaves part of each round's correction in the true residual.  That
+  // part scales with the round's starting residual; the last round's
+  // contraction of the true residual (rho, which includes it) bounds the
+  // coming round's share by rho * worst_true.  Where that is at most
+  // tol / 10 the round only has to reach tol / 2 (the true residual then
+  // ends near or below 0.6 tol); otherwise it aims at tol / 10.
+  if (P.prec != KRR_FP64) {
+    const double rho = S.prev_true > 0.0 ? S.worst_true / S.prev_true : 1.0;
+    S.tol_inner = (rho * S.worst_true <= 0.1 * S.tol ? 0.5 : 0.1) * S.tol;
+  }
+  S.prev_true = S.worst_true;
+  S.gap_read = S.gap_pending = false;
+  if (P.nsamp > 0) S.gap_next = 0.5 * S.worst_true;
+  const int64_t len = st.n * S.m;
+  int rc = hip_check(hipMemcpyAsync(st.r, wres, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
+                     "r = true residual");
+  if (rc == KRR_OK)
+    rc = dot_cols(st, st.r, st.r, S.m, kFinActivate, S.tol_inner * S.tol_inner, 0, s);
+  if (rc == KRR_OK) rc = restart_direction(S, s);
+  if (rc < 0) {
+    fail(S, rc);
+    return;
+  }
+  S.phase = kPhaseIterate;
+}
+
+}  // namespace
+
 int solve_step(Solve* const* solves, int n, hipStream_t s) {
   // 1. products: direction products of iterating solves (their precision)
   //    and FP64 true-residual products of checking solves, one group.
@@ -481,6 +581,21 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
     Precond& P = *S.P;
     PcgState& st = P.pcg;
     const bool check = S.phase == kPhaseCheck;
+    // a step predicted to converge carries x beside p (columns m .. 2m - 1)
+    S.spec_now = !check && S.spec_next && P.spec_m >= S.m;
+    S.spec_next = false;
+    if (check) ++S.check_products;
+    const int32_t mc = S.spec_now ? 2 * S.m : S.m;
+    if (S.spec_now) {
+      const int rc = hip_check(hipMemcpyAsync(st.p + (int64_t)S.m * st.n, st.x,
+                                              sizeof(double) * st.n * S.m,
+                                              hipMemcpyDeviceToDevice, s),
+                               "carry x");
+      if (rc < 0) {
+        fail(S, rc);
+        continue;
+      }
+    }
     VecBlock src{check ? st.x : st.p, st.n}, dst{st.w, st.n};
     if (P.type == kRPChol) {
       ProductReq r;
@@ -490,7 +605,7 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       r.rows = check ? &P.pts64 : &P.pts;
       r.cols = r.rows;
       r.V = src.view();
-      r.m = S.m;
+      r.m = mc;
       r.shift = P.mu;
       r.Vs = src.view();
       r.W = dst.out();
@@ -498,7 +613,7 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       reqs.push_back(r);
       owner.push_back(q);
     } else {
-      const int rc = apply_operator(P, src, S.m, dst, check, s);
+      const int rc = apply_operator(P, src, mc, dst, check, s);
       if (rc < 0) fail(S, rc);
     }
   }
@@ -564,6 +679,14 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       rc = hip_check(hipGetLastError(), "axpby");
       if (rc == KRR_OK) rc = dot_cols(st, st.w, st.w, S.m, kFinSum, 0, kTrue, s);
     }
+    if (rc == KRR_OK && S.phase == kPhaseIterate && S.spec_now) {
+      // the true residual of the updated x, from the product's x columns
+      double* wx = st.w + (int64_t)S.m * nn;
+      carried_residual<<<dim3((unsigned)std::min<int64_t>(ceil_div(nn, 256), 4096), (unsigned)S.m),
+                         256, 0, s>>>(st.b, st.w, wx, st.scal, mm, nn);
+      rc = hip_check(hipGetLastError(), "carried_residual");
+      if (rc == KRR_OK) rc = dot_cols(st, wx, wx, S.m, kFinSum, 0, kTrue, s);
+    }
     if (rc == KRR_OK) rc = pull_async(S, s);
     if (rc < 0) fail(S, rc);
   }
@@ -595,8 +718,21 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
       }
       S.history.push_back(worst);
       if (!any || S.it >= S.max_iter) {
-        S.phase = kPhaseCheck;
+        // a step that carried x has its true residual in hand already
+        if (S.spec_now)
+          check_decision(S, h, st.w + (int64_t)S.m * st.n, s);
+        else
+          S.phase = kPhaseCheck;
         continue;
+      }
+      if (P.spec_m >= S.m && operator_entries(P, S.m) > kBurstEntries) {
+        // carry x in the next step when its recursive residual, predicted
+        // by this step's contraction applied once more, is within
+        // kSpecReach of the target, or when it is the last step allowed
+        const size_t nh = S.history.size();
+        const double prev = nh >= 2 ? S.history[nh - 2] : 1.0;
+        const double rho = prev > 0.0 ? std::min(1.0, worst / prev) : 1.0;
+        S.spec_next = worst * rho <= kSpecReach * S.tol_inner || S.it + 1 >= S.max_iter;
       }
       if (S.gap_read) {
         // The recursive residual r tracks b - A_mixed x; the FP64 residual
@@ -633,59 +769,8 @@ int solve_step(Solve* const* solves, int n, hipStream_t s) {
         }
       }
       if (rc < 0) fail(S, rc);
-    } else {  // check
-      S.worst_true = 0.0;
-      bool replace = false, bad = false;
-      for (int c = 0; c < S.m; ++c) {
-        const double bb = h[kBB * mm + c];
-        S.true_rel[c] = 0.0;
-        if (bb <= 0) continue;
-        const double rt = std::sqrt(h[kTrue * mm + c] / bb);
-        S.true_rel[c] = rt;
-        if (!std::isfinite(rt)) bad = true;
-        S.worst_true = std::max(S.worst_true, rt);
-        // FP64 tiles: replace when the recurrence drifted (> 10 tol).
-        // FP32 / MIXED tiles: iterative refinement with the FP64 residual
-        // until it meets tol (the lower-precision operator limits the
-        // recurrence).
-        if (rt > (P.prec == KRR_FP64 ? 10.0 * S.tol : S.tol)) replace = true;
-      }
-      if (bad) {
-        set_error("NaN/Inf in the true residual");
-        fail(S, KRR_ENAN);
-        continue;
-      }
-      const int max_restarts = P.prec == KRR_FP64 ? 1 : kMaxRefine;
-      if (!replace || S.restarts >= max_restarts || S.it >= S.max_iter) {
-        S.phase = kPhaseDone;
-        continue;
-      }
-      ++S.restarts;
-      // A refinement round aims below tol: the lower-precision operator
-      // leaves part of each round's correction in the true residual.  That
-      // part scales with the round's starting residual; the last round's
-      // contraction of the true residual (rho, which includes it) bounds the
-      // coming round's share by rho * worst_true.  Where that is at most
-      // tol / 10 the round only has to reach tol / 2 (the true residual then
-      // ends near or below 0.6 tol); otherwise it aims at tol / 10.
-      if (P.prec != KRR_FP64) {
-        const double rho = S.prev_true > 0.0 ? S.worst_true / S.prev_true : 1.0;
-        S.tol_inner = (rho * S.worst_true <= 0.1 * S.tol ? 0.5 : 0.1) * S.tol;
-      }
-      S.prev_true = S.worst_true;
-      S.gap_read = S.gap_pending = false;
-      if (P.nsamp > 0) S.gap_next = 0.5 * S.worst_true;
-      const int64_t len = st.n * S.m;
-      int rc = hip_check(hipMemcpyAsync(st.r, st.w, sizeof(double) * len, hipMemcpyDeviceToDevice, s),
-                         "r = true residual");
-      if (rc == KRR_OK)
-        rc = dot_cols(st, st.r, st.r, S.m, kFinActivate, S.tol_inner * S.tol_inner, 0, s);
-      if (rc == KRR_OK) rc = restart_direction(S, s);
-      if (rc < 0) {
-        fail(S, rc);
-        continue;
-      }
-      S.phase = kPhaseIterate;
+    } else {
+      check_decision(S, h, st.w, s);
     }
   }
   return KRR_OK;
@@ -721,7 +806,7 @@ int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
     info->converged_cols = conv;
     info->relres_recursive = worst_rec;
     info->relres_true = S.worst_true;
-    info->products = S.it + S.restarts + 1;
+    info->products = S.it + S.check_products;
     info->build_seconds = P.build_seconds;
     info->solve_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - S.t0).count();
@@ -736,17 +821,11 @@ int solve_end(Solve& S, double* beta, krr_solve_info* info, hipStream_t s) {
 
 namespace {
 
-// Products of at most this many kernel entries take well under 0.1 ms, so a
-// host round trip per iteration would cost as much as the iteration.
-constexpr double kBurstEntries = 1.6e7;
-
 bool burst_eligible(const Solve& S) {
   const Precond& P = *S.P;
   if (S.phase != kPhaseIterate || S.gap_next > 0.0 || S.gap_pending || S.gap_read) return false;
   if (red_for(P.pcg.n).nblk != 1) return false;  // the one-launch short-vector kernels
-  const double entries = P.type == kRPChol ? (double)P.N * (double)P.N * S.m
-                                           : 2.0 * (double)P.N * (double)P.k * S.m;
-  return entries <= kBurstEntries && S.max_iter - S.it >= 2;
+  return operator_entries(P, S.m) <= kBurstEntries && S.max_iter - S.it >= 2;
 }
 
 // Up to kBurst iterations of one solve between two host synchronisations.

@@ -230,11 +230,16 @@ int matvec_impl(int kind, double sigma, int prec, const double* Xr, int64_t nr, 
                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 // Tile timer hooks: start returns a token (or null when timing is off).
-void* tile_timer_start(hipStream_t s);
+// vectors: the right-hand-side vectors the launched Gaussian matrix-core
+// tile instantiation carries (0: its 9-16-vector form; -1 for other tiles)
+void* tile_timer_start(hipStream_t s, int vectors = -1);
 void tile_timer_stop(void* token, hipStream_t s);
 
 // Event timing of the product tile kernel launches (process-wide).
 void tile_timing_enable(bool on);
-int tile_timing_read(double* total_ms, int64_t* launches);
+// All recorded launches, and those whose tile carried `vectors` vectors
+// (match_*, optional); clears the record.
+int tile_timing_read(double* total_ms, int64_t* launches, int vectors = -1,
+                     double* match_ms = nullptr, int64_t* match_launches = nullptr);
 
 }  // namespace krr

@@ -279,7 +279,9 @@ struct GTable {
 // VGPRs, 4 waves per SIMD (no spill up to 2 right-hand sides: the distance
 // of one column tile at a time and V staged for the m columns used; the
 // 2,000,000 x 10,000 product 17.2-18.7 -> 16.6-16.8 ms together with the
-// XCD item order; 5 waves spill 28+ registers and lose 1-50%).  Up to 48
+// XCD item order; 5 waves spill 28+ registers and lose 1-50%; with 4 to 16
+// right-hand sides they spill 14-43 registers and are still 1-6% faster
+// than at 3 waves, measured at d = 8 and 16 on 200,000 x 100,000).  Up to 48
 // padded dimensions they are held to 168 VGPRs, 3 waves instead of 2, at the
 // price of a register spill (at d = 32, up to 44 registers, outside the
 // inner loop); measured on N = 200,000: d = 32 with 1 / 8 right-hand sides
@@ -586,7 +588,7 @@ int g_launch(const std::vector<GJob<T>>& jobs, hipStream_t s) {
           any_mfma = any_mfma || tab.job[q].route != 2;
           any_direct = any_direct || tab.job[q].route != 1;
         }
-        void* tok = tile_timer_start(s);
+        void* tok = tile_timer_start(s, mv);
         if (any_mfma) switch (D) {
           case 4: launch_d<T, 4>(mv, grid, tab, s); break;
           case 8: launch_d<T, 8>(mv, grid, tab, s); break;

@@ -478,7 +478,11 @@ int rows_for_dpad(int D) { return D <= 32 ? 2 : 1; }
 struct TileTimer {
   std::mutex mu;
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  struct Rec {
+    hipEvent_t e0, e1;
+    int vectors;
+  };
+  std::vector<Rec> ev;
   std::vector<hipEvent_t> pool;
   hipEvent_t get() {
     if (!pool.empty()) {
@@ -498,14 +502,14 @@ TileTimer& timer() {
 
 }  // namespace
 
-void* tile_timer_start(hipStream_t s) {
+void* tile_timer_start(hipStream_t s, int vectors) {
   TileTimer& tt = timer();
   std::lock_guard<std::mutex> g(tt.mu);
   if (!tt.on) return nullptr;
   hipEvent_t e0 = tt.get(), e1 = tt.get();
   if (!e0 || !e1) return nullptr;
   (void)hipEventRecord(e0, s);
-  tt.ev.emplace_back(e0, e1);
+  tt.ev.push_back({e0, e1, vectors});
   return reinterpret_cast<void*>(tt.ev.size());  // 1-based index
 }
 
@@ -514,7 +518,7 @@ void tile_timer_stop(void* token, hipStream_t s) {
   TileTimer& tt = timer();
   std::lock_guard<std::mutex> g(tt.mu);
   const size_t i = reinterpret_cast<size_t>(token) - 1;
-  if (i < tt.ev.size()) (void)hipEventRecord(tt.ev[i].second, s);
+  if (i < tt.ev.size()) (void)hipEventRecord(tt.ev[i].e1, s);
 }
 
 void tile_timing_enable(bool on) {
@@ -523,20 +527,28 @@ void tile_timing_enable(bool on) {
   t.on = on;
 }
 
-int tile_timing_read(double* total_ms, int64_t* launches) {
+int tile_timing_read(double* total_ms, int64_t* launches, int vectors, double* match_ms,
+                     int64_t* match_launches) {
   TileTimer& t = timer();
   std::lock_guard<std::mutex> g(t.mu);
-  double tot = 0.0;
-  for (auto& pr : t.ev) {
-    KRR_TRY(hip_check(hipEventSynchronize(pr.second), "timing sync"));
+  double tot = 0.0, mt = 0.0;
+  int64_t mn = 0;
+  for (auto& rec : t.ev) {
+    KRR_TRY(hip_check(hipEventSynchronize(rec.e1), "timing sync"));
     float ms = 0.f;
-    KRR_TRY(hip_check(hipEventElapsedTime(&ms, pr.first, pr.second), "elapsed"));
+    KRR_TRY(hip_check(hipEventElapsedTime(&ms, rec.e0, rec.e1), "elapsed"));
     tot += ms;
-    t.pool.push_back(pr.first);
-    t.pool.push_back(pr.second);
+    if (rec.vectors == vectors) {
+      mt += ms;
+      ++mn;
+    }
+    t.pool.push_back(rec.e0);
+    t.pool.push_back(rec.e1);
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = (int64_t)t.ev.size();
+  if (match_ms) *match_ms = mt;
+  if (match_launches) *match_launches = mn;
   t.ev.clear();
   return KRR_OK;
 }

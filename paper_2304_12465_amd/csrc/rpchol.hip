@@ -443,7 +443,8 @@ int rpchol_layout(Arena& a, Precond& P) {
   const int64_t N = P.N;
   P.QT = a.take<double>((size_t)P.r_req * N);
   P.core = a.take<double>((size_t)P.r_req * P.r_req);
-  pcg_carve(a, P.pcg, N, P.m_max, 0, P.r_req);
+  P.spec_m = spec_columns(P);
+  pcg_carve(a, P.pcg, N, P.m_max, 0, P.r_req, P.spec_m);
   // MIXED: sampled rows for the residual-gap estimate of the refinement
   P.nsamp = P.prec == KRR_MIXED ? std::min<int64_t>(N, kGapRows) : 0;
   if (P.nsamp > 0) {
@@ -470,7 +471,8 @@ int rpchol_layout(Arena& a, Precond& P) {
   w.gi = a.take<int64_t>(nch);
   w.vmax = a.take<double>(1);
   // scratch for products, split-K GEMMs of the build and of the applies
-  const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max);
+  // iteration products take up to m_max + spec_m columns
+  const size_t ps = product_scratch_bytes(P.prec, N, N, P.m_max + P.spec_m);
   const size_t ps64 = std::max(product_scratch_bytes(KRR_FP64, N, N, P.m_max),
                                product_scratch_bytes(KRR_FP64, P.nsamp, N, P.m_max));
   const size_t gs = std::max(gemm_scratch_bytes(P.m_max, P.r_req, N),

@@ -42,7 +42,7 @@ struct PcgState {
   double* part = nullptr;                   // reduction partials
   int nblk = 0;                             // reduction blocks per column
   double* host = nullptr;                   // pinned host mirror of scal
-  double* tmpN = nullptr;                   // N x m_max (restricted: K_NS p)
+  double* tmpN = nullptr;                   // N x (m_max + spec) (restricted: K_NS p)
   double* tmpR = nullptr;                   // rank x m_max (Woodbury: Q^T r)
 };
 
@@ -133,6 +133,9 @@ struct Precond {
   double* kns_part = nullptr;
   // PCG state and scratch
   PcgState pcg;
+  // FP64 tiles: the columns of x that an iteration's operator product may
+  // carry beside p (p and w hold m_max + spec_m columns; 0 = none)
+  int32_t spec_m = 0;
   Arena scratch;
   size_t ws_used = 0;
   double build_seconds = 0.0;
@@ -156,9 +159,18 @@ __host__ __device__ inline int64_t gap_row(int64_t q, int64_t N, int64_t nsamp) 
   return q * N / nsamp;
 }
 
-size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_for_restricted, int32_t rank);
+size_t pcg_bytes(int64_t n, int32_t m_max, int64_t N_for_restricted, int32_t rank,
+                 int32_t spec_m = 0);
 void pcg_carve(Arena& a, PcgState& st, int64_t n, int32_t m_max, int64_t N_for_restricted,
-               int32_t rank);
+               int32_t rank, int32_t spec_m = 0);
+// Columns of x carried beside p by the iteration products (FP64 tiles, up
+// to kSpecMax right-hand sides, not over a stored block): the iteration
+// expected to converge also forms M x, so that its true residual needs no
+// product of its own.  Set before the layout is carved.
+constexpr int32_t kSpecMax = 4;
+inline int32_t spec_columns(const Precond& P) {
+  return (P.prec == KRR_FP64 && !P.stored && P.m_max <= kSpecMax) ? P.m_max : 0;
+}
 
 // System operator M V (full: K V + mu V; restricted: K_SN K_NS V + H V) in the
 // product precision `prec` (or FP64 when force64).
@@ -198,6 +210,11 @@ struct Solve {
   // arrive with this step's scalars
   double gap_next = 0.0;
   bool gap_pending = false, gap_read = false;
+  // true residual carried by an iteration: spec_next = the next step's
+  // product also takes x (its recursive residual is predicted within reach
+  // of tol); spec_now = this step's did
+  bool spec_next = false, spec_now = false;
+  int check_products = 0;  // operator products spent on true residuals
   std::chrono::steady_clock::time_point t0;
 };
 int solve_begin(Solve& S, Precond& P, const double* Y, int32_t m, double tol, int32_t max_iter,

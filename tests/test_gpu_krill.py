@@ -169,6 +169,48 @@ def test_restricted_solve_fp32_tiles_within_derived_bounds():
     print(f"fp32-tile fitted-value difference vs oracle: {rel:.2e}")
 
 
+@pytest.mark.parametrize("m", [1, 3])
+def test_carried_true_residual_matches_oracle(m):
+    # 40,000 points x 250 centres: above the size of the short-solve bursts,
+    # so every iteration is a step.  With FP64 tiles the step predicted to
+    # converge, and the last step allowed, carry x beside p; the exit check
+    # (b - M x) - alpha (M p) then needs no product of its own.  relres_true
+    # must be the oracle's ||b - M beta|| / ||b|| of the returned beta, to
+    # within the FP64 tile error of M x, M p (test_restricted_operator: 1e-12
+    # of (|A_SN||A_NS| + |H|)|v|) and of b = A(S,:) y.
+    p = small(n=40_000, k=250)
+    P = build(p, 0, m_max=m)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    g = np.random.default_rng(21)
+    Y = np.column_stack([p.Y[:, 0]] + [g.standard_normal(p.X.shape[0]) for _ in range(m - 1)])
+    b = kr.rhs(Y)
+    M = kr.restricted_matrix()
+    Mabs = np.abs(kr.AnS).T @ np.abs(kr.AnS) + np.abs(kr.H)
+    bnorm = np.linalg.norm(b, axis=0)
+    berr = 1e-12 * np.linalg.norm(np.abs(kr.AnS).T @ np.abs(Y), axis=0)
+    for max_iter, tol in ((3, 1e-12), (200, 1e-8)):
+        beta, info = P.solve(T(Y), tol, max_iter=max_iter)
+        beta = beta.cpu().numpy().reshape(-1, m)
+        res = np.linalg.norm(b - M @ beta, axis=0) / bnorm
+        err = (3e-12 * np.linalg.norm(Mabs @ np.abs(beta), axis=0) + berr) / bnorm
+        print(f"m={m} max_iter={max_iter}: iters {info['iters']} products {info['products']} "
+              f"relres_true {info['relres_true']:.3e} oracle {res.max():.3e} bound {err.max():.1e}")
+        assert abs(info["relres_true"] - res.max()) <= err.max() + 1e-6 * res.max(), (info, res)
+        if max_iter == 3:
+            assert not info["converged"] and info["iters"] == 3 and info["products"] == 3, info
+        else:
+            assert info["converged"] and info["products"] <= info["iters"] + 1, info
+    # the same solve with no carried columns (m_max above the carrying limit):
+    # the same iterates, and one more product for the exit check
+    P5 = build(p, 0, m_max=5)
+    beta5, info5 = P5.solve(T(Y), 1e-8, max_iter=200)
+    assert info5["iters"] == info["iters"] and info5["products"] == info5["iters"] + 1, info5
+    np.testing.assert_allclose(beta, beta5.cpu().numpy().reshape(-1, m), rtol=0,
+                               atol=1e-10 * np.abs(beta).max())
+
+
 def test_given_centres_and_multi_rhs():
     p = small()
     S = np.sort(np.random.default_rng(4).choice(p.X.shape[0], p.centers, replace=False))

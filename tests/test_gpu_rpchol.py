@@ -132,6 +132,34 @@ def test_apply_matches_svd_form_long_contraction(n, m, m_max):
     assert np.all(rel <= 100 * len(piv_o) * EPS * kapP), (rel, kapP)
 
 
+def test_carried_true_residual_full_data():
+    # 5,000 points of the c1 recipe: above the size of the short-solve
+    # bursts, so every iteration is a step.  FP64 tiles carry x beside p in
+    # the last step allowed and in the step predicted to converge; the exit
+    # check is then (y - (K + mu I) x) - alpha (K + mu I) p from that step's
+    # product.  relres_true must be the dense oracle's ||y - (K + mu I) beta||
+    # / ||y|| of the returned beta, to within the FP64 tile error (1e-13 of
+    # sum |K||v| per entry; 3e-12 allowed).  mu = 1 keeps the solve short.
+    p = synth.c1(n=5000)
+    p.mu = 1.0
+    P = build(p, 0)
+    K = OK.block(p.X, p.X, p.kind, p.sigma)
+    y = p.Y
+    ynorm = np.linalg.norm(y)
+    for max_iter, tol in ((4, 1e-14), (500, 1e-10)):
+        beta, info = P.solve(T(y), tol, max_iter=max_iter)
+        beta = beta.cpu().numpy().reshape(-1, 1)
+        res = np.linalg.norm(y - (K @ beta + p.mu * beta)) / ynorm
+        err = 3e-12 * np.linalg.norm(np.abs(K) @ np.abs(beta) + p.mu * np.abs(beta)) / ynorm
+        print(f"max_iter={max_iter}: iters {info['iters']} products {info['products']} "
+              f"relres_true {info['relres_true']:.3e} oracle {res:.3e} bound {err:.1e}")
+        assert abs(info["relres_true"] - res) <= err + 1e-6 * res, (info, res, err)
+        if max_iter == 4:
+            assert not info["converged"] and info["iters"] == 4 and info["products"] == 4, info
+        else:
+            assert info["converged"] and info["products"] <= info["iters"] + 1, info
+
+
 def test_c1_solve_matches_dense_cholesky():
     p = synth.c1()
     P = build(p, 0)
