@@ -4,8 +4,9 @@ Headline workload (the largest single-GPU configuration): restricted KRR
 with KRILL preconditioning (Alg. 2) on N = 2,000,000 points of dimension 16
 (standard normal, dimension j scaled by 1/(1+j)), Gaussian kernel sigma = 4,
 k = 10,000 centres drawn uniformly, a sparse sign sketch of 2k rows with 8
-nonzeros per column, mu = 1e-5 N, PCG to a relative residual of 1e-6, FP64
-kernel tiles.
+nonzeros per column, mu = 1e-5 N, PCG to a relative residual of 1e-6: FP64
+tiles for the restricted products, the right-hand side and the residual
+checks, FP32 tiles for the sketch (KRR_MIXED), FP64 factor and CG.
 
 One step = one whole solve with the inputs resident in HBM: the KRILL build
 (centres, H, the sketch, B = Phi A(:,S), B^T B + H, its Cholesky factor and
@@ -22,7 +23,8 @@ and `traffic` come from rocprofv3 counters in profiles/.  `cpu_baseline`
 times the FP64 oracle's restricted product on a bounded row sample on all
 host cores.  The other workloads appear beside it as extra keys: the same
 solve with FP32 tiles, the restricted operator over a stored A(:,S) against
-recomputed tiles at d = 16, 32, 64, the 1,000,000-point Gaussian problem (MIXED, FP32 and
+recomputed tiles at d = 16, 32, 64, the same solve with the sketch on FP64 tiles too, the
+1,000,000-point Gaussian problem (MIXED, FP32 and
 FP64 product rates and a MIXED solve), the 100,000-point Laplace problem
 (FP32 and FP64 solves) and the served stream (p50/p99 latency of 64
 requests, batched MIXED against one at a time in MIXED and in FP64).
@@ -117,10 +119,10 @@ def headline(a, b, torch, synth, np):
     X = torch.from_numpy(p.X).to(dev)
     Y = torch.from_numpy(p.Y).to(dev)
     torch.cuda.synchronize()
-    ws = b.workspace(b.krill_ws(p.kind, b.FP64, N, d, k, p.sketch_rows, p.zeta, 1), dev)
+    ws = b.workspace(b.krill_ws(p.kind, b.MIXED, N, d, k, p.sketch_rows, p.zeta, 1), dev)
 
     def one():
-        P = b.krill_build(p.kind, p.sigma, b.FP64, X, p.mu, k, sketch_rows=p.sketch_rows,
+        P = b.krill_build(p.kind, p.sigma, b.MIXED, X, p.mu, k, sketch_rows=p.sketch_rows,
                           zeta=p.zeta, seed=p.algo_seed, ws=ws)
         beta, info = P.solve(Y, p.tol, 200)
         return P, beta, info
@@ -180,12 +182,14 @@ def headline(a, b, torch, synth, np):
     out = {
         "metric": METRIC, "value": entries / wall, "unit": "kernel entries/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "precision": {"restricted_products": "f64", "rhs_and_checks": "f64", "sketch": "f32",
+                      "factor": "f64", "cg": "f64"},
         "data": "synthetic",
         "config": {"workload": f"restricted KRR with KRILL: N={N}, d={d} standard normal with "
                                "dimension j scaled by 1/(1+j), Gaussian sigma=4, k=10000 uniform "
                                "centres, sparse sign sketch 20000 rows x 8 nonzeros, mu=1e-5 N, "
-                               "PCG to 1e-6, FP64 tiles",
+                               "PCG to 1e-6, FP64 product tiles, FP32 sketch tiles",
                    "N": N, "d": d, "k": k, "sketch_rows": p.sketch_rows, "zeta": p.zeta,
                    "tol": p.tol},
         "solve": solve,
@@ -293,7 +297,8 @@ def main():
     out, ctx = headline(a, b, torch, synth, np)
     if not a.no_extra:
         import bench_configs as BC
-        legs = (("c4_fp32", BC.c4_fp32_leg), ("stored_vs_recomputed", BC.stored_leg),
+        legs = (("c4_fp64", BC.c4_fp64_leg), ("c4_fp32", BC.c4_fp32_leg),
+                ("stored_vs_recomputed", BC.stored_leg),
                 ("c2", BC.c2_leg), ("c3", BC.c3_leg), ("c5", BC.c5_leg))
         for name, fn in legs:
             print(f"bench: {name}", file=sys.stderr, flush=True)

@@ -103,15 +103,24 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X, published FP64 vector / matrix peak
 
 def c4_fp32_leg(a, b, torch, synth, ctx):
     """The headline restricted solve with FP32 tiles (FP64 refinement rounds)."""
+    return c4_prec_leg(b.FP32, b, torch, ctx)
+
+
+def c4_fp64_leg(a, b, torch, synth, ctx):
+    """The headline restricted solve with the sketch on FP64 tiles as well."""
+    return c4_prec_leg(b.FP64, b, torch, ctx)
+
+
+def c4_prec_leg(prec, b, torch, ctx):
     p = ctx["p"]
     X = ctx["X"]
     N, d = p.X.shape
     Y = torch.from_numpy(p.Y).to(X.device)
-    ws = b.workspace(b.krill_ws(p.kind, b.FP32, N, d, p.centers, p.sketch_rows, p.zeta, 1),
+    ws = b.workspace(b.krill_ws(p.kind, prec, N, d, p.centers, p.sketch_rows, p.zeta, 1),
                      X.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = b.krill_build(p.kind, p.sigma, b.FP32, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
+    P = b.krill_build(p.kind, p.sigma, prec, X, p.mu, p.centers, sketch_rows=p.sketch_rows,
                       zeta=p.zeta, seed=p.algo_seed, ws=ws)
     tb = time.perf_counter() - t0
     beta, info = P.solve(Y, p.tol, 400)

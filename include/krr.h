@@ -184,8 +184,13 @@ int krr_rpchol_factor(krr_precond P, double* FT, hipStream_t stream);
  * (H in place of mu A(S,S)); the right-hand side A(S,:) y is formed in FP64.
  * `centers`: device int64[k] of distinct indices in [0, N), or NULL to draw
  * k centres uniformly without replacement with SplitMix64 keyed by `seed`.
- * Limits: 1 <= k <= min(N, 65536), 1 <= zeta <= sketch_rows; `prec` is
- * KRR_FP64 or KRR_FP32 (KRR_MIXED returns KRR_EINVAL before any launch).
+ * Limits: 1 <= k <= min(N, 65536), 1 <= zeta <= sketch_rows.  `prec`:
+ * KRR_FP64 or KRR_FP32 tiles for the sketch and the restricted products;
+ * KRR_MIXED = FP64 restricted products (and FP64 right-hand side and
+ * checks, as KRR_FP64) with the sketch B on FP32 tiles (the workspace then
+ * also holds FP32 copies of X and the centres): B carries the FP32 tiles'
+ * entry error (2e-5 of |Phi||A(:,S)| at most), which changes only the
+ * preconditioner, not the system solved.
  * The build synchronises `stream`.  Returns KRR_ENOTSPD if P cannot be
  * factored.                                                                */
 int krr_krill_ws(krr_kernel_kind kind, krr_precision prec, int64_t N, int32_t d, int32_t k,

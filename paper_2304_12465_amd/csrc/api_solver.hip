@@ -266,11 +266,6 @@ int krill_params(Precond& P, krr_kernel_kind kind, krr_precision prec, int64_t N
               (long long)N, d, k, sketch_rows, zeta, m_max);
     return KRR_EINVAL;
   }
-  if (prec == KRR_MIXED) {
-    // the sketch and the restricted products have FP64 and FP32 tiles only
-    set_error("KRILL builds take KRR_FP64 or KRR_FP32 tiles, not KRR_MIXED");
-    return KRR_EINVAL;
-  }
   const int32_t ds = sketch_rows > 0 ? sketch_rows : 2 * k;
   const int32_t z = zeta > 0 ? zeta : (int32_t)std::ceil(std::log((double)k + 1.0));
   if (z > ds) {
@@ -279,7 +274,10 @@ int krill_params(Precond& P, krr_kernel_kind kind, krr_precision prec, int64_t N
   }
   P.type = kKrill;
   P.kind = kind;
-  P.prec = prec;
+  // KRR_MIXED: FP64 restricted products, right-hand side and checks, FP32
+  // sketch tiles
+  P.prec = prec == KRR_MIXED ? KRR_FP64 : prec;
+  P.sketch_prec = prec == KRR_MIXED ? KRR_FP32 : prec;
   P.N = N;
   P.d = d;
   P.k = k;

@@ -360,6 +360,10 @@ int krill_layout(Arena& a, Precond& P) {
   KRR_TRY(carve_points(P.kind, KRR_FP64, k, P.d, a, &P.cpts64));
   if (P.prec != KRR_FP64) KRR_TRY(carve_points(P.kind, P.prec, k, P.d, a, &P.cpts));
   else P.cpts = P.cpts64;
+  if (P.sketch_prec != P.prec) {
+    KRR_TRY(carve_points(P.kind, P.sketch_prec, N, P.d, a, &P.skpts));
+    KRR_TRY(carve_points(P.kind, P.sketch_prec, k, P.d, a, &P.skcpts));
+  }
   P.centers = a.take<int64_t>(k);
   P.H = a.take<double>((size_t)k * k);
   P.C = a.take<double>((size_t)k * k);
@@ -408,6 +412,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
   KrillWork& w = P.kw;
   KRR_TRY(fill_points(P.kind, KRR_FP64, X, nullptr, P.pts64, s));
   if (P.prec != KRR_FP64) KRR_TRY(fill_points(P.kind, P.prec, X, nullptr, P.pts, s));
+  const bool own_sketch = P.sketch_prec != P.prec;
+  if (own_sketch) KRR_TRY(fill_points(P.kind, P.sketch_prec, X, nullptr, P.skpts, s));
 
   // 1. centres
   if (centers) {
@@ -473,6 +479,13 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
                       P.cpts64, s));
   if (P.prec != KRR_FP64)
     KRR_TRY(fill_points(P.kind, P.prec, w.craw, shared_params(P.kind, P.prec, P.pts), P.cpts, s));
+  if (own_sketch)
+    KRR_TRY(fill_points(P.kind, P.sketch_prec, w.craw,
+                        shared_params(P.kind, P.sketch_prec, P.skpts), P.skcpts, s));
+  // the point layouts of the sketch tiles
+  const PointSet& skp = own_sketch ? P.skpts : P.pts;
+  const PointSet& skc = own_sketch ? P.skcpts : P.cpts;
+  const bool sk64 = P.sketch_prec == KRR_FP64;
 
   // 2. H = mu A_SS + N eps tr(A_SS) I  (tr(A_SS) = k: unit diagonal)
   KRR_TRY(kernel_block64(P.kind, P.sigma, P.cpts64, P.cpts64, P.H, k, s));
@@ -526,12 +539,10 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
       int* row_of = reinterpret_cast<int*>(w.entries);
       entry_rows<<<(unsigned)ds, 256, 0, s>>>(w.offs, row_of);
       KRR_LAUNCH_CHECK("entry_rows");
-      KRR_TRY(sketch_gauss_mfma_launch(P.prec == KRR_FP64 ? KRR_FP64 : KRR_FP32, P.sigma,
-                                       P.prec == KRR_FP64 ? P.pts64 : P.pts,
-                                       P.prec == KRR_FP64 ? P.cpts64 : P.cpts, w.offs, w.tmp,
-                                       row_of, ds, izeta, w.B, s));
+      KRR_TRY(sketch_gauss_mfma_launch(sk64 ? KRR_FP64 : KRR_FP32, P.sigma, skp, skc, w.offs,
+                                       w.tmp, row_of, ds, izeta, w.B, s));
     }
-    if (P.prec == KRR_FP64) {
+    if (sk64) {
       const double sc = P.kind == KRR_LAPLACE ? -1.0 / P.sigma : -s_nat;
       void* fn = P.kind == KRR_LAPLACE ? sketch_pick<KRR_LAPLACE, double>(D)
                                        : sketch_pick<KRR_GAUSSIAN, double>(D);
@@ -539,8 +550,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
                           int64_t, int, double, double, double*, const double*, const double*,
                           double);
       reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(
-          P.cpts64.x64, k, P.pts64.x64, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
-          gauss ? P.pts64.xmax64 : nullptr, gauss ? P.cpts64.xmax64 : nullptr, s_nat);
+          skc.x64, k, skp.x64, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
+          gauss ? skp.xmax64 : nullptr, gauss ? skc.xmax64 : nullptr, s_nat);
     } else {
       const float sc = (float)(P.kind == KRR_LAPLACE ? -log2e / P.sigma : -log2e * s_nat);
       void* fn = P.kind == KRR_LAPLACE ? sketch_pick<KRR_LAPLACE, float>(D)
@@ -549,8 +560,8 @@ int krill_build(Precond& P, const double* X, const int64_t* centers, hipStream_t
                           int64_t, int, float, double, double*, const float*, const float*,
                           double);
       reinterpret_cast<Fn>(fn)<<<g, 256, 0, s>>>(
-          P.cpts.x32, k, P.pts.x32, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
-          gauss ? P.pts.xmax32 : nullptr, gauss ? P.cpts.xmax32 : nullptr, s_nat);
+          skc.x32, k, skp.x32, w.offs, w.tmp, ds, rows_per_wg, sc, izeta, w.B,
+          gauss ? skp.xmax32 : nullptr, gauss ? skc.xmax32 : nullptr, s_nat);
     }
     KRR_LAUNCH_CHECK("sketch_apply");
   }

@@ -120,6 +120,10 @@ struct Precond {
   double shift = 0.0;             // N eps tr(A_SS)
   int64_t* centers = nullptr;     // device, k
   PointSet cpts64, cpts;          // centres in both layouts
+  // precision of the sketch tiles: prec, or FP32 under FP64 products (a
+  // KRR_MIXED build), which then keeps FP32 layouts of X and the centres
+  krr_precision sketch_prec = KRR_FP64;
+  PointSet skpts, skcpts;
   double* H = nullptr;            // k x k: mu A_SS + shift I
   double* C = nullptr;            // k x k: lower Cholesky factor of P = B^T B + H
   double* Linv = nullptr;         // k x k: L^{-1} (the apply is two dense products)

@@ -61,8 +61,9 @@ def test_centres_and_sketch_bit_exact():
     np.testing.assert_array_equal(signs, s_o.astype(np.int32))
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-5)])
 def test_sketch_H_and_factor(prec, tol):
+    # prec 2 (KRR_MIXED): the sketch on FP32 tiles, H and the factor in FP64
     p = small()
     P = build(p, prec)
     k = p.centers
@@ -77,6 +78,14 @@ def test_sketch_H_and_factor(prec, tol):
         L = B().krill_export(P, 4, (k, k), torch.float64).cpu().numpy()
         assert np.all(np.triu(L, 1) == 0)
         np.testing.assert_allclose(L @ L.T, kr.P, rtol=0, atol=1e-10 * np.abs(kr.P).max())
+    if prec == 2:
+        # P = B^T B + H from the FP32-tile B: with |dB| <= E = tol |Phi||A(:,S)|,
+        # |dP| <= 2 |B|^T E + E^T E entrywise, plus the factorisation's rounding
+        L = B().krill_export(P, 4, (k, k), torch.float64).cpu().numpy()
+        assert np.all(np.triu(L, 1) == 0)
+        E = tol * (np.abs(kr.Phi) @ np.abs(kr.AnS))
+        dP = 2.0 * np.abs(kr.B).T @ E + E.T @ E + 1e-10 * np.abs(kr.P).max()
+        assert np.all(np.abs(L @ L.T - kr.P) <= dP), np.max(np.abs(L @ L.T - kr.P) / dP)
 
 
 @pytest.mark.parametrize("n,k", [(6000, 1100), (8000, 2100)])
@@ -105,7 +114,7 @@ def test_factor_and_apply_past_one_outer_block(n, k):
     assert rel <= 100 * k * 2.0 ** -52 * kap, (rel, kap)
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 4e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 4e-5), (2, 1e-12)])
 def test_restricted_operator(prec, tol):
     p = small()
     P = build(p, prec, m_max=2)
@@ -135,6 +144,41 @@ def test_restricted_solve_matches_oracle_fp64():
     rel = np.linalg.norm(fit - fit_o) / np.linalg.norm(fit_o)
     assert rel <= 1e-6, rel
     assert abs(info["iters"] - int(io["iters"][0])) <= 1
+
+
+def test_restricted_solve_mixed_sketch():
+    # KRR_MIXED: the FP64 build's restricted products, right-hand side and
+    # checks, with the sketch on FP32 tiles.  The system is the FP64 one; only
+    # the preconditioner differs (by the sketch's FP32 error).  So the oracle's
+    # FP64 true residual of the returned beta meets 10 tol, the library's
+    # true residual is the oracle's to within the FP64 tile error, the M-norm
+    # distance to the oracle's solution is within (||b - M beta|| +
+    # ||b - M x_o||) / sqrt(lambda_min(M)), and the iteration count stays
+    # within 2 of the FP64 build's.
+    p = small(n=3000, k=150)
+    P = build(p, 2)
+    P64 = build(p, 0)
+    S = np.array(P.pivots())
+    assert P64.pivots() == P.pivots()
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    beta, info = P.solve(T(p.Y), p.tol, max_iter=200)
+    _, info64 = P64.solve(T(p.Y), p.tol, max_iter=200)
+    assert info["converged"] and abs(info["iters"] - info64["iters"]) <= 2, (info, info64)
+    beta = beta.cpu().numpy()
+    b = kr.rhs(p.Y)
+    M = kr.restricted_matrix()
+    bn = np.linalg.norm(b)
+    r_true = np.linalg.norm(b - M @ beta) / bn
+    assert r_true <= 10 * p.tol, r_true
+    Mabs = np.abs(kr.AnS).T @ np.abs(kr.AnS) + np.abs(kr.H)
+    err = (3e-12 * np.linalg.norm(Mabs @ np.abs(beta))
+           + 1e-12 * np.linalg.norm(np.abs(kr.AnS).T @ np.abs(p.Y))) / bn
+    assert abs(info["relres_true"] - r_true) <= err + 1e-6 * r_true, (info, r_true, err)
+    xo, io = OPCG.pcg(kr.product, kr.precondition, b, p.tol, 200)
+    e = (beta - xo)[:, 0]
+    bound = (r_true * bn + np.linalg.norm(b - M @ xo)) / np.sqrt(np.linalg.eigvalsh(M).min())
+    assert np.sqrt(e @ M @ e) <= 1.01 * bound
 
 
 def test_restricted_solve_fp32_tiles_within_derived_bounds():
@@ -338,7 +382,7 @@ def small_laplace(n=2000, k=100):
     return p
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5), (2, 2e-5)])
 def test_laplace_sketch_H_factor_and_operator(prec, tol):
     # KRILL with the Laplace kernel: B = Phi A(:,S) (direct differences), H and
     # L against the oracle, then the restricted operator (FP32: the quantised
@@ -363,7 +407,7 @@ def test_laplace_sketch_H_factor_and_operator(prec, tol):
     got = P.operator(T(V)).cpu().numpy()
     ref = kr.product(V)
     scale = np.abs(kr.AnS).T @ (np.abs(kr.AnS) @ np.abs(V)) + np.abs(kr.H) @ np.abs(V)
-    otol = 1e-12 if prec == 0 else 4e-5
+    otol = 4e-5 if prec == 1 else 1e-12  # MIXED (2): FP64 restricted products
     assert np.all(np.abs(got - ref) <= otol * scale), np.max(np.abs(got - ref) / scale)
 
 
