@@ -26,7 +26,8 @@ FLAGS = [
 # Per-file extra flags: the MFMA tiles keep MFMA results in VGPRs (no
 # accumulator-register round trips between the contraction and the VALU work).
 EXTRA = {"product_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
-         "product_gauss_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+         "product_gauss_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "sketch_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src):

@@ -189,29 +189,50 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
     for (int ct = 0; ct < NT; ++ct) {
       if (ct + 1 < NT) distance(ct + 1, dot[(ct + 1) & 1]);
       // dot[rt][t] = y_col . c_li - ||c_li||^2 / 2 for col = ct*16 + col(t, g)
-      T ex[kSkRT][4];
+      // ex: the kernel values (FP64: signed).  FP32: w is the signed sum of
+      // the lane's four columns (one multiply, then a chain of multiply-adds
+      // in a fixed order) for a tile that stays within the current row; the
+      // FP64 tile keeps the signed values and adds them pairwise (the chain's
+      // extra registers would spill at 128 VGPRs)
+      constexpr bool kChain = std::is_same<T, float>::value;
+      T ex[kSkRT][4], w[kSkRT];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int col = ct * 16 + GT<T>::col(t, g);
         const T ay = sAy[col], sg = sSg[col];
 #pragma unroll
-        for (int rt = 0; rt < kSkRT; ++rt)
-          ex[rt][t] = sg * GT<T>::ex(fma_g(dot[ct & 1][rt][t], s2, ay), etab);
+        for (int rt = 0; rt < kSkRT; ++rt) {
+          const T e = GT<T>::ex(fma_g(dot[ct & 1][rt][t], s2, ay), etab);
+          if constexpr (kChain) {
+            ex[rt][t] = e;
+            w[rt] = t == 0 ? sg * e : fma_g(sg, e, w[rt]);
+          } else {
+            ex[rt][t] = sg * e;
+          }
+        }
       }
       const int64_t rf = sRow[ct * 16], rl = sRow[ct * 16 + 15];
       if (rf == rc && rl == rc) {
 #pragma unroll
-        for (int rt = 0; rt < kSkRT; ++rt)
-          cur[rt] += (double)((ex[rt][0] + ex[rt][1]) + (ex[rt][2] + ex[rt][3]));
+        for (int rt = 0; rt < kSkRT; ++rt) {
+          if constexpr (kChain)
+            cur[rt] += (double)w[rt];
+          else
+            cur[rt] += (double)((ex[rt][0] + ex[rt][1]) + (ex[rt][2] + ex[rt][3]));
+        }
       } else {
         // the tile reaches into later rows: finish them in order
         int64_t rho = rc;
         while (true) {
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (sRow[ct * 16 + GT<T>::col(t, g)] == rho)
+          for (int t = 0; t < 4; ++t) {
+            const int col = ct * 16 + GT<T>::col(t, g);
+            if (sRow[col] == rho) {
+              const T sg = kChain ? sSg[col] : T(1);
 #pragma unroll
-              for (int rt = 0; rt < kSkRT; ++rt) cur[rt] += (double)ex[rt][t];
+              for (int rt = 0; rt < kSkRT; ++rt) cur[rt] += (double)(sg * ex[rt][t]);
+            }
+          }
           if (rho == rl) break;
           flush(rho);
           int64_t nx = rl;  // next row present in this tile
