@@ -86,9 +86,13 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
   // needs no per-element checks; a K-major operand takes that path when its
   // whole tile is in range.  The last step of a K range, and K-major tiles
   // at the edge, clamp every address instead.
-  // row-major operand: 64 rows x kKStep k; K-major operand: kKStep k x 64 rows
+  // row-major operand: 64 rows x kKStep k, kUE consecutive k per thread;
+  // K-major operand: lane l of wave w takes row l at k = kUE w .. kUE w + kUE
+  // - 1, so each load instruction reads 64 consecutive values and each LDS
+  // store writes 64 consecutive rows of one k (consecutive banks; the
+  // transposing store of kUE rows per thread hit every fourth bank)
   const int ar = tid >> 2, ak = (tid & 3) * kUE;
-  const int kk = tid / (64 / kUE), mn = (tid % (64 / kUE)) * kUE;
+  const int km = tid & 63, kq = (tid >> 6) * kUE;
   // split K: this workgroup covers [kb, ke); the bounds checks below use ke
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
@@ -125,7 +129,7 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
             ra[r][u] = arow[r][k0 + ak + u];
             okm |= (aok[r] ? 1u : 0u) << (kUE * r + u);
           } else {
-            ra[r][u] = A[(k0 + kk) * lda + m0 + 64 * r + mn + u];
+            ra[r][u] = A[(k0 + kq + u) * lda + m0 + 64 * r + km];
             okm |= 1u << (kUE * r + u);
           }
         }
@@ -137,7 +141,7 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
             rb[r][u] = brow[r][k0 + ak + u];
             okm |= (bok[r] ? 1u : 0u) << (16 + kUE * r + u);
           } else {
-            rb[r][u] = B[(k0 + kk) * ldb + n0 + 64 * r + mn + u];
+            rb[r][u] = B[(k0 + kq + u) * ldb + n0 + 64 * r + km];
             okm |= 1u << (16 + kUE * r + u);
           }
         }
@@ -153,8 +157,8 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
           gm = m0 + 64 * r + ar;
           gk = k0 + ak + u;
         } else {
-          gm = m0 + 64 * r + mn + u;
-          gk = k0 + kk;
+          gm = m0 + 64 * r + km;
+          gk = k0 + kq + u;
         }
         const bool ok = gm < M && gk < ke;
         const int64_t cm = gm < M ? gm : M - 1, ck = gk < ke ? gk : ke - 1;
@@ -170,8 +174,8 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
           gn = n0 + 64 * r + ar;
           gk = k0 + ak + u;
         } else {
-          gn = n0 + 64 * r + mn + u;
-          gk = k0 + kk;
+          gn = n0 + 64 * r + km;
+          gk = k0 + kq + u;
         }
         const bool ok = gn < N && gk < ke;
         const int64_t cn = gn < N ? gn : N - 1, ck = gk < ke ? gk : ke - 1;
@@ -188,7 +192,7 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
         if (!AT)
           As[buf][64 * r + ar][ak + u] = v;
         else
-          As[buf][64 * r + mn + u][kk] = v;
+          As[buf][64 * r + km][kq + u] = v;
       }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -198,7 +202,7 @@ void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double
         if (BT)
           Bs[buf][64 * r + ar][ak + u] = v;
         else
-          Bs[buf][64 * r + mn + u][kk] = v;
+          Bs[buf][64 * r + km][kq + u] = v;
       }
   };
   int cur = 0;
