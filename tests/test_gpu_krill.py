@@ -88,11 +88,12 @@ def test_sketch_H_and_factor(prec, tol):
         assert np.all(np.abs(L @ L.T - kr.P) <= dP), np.max(np.abs(L @ L.T - kr.P) / dP)
 
 
-@pytest.mark.parametrize("n,k", [(6000, 1100), (8000, 2100)])
+@pytest.mark.parametrize("n,k", [(6000, 1024), (6000, 1100), (8000, 2100)])
 def test_factor_and_apply_past_one_outer_block(n, k):
-    # k = 1,100 and 2,100 centres: the Cholesky factor and the inverse of L
-    # are built in two levels of blocks (outer steps of 512 with a ragged
-    # last step), so the outer panel solves and trailing updates all run;
+    # k = 1,024, 1,100 and 2,100 centres: the Cholesky factor and the inverse
+    # of L are built in two levels of blocks (outer steps of 512, the last one
+    # whole or ragged, on two streams), so the outer panel solves and
+    # trailing updates all run;
     # at k = 2,100 B^T B runs on 128 x 128 tiles.  sigma = 0.3 keeps kappa(P)
     # near 1e4-1e5, so the apply bound below is tight.
     p = small(n=n, k=k)
