@@ -348,8 +348,11 @@ def test_full_size_restricted_products_sampled(prec):
     assert np.all(err <= tol * scale), (err / scale).max()
 
 
-def test_full_size_restricted_solve_fp64_oracle_residual():
-    # The headline configuration with FP64 tiles.  The restricted residual
+@pytest.mark.parametrize("prec", [2, 0])
+def test_full_size_restricted_solve_fp64_oracle_residual(prec):
+    # The headline configuration (KRR_MIXED: FP64 restricted products with the
+    # sketch on FP32 tiles) and the all-FP64 build; both solve the same FP64
+    # system, only their preconditioners differ.  The restricted residual
     # b - M beta, M = A(S,:)A(:,S) + H, is re-checked on 32 sampled centres:
     # the oracle forms their rows of A(S,:) against all 2,000,000 points (for
     # b = A(S,:)y and for A(S,:) t), t = A(:,S) beta comes from the FP64
@@ -357,7 +360,7 @@ def test_full_size_restricted_solve_fp64_oracle_residual():
     # H = mu A_SS + N eps tr(A_SS) I from the oracle's kernel.
     p = synth.c4()
     N, k = p.X.shape[0], p.centers
-    P = build(p, 0)
+    P = build(p, prec)
     beta, info = P.solve(T(p.Y), p.tol, max_iter=100)
     assert info["converged"] and info["relres_true"] <= 10 * p.tol, info
     beta_h = beta.cpu().numpy()
