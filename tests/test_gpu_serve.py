@@ -57,6 +57,36 @@ def test_alone_equals_in_the_mix_bitwise():
         assert np.array_equal(beta.cpu().numpy(), ba)
 
 
+def test_fp64_requests_carrying_x_alone_equal_in_the_mix():
+    # FP64 requests above the burst size: each carries x beside p in the step
+    # predicted to converge (its products then give the exit check), on its
+    # own schedule; stepped together their products share launches.  Every
+    # request's solution, iteration count, product count and true residual
+    # are bitwise those it gets alone.
+    specs = [(5000, 8, 0, 1), (6000, 16, 0, 3), (4500, 16, 1, 2)]
+    probs = []
+    for i, (n, d, kind, m) in enumerate(specs):
+        req = synth.Request(i, 0.0, n, d, kind, m, min(200, n // 20), 7100 + i)
+        probs.append(synth.c5_problem(req))
+    alone = []
+    for p in probs:
+        P = build(p, 0)
+        beta, info = P.solve(T(p.Y), 1e-8, 400)
+        assert info["converged"] and info["products"] <= info["iters"] + 1, info
+        alone.append((beta.cpu().numpy(), info))
+    Ps = [build(p, 0) for p in probs]
+    Ss = [B().Solve(P, T(p.Y), 1e-8, 400) for P, p in zip(Ps, probs)]
+    live = list(Ss)
+    while live:
+        st = B().solve_step(live)
+        live = [s for s, v in zip(live, st) if v == 0]
+    for S, (ba, ia) in zip(Ss, alone):
+        beta, info = S.end()
+        for key in ("iters", "products", "relres_true", "converged"):
+            assert info[key] == ia[key], (key, info, ia)
+        assert np.array_equal(beta.cpu().numpy(), ba)
+
+
 def test_failing_request_is_isolated():
     probs = problems()[:3]
     Ps = [build(p, prec) for p, prec in probs]
