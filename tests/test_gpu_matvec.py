@@ -315,3 +315,31 @@ def test_laplace_quantised_wide_range():
     delta = dpad * rng_ / ((2 ** qbits - 1) * sigma) + 4 * 2 ** -24
     tol = delta + 257 * 2 ** -24
     assert np.all(np.abs(W - ref) <= tol * scale), (np.max(np.abs(W - ref) / scale), tol)
+
+
+def test_tile_timing_by_vector_count():
+    # krr_timing_read_vectors: every recorded tile launch, and those of the
+    # Gaussian matrix-core tile carrying exactly the given number of vectors
+    # (the roofline's kernel); the record is cleared by the read
+    b = B()
+    g = np.random.default_rng(17)
+    X = torch.from_numpy(g.standard_normal((3000, 16))).to("cuda:0")
+    V1 = torch.from_numpy(g.standard_normal((3000, 1))).to("cuda:0")
+    V2 = torch.from_numpy(g.standard_normal((3000, 2))).to("cuda:0")
+    b.kernel_matvec(0, 4.0, b.FP64, X, X, V1)
+    torch.cuda.synchronize()
+    b.timing_read()
+    b.timing_enable(True)
+    for _ in range(3):
+        b.kernel_matvec(0, 4.0, b.FP64, X, X, V1)
+    for _ in range(2):
+        b.kernel_matvec(0, 4.0, b.FP64, X, X, V2)
+    b.kernel_matvec(1, 4.0, b.FP64, X, X, V1)  # Laplace: another tile, no vector tag
+    torch.cuda.synchronize()
+    b.timing_enable(False)
+    ms, n, ms1, n1 = b.timing_read_vectors(1)
+    assert n == 6 and n1 == 3, (n, n1)
+    assert 0.0 < ms1 < ms
+    assert b.timing_read() == (0.0, 0)
+    with pytest.raises(b.KrrError):
+        b.timing_read_vectors(-1)
