@@ -270,8 +270,9 @@ void krr_precond_free(krr_precond P);
  * predicted within 5 tol (and the last step allowed) also multiplies x in
  * the same launches; if it ends the solve, its true residual
  * (b - M x) - alpha (M p) is the exit check and no further product runs.
- * FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG restarted
- * from the FP64 true residual, each round run to tol/10 on its recursive
+ * (A KRR_MIXED KRILL build runs FP64 restricted products: the FP64 rules
+ * apply.)  FP32 / MIXED tiles: up to 6 rounds of iterative refinement (CG
+ * restarted from the FP64 true residual, each round run to tol/10 on its recursive
  * residual, or to tol/2 where the previous round's contraction puts the
  * operator's share of the coming round below tol/10; MIXED full-data rounds
  * also stop at the operator's floor, seen on an FP64 residual of 1,024
