@@ -5,8 +5,16 @@
 // Orientation: the centres are the rows of an MFMA tile (held in registers
 // as the B operand, 128 per workgroup), the nonzeros of a range of sketch
 // rows are its columns, 64 at a time, with their points gathered into LDS.
-// The distance contraction runs on v_mfma_f64_16x16x4f64 /
-// v_mfma_f32_16x16x4f32 exactly as in the product tiles; instead of a
+// The distance contraction runs on v_mfma_f64_16x16x4f64 as in the FP64
+// product tile.  FP32 points (padded dimension 8, 16, 24 or 32) run it on
+// v_mfma_f32_16x16x32_bf16 instead: every coordinate is split into three
+// bf16 slices, x = h + m + l (round to nearest at each step; the three
+// slices hold the FP32 value exactly), and the six slice products of
+// weight down to 2^-16 (hh, hm, mh, hl, lh, mm) are contracted with FP32
+// accumulation; each is exact in FP32, and the three dropped ones are below
+// 2^-24 |x||y| together, under the FP32 contraction's own rounding.  At
+// d = 16 that is three 16-cycle MFMAs per 256 entries against four 32-cycle
+// FP32 ones.  Other padded dimensions use v_mfma_f32_16x16x4f32.  Instead of a
 // product with V, each lane adds the exponentials of its columns (signed)
 // into the running sum of the current sketch row, and a row's sum is
 // completed across the four lanes that share a centre when the nonzeros
@@ -24,6 +32,46 @@ namespace {
 
 constexpr int kSkRT = 2;     // 16-centre tiles per wave (128 centres per workgroup)
 constexpr int kSkCols = 64;  // nonzeros per LDS chunk (four 16-column tiles)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 points with D a multiple of 8 up to 32 take the three-slice bf16
+// contraction.
+template <typename T, int D>
+constexpr bool sk_split() {
+  return std::is_same<T, float>::value && D % 8 == 0 && D <= 32;
+}
+// The six slice products: slice of the point (A operand) and of the centre
+// (B operand) of product p; h = 0, m = 1, l = 2.
+__device__ __forceinline__ int sk_yslice(int p) { return p == 2 || p == 5 ? 1 : p == 4 ? 2 : 0; }
+__device__ __forceinline__ int sk_xslice(int p) { return p == 1 || p == 5 ? 1 : p == 3 ? 2 : 0; }
+// MFMA steps (K = 32 each) over the 6 D slice coordinates
+template <int D>
+constexpr int sk_steps() {
+  return (6 * D + 31) / 32;
+}
+// LDS row pitch (bf16) of a chunk's split points: 3 D, plus 8 when 3 D / 8
+// is even, so the 16-byte reads of 8 consecutive rows fall in distinct banks
+template <int D>
+constexpr int sk_pitch() {
+  return (3 * D / 8) % 2 ? 3 * D : 3 * D + 8;
+}
+
+// Two coordinates -> their h, m and l bf16 slices, each pair packed in a
+// 32-bit word (low half: a).  Each remainder is exact in FP32.
+__device__ __forceinline__ void split3_pair(float a, float b, uint32_t& h, uint32_t& m,
+                                            uint32_t& l) {
+  h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+  a -= __builtin_bit_cast(float, h << 16);
+  b -= __builtin_bit_cast(float, h & 0xffff0000u);
+  m = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+  a -= __builtin_bit_cast(float, m << 16);
+  b -= __builtin_bit_cast(float, m & 0xffff0000u);
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
 
 template <typename T>
 struct SketchJob {
@@ -61,8 +109,16 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   constexpr int KS = D / 4;
   constexpr int NT = kSkCols / 16;
   constexpr int kY = kSkCols * D / 256;
+  constexpr bool kSplit = sk_split<T, D>();
+  constexpr int NC = sk_steps<D>();        // bf16 MFMA steps
+  constexpr int PY = sk_pitch<D>();
+  constexpr int kSegs = kSkCols * D / 4;   // 4-coordinate segments of a chunk's points
+  constexpr int kSegPT = (kSegs + 255) / 256;
   __shared__ double etab[GT<T>::kTable];  // FP64 exp table (one unused entry for FP32)
-  __shared__ T sY[kSkCols][D + 1];
+  // a chunk's points: their values, or (kSplit) their bf16 slices h | m | l
+  // per row; the form not used keeps one element
+  __shared__ T sY[kSplit ? 1 : kSkCols][D + 1];
+  __shared__ __attribute__((aligned(16))) __bf16 sYb[kSplit ? kSkCols : 1][PY];
   __shared__ T sAy[kSkCols];
   __shared__ T sSg[kSkCols];
   __shared__ int sRow[kSkCols];
@@ -76,14 +132,38 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   const int g = lane >> 4, li = lane & 15;
   const int64_t k = J.k;
   const int64_t c0 = (int64_t)blockIdx.x * (4 * 16 * kSkRT) + wave * (16 * kSkRT);
-  T xb[kSkRT][KS];  // B operand: centre c0 + 16 rt + li, coordinates 4 ks + g
+  T xb[kSkRT][kSplit ? 1 : KS];  // B operand: centre c0 + 16 rt + li, coordinates 4 ks + g
+  // kSplit: K index 32 st + 8 g + e of step st is coordinate d0 + e of slice
+  // product p, with 8-coordinate group G = 4 st + g, p = G / (D/8) and d0 =
+  // 8 (G % (D/8)); groups with p >= 6 pad the last step (zero centre slices)
+  bf16x8 xbb[kSkRT][kSplit ? NC : 1];
+  int aoff[kSplit ? NC : 1];  // LDS offset of the lane's point slice in a row
   acc_t cinit[kSkRT];
 #pragma unroll
   for (int rt = 0; rt < kSkRT; ++rt) {
     int64_t c = c0 + rt * 16 + li;
     if (c > k - 1) c = k - 1;
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) xb[rt][ks] = J.cc[c * D + 4 * ks + g];
+      for (int st = 0; st < NC; ++st) {
+        const int G = 4 * st + g, p = G / (D / 8), d0 = 8 * (G % (D / 8));
+        u32x4 w = {0u, 0u, 0u, 0u};
+        if (p < 6) {
+          const int xs = sk_xslice(p);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            uint32_t h, m, l;
+            split3_pair(J.cc[c * D + d0 + 2 * e], J.cc[c * D + d0 + 2 * e + 1], h, m, l);
+            w[e] = xs == 0 ? h : xs == 1 ? m : l;
+          }
+        }
+        xbb[rt][st] = __builtin_bit_cast(bf16x8, w);
+        if (rt == 0) aoff[st] = p < 6 ? sk_yslice(p) * D + d0 : 0;
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) xb[rt][ks] = J.cc[c * D + 4 * ks + g];
+    }
     const T h = T(-0.5) * J.cn[c];
     cinit[rt] = acc_t{h, h, h, h};
   }
@@ -123,14 +203,25 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
     const int64_t e = base + tid;
     return J.entries[e < ee ? e : ee - 1];
   };
-  T y_st[kY];
+  T y_st[kSplit ? 1 : kY];
+  f32x4 y4_st[kSplit ? kSegPT : 1];  // kSplit: coordinates 4 part .. 4 part + 3 of a point
   T ay_st = T(0), sg_st = T(0);
   int row_st = 0;
   auto stage_points = [&](int64_t base, int64_t code) {
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int q = 0; q < kY; ++q) {
-      const int idx = tid + q * 256;
-      y_st[q] = J.yc[sJn[idx / D] * D + idx % D];
+      for (int q = 0; q < kSegPT; ++q) {
+        const int seg = tid + q * 256;
+        if (kSegs % 256 == 0 || seg < kSegs)
+          y4_st[q] = *reinterpret_cast<const f32x4*>(J.yc + sJn[seg / (D / 4)] * D +
+                                                      4 * (seg % (D / 4)));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kY; ++q) {
+        const int idx = tid + q * 256;
+        y_st[q] = J.yc[sJn[idx / D] * D + idx % D];
+      }
     }
     if (tid < kSkCols) {
       const int64_t e = base + tid;
@@ -155,10 +246,26 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   int64_t rc = r0;  // row whose sum is being formed (uniform)
   for (int64_t e0 = eb; e0 < ee; e0 += kSkCols) {
     __syncthreads();  // the previous chunk's LDS reads are done
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int q = 0; q < kY; ++q) {
-      const int idx = tid + q * 256;
-      sY[idx / D][idx % D] = y_st[q];
+      for (int q = 0; q < kSegPT; ++q) {
+        const int seg = tid + q * 256;
+        if (kSegs % 256 == 0 || seg < kSegs) {
+          uint32_t h0, m0, l0, h1, m1, l1;
+          split3_pair(y4_st[q][0], y4_st[q][1], h0, m0, l0);
+          split3_pair(y4_st[q][2], y4_st[q][3], h1, m1, l1);
+          __bf16* row = &sYb[seg / (D / 4)][4 * (seg % (D / 4))];
+          *reinterpret_cast<uint2*>(row) = make_uint2(h0, h1);
+          *reinterpret_cast<uint2*>(row + D) = make_uint2(m0, m1);
+          *reinterpret_cast<uint2*>(row + 2 * D) = make_uint2(l0, l1);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kY; ++q) {
+        const int idx = tid + q * 256;
+        sY[idx / D][idx % D] = y_st[q];
+      }
     }
     if (tid < kSkCols) {
       sAy[tid] = ay_st;
@@ -174,15 +281,27 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
     }
     acc_t dot[2][kSkRT];
     auto distance = [&](int ct, acc_t* dv) {
-      T ya[KS];  // A operand: point of nonzero ct*16 + li, coordinates 4 ks + g
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
 #pragma unroll
       for (int rt = 0; rt < kSkRT; ++rt) dv[rt] = cinit[rt];
+      if constexpr (kSplit) {
+        bf16x8 ya[NC];  // A operand: slices of the point of nonzero ct*16 + li
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+        for (int st = 0; st < NC; ++st)
+          ya[st] = *reinterpret_cast<const bf16x8*>(&sYb[ct * 16 + li][aoff[st]]);
 #pragma unroll
-        for (int rt = 0; rt < kSkRT; ++rt) dv[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dv[rt]);
+        for (int st = 0; st < NC; ++st)
+#pragma unroll
+          for (int rt = 0; rt < kSkRT; ++rt)
+            dv[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[st], xbb[rt][st], dv[rt], 0, 0, 0);
+      } else {
+        T ya[KS];  // A operand: point of nonzero ct*16 + li, coordinates 4 ks + g
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+          for (int rt = 0; rt < kSkRT; ++rt) dv[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dv[rt]);
+      }
     };
     distance(0, dot[0]);
 #pragma unroll

@@ -88,6 +88,21 @@ def test_sketch_H_and_factor(prec, tol):
         assert np.all(np.abs(L @ L.T - kr.P) <= dP), np.max(np.abs(L @ L.T - kr.P) / dP)
 
 
+@pytest.mark.parametrize("d", [3, 7, 16, 19, 23, 30])
+def test_fp32_sketch_over_padded_dimensions(d):
+    # FP32 sketch tiles at padded dimensions 4, 8, 16, 20, 24 and 32: the
+    # multiples of 8 contract three bf16 slices per coordinate on the bf16
+    # matrix cores, 4 and 20 run the FP32 ones; both within the FP32 tiles'
+    # entry bound 2e-5 |Phi||A(:,S)| of the oracle's B
+    p = synth.c4(n=3000, k=300, d=d)
+    P = build(p, 1)
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, np.array(P.pivots()), sketch_rows=p.sketch_rows,
+                   zeta=p.zeta, seed=p.algo_seed)
+    Bg = B().krill_export(P, 2, (p.sketch_rows, p.centers), torch.float64).cpu().numpy()
+    bound = 2e-5 * (np.abs(kr.Phi) @ np.abs(kr.AnS)) + 1e-300
+    assert np.all(np.abs(Bg - kr.B) <= bound), np.max(np.abs(Bg - kr.B) / bound)
+
+
 @pytest.mark.parametrize("n,k", [(6000, 1024), (6000, 1100), (8000, 2100)])
 def test_factor_and_apply_past_one_outer_block(n, k):
     # k = 1,024, 1,100 and 2,100 centres: the Cholesky factor and the inverse
