@@ -330,35 +330,44 @@ void launch_gemm(TileShape ts, dim3 grid, hipStream_t s, int64_t M, int64_t N, i
 
 constexpr int kNb = 64;  // block size of the blocked factorisation and solves
 
-// Cholesky of one nb x nb diagonal block (nb <= kNb), right-looking, in
-// one wave: lane i keeps row i in registers (the loops are unrolled, so
-// every index is a constant); the multipliers of column k pass through LDS
-// to all lanes.  Whole rows are read and written: the entries above the
-// diagonal start with whatever A holds there and collect values of no
-// meaning, but no entry on or below the diagonal ever reads one (row i's
-// entry j <= i takes the multipliers of columns k < j from rows i and j).
-// Rows and columns past nb stay zero and take pivot 1.  A non-positive
-// pivot is replaced by 1 so the sweep stays finite; `info` reports the
-// first one.
-__global__ __launch_bounds__(64) void potrf_diag(double* __restrict__ A, int64_t lda, int nb,
-                                                 int64_t col0, int* __restrict__ info) {
+// Cholesky of one nb x nb diagonal block (nb <= kNb), right-looking, one
+// quad of lanes per row (256 threads): lane c of row i keeps entries
+// j = 4 u + c (u < kNb / 4) in registers (the loops are unrolled, so every
+// index is a constant).  Step k: every lane forms y = 1 / sqrt(p) of the
+// pivot p (passed through LDS), the lane holding entry (i, k) stores the
+// multiplier l_i = A(i, k) y into LDS, and after the barrier every lane
+// updates its entries j > k by A(i, j) -= l_i l_j; the lane holding (k + 1,
+// k + 1) then passes the next pivot.  Each entry takes the same multiply-adds
+// in the same order as with one lane per row, at a quarter of the
+// multiply-adds per lane per step.  Whole rows are read and written: the
+// entries above the diagonal start with whatever A holds there and collect
+// values of no meaning, but no entry on or below the diagonal ever reads one
+// (entry (i, j), j <= i, takes the multipliers of columns k < j from rows i
+// and j).  Rows and columns past nb stay zero and take pivot 1.  A
+// non-positive pivot is replaced by 1 so the sweep stays finite; `info`
+// reports the first one.
+__global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ A, int64_t lda, int nb,
+                                                  int64_t col0, int* __restrict__ info) {
+  constexpr int kU = kNb / 4;
   __shared__ double colv[kNb];
-  const int i = threadIdx.x;
+  __shared__ double piv;
+  const int i = threadIdx.x >> 2, c = threadIdx.x & 3;
   const bool row = i < nb;
-  double t[kNb];
+  double t[kU];
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) t[j] = (row && j < nb) ? A[i * lda + j] : 0.0;
+  for (int u = 0; u < kU; ++u) t[u] = (row && 4 * u + c < nb) ? A[i * lda + 4 * u + c] : 0.0;
+  if (threadIdx.x == 0) piv = t[0];
+  __syncthreads();
   int bad = 0;
 #pragma unroll
   for (int k = 0; k < kNb; ++k) {
     __builtin_amdgcn_sched_barrier(0);  // one column at a time: bounds the live LDS reads
-    const double p = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(t[k]), k),
-                                      __builtin_amdgcn_readlane(__double2loint(t[k]), k));
+    const double p = piv;
     // y = 1 / sqrt(p): v_rsq_f64 and two Newton steps (each doubles the
     // correct bits), so the column takes one multiply instead of a square
-    // root and a division on the step's dependent chain (the 64-wide block
-    // 26.5 -> 22.2 us); row k gets p y = sqrt(p) to within an ulp or two.
-    // Pivots below 2^-960 (none in a well-posed factor) take the square root.
+    // root and a division on the step's dependent chain; row k gets p y =
+    // sqrt(p) to within an ulp or two.  Pivots below 2^-960 (none in a
+    // well-posed factor) take the square root.
     double y = 1.0;
     if (k < nb) {
       if (p >= 0x1p-960) {
@@ -372,20 +381,25 @@ __global__ __launch_bounds__(64) void potrf_diag(double* __restrict__ A, int64_t
         bad = (int)(col0 + k + 1);
       }
     }
-    const double l = t[k] * y;
-    t[k] = l;
-    colv[i] = l;
+    if (c == (k & 3)) {
+      const double l = t[k >> 2] * y;
+      t[k >> 2] = l;
+      colv[i] = l;
+    }
     __syncthreads();
+    const double li = colv[i];
 #pragma unroll
-    for (int j = k + 1; j < kNb; ++j) t[j] = __builtin_fma(-l, colv[j], t[j]);
+    for (int u = k >> 2; u < kU; ++u)
+      if (4 * u + c > k) t[u] = __builtin_fma(-li, colv[4 * u + c], t[u]);
+    if (k + 1 < kNb && i == k + 1 && c == ((k + 1) & 3)) piv = t[(k + 1) >> 2];
     __syncthreads();
   }
   if (row) {
 #pragma unroll
-    for (int j = 0; j < kNb; ++j)
-      if (j < nb) A[i * lda + j] = t[j];
+    for (int u = 0; u < kU; ++u)
+      if (4 * u + c < nb) A[i * lda + 4 * u + c] = t[u];
   }
-  if (i == 0 && bad && *info == 0) *info = bad;
+  if (threadIdx.x == 0 && bad && *info == 0) *info = bad;
 }
 
 // A lower-triangular nb x nb block (nb <= kNb) staged in LDS, padded to
@@ -955,7 +969,7 @@ int potrf_block(int64_t n, double* A, int64_t lda, int* info, int64_t col0, hipS
   for (int64_t k = 0; k < n; k += kNb) {
     const int nb = (int)std::min<int64_t>(kNb, n - k);
     double* Akk = A + k * lda + k;
-    potrf_diag<<<1, 64, 0, s>>>(Akk, lda, nb, col0 + k, info);
+    potrf_diag<<<1, 256, 0, s>>>(Akk, lda, nb, col0 + k, info);
     KRR_LAUNCH_CHECK("potrf_diag");
     const int64_t rest = n - k - nb;
     if (rest > 0) {
