@@ -217,10 +217,16 @@ def c3_leg(a, b, torch, synth, ctx=None, solve=True):
                             "mfma_tflops_executed": rate * mfma_flops / 1e12,
                             "frac_of_bf16_peak_executed": rate * mfma_flops / 1e12 / BF16_PEAK_TFLOPS}
     ms32 = _product_rate(b, torch, p.kind, p.sigma, b.FP32, X, m, launches=2)
-    f32_flops = 2 * 32 + 2 * 16   # distance (K = 32) and E.V (16 columns) on the f32 MFMA
-    out["fp32_product"] = {"launch_ms": ms32, "entries_per_s": N * N / (ms32 * 1e-3),
-                           "frac_of_fp32_peak": N * N * f32_flops / (ms32 * 1e-3) / 1e12 /
-                           F32_PEAK_TFLOPS}
+    # FP32 model: distance (K = 32) and E.V (16 columns), 2 flops per
+    # multiply-add; executed: the distance as 6 bf16 slice products of K = 32
+    # on the bf16 matrix cores, E.V on the FP32 ones (the two are reported as
+    # the fraction of the launch their executed work needs at the peaks)
+    f32_flops = 2 * 32 + 2 * 16
+    t32 = ms32 * 1e-3
+    busy = N * N * (6 * 2 * 32 / (BF16_PEAK_TFLOPS * 1e12) + 2 * 16 / (F32_PEAK_TFLOPS * 1e12))
+    out["fp32_product"] = {"launch_ms": ms32, "entries_per_s": N * N / t32,
+                           "algorithmic_tflops_fp32_model": N * N * f32_flops / t32 / 1e12,
+                           "matrix_core_time_frac_executed": busy / t32}
     ms64 = _product_rate(b, torch, p.kind, p.sigma, b.FP64, X, m, launches=2)
     f64_flops = 2 * 32 + 2 + 2 * m  # distance, norms, E.V on the VALU
     out["fp64_product"] = {"launch_ms": ms64, "entries_per_s": N * N / (ms64 * 1e-3),

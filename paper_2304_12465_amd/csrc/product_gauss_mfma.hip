@@ -6,7 +6,11 @@
 // ~eps ||x||^2).  The distance MFMA starts from -||x||^2 / 2, so one FMA
 // gives the exponent; exp runs on the VALU (FP64: the table-driven exp64_u
 // on an exponent scaled by 1024/ln2; FP32: v_exp_f32 on an exponent scaled
-// by log2 e).  The reduction against V
+// by log2 e).  FP32 points of padded dimension 8, 16 or 32 run the
+// contraction as three bf16 slices per coordinate on
+// v_mfma_f32_16x16x32_bf16 (gauss_mfma.h: exact slices, six slice products,
+// the dropped ones below 2^-24 |x||y|), other FP32 dimensions on
+// v_mfma_f32_16x16x4f32.  The reduction against V
 // is a second MFMA for more than 4 right-hand sides: the distance output
 // layout (lane l holds, for t = 0..3, column col(t, l/16) of row l % 16) is
 // the A-operand layout of K-step t of the 16x16x4 MFMA with K index l / 16
@@ -41,13 +45,26 @@ __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
 // set to kFar when the norms are stored, so their kernel values are exactly
 // 0.  No value is tested when it is loaded: the loads stay in flight across
 // the current chunk's MFMAs.
+// The product tiles take the three-slice bf16 contraction at padded
+// dimension 8, 16 and 32 (at 24 its slices spill 30-160 registers at 4 waves
+// per SIMD, against 0-36 for the FP32 contraction).
+template <typename T, int D>
+constexpr bool g_split() {
+  return s3_split<T, D>() && D != 24;
+}
+
 template <typename T, int D, int VS>
 struct StageG {
-  static constexpr int kY = kColsG * D / 256;  // point values per thread
+  static constexpr bool kSplit = g_split<T, D>();
+  // point values per thread; split path: 4-coordinate segments instead
+  static constexpr int kY = kSplit ? 1 : kColsG * D / 256;
+  static constexpr int kSegs = kColsG * D / 4;
+  static constexpr int kSegPT = kSplit ? (kSegs + 255) / 256 : 1;
   // V: 64 columns x VS right-hand-side slots (16 for the MFMA reduction,
   // the m used for the VALU one), at most one value per thread below 256
   static constexpr int kV = (kColsG * VS + 255) / 256;
   T y[kY];
+  f32x4 y4[kSegPT];  // split path: coordinates 4 (seg % (D/4)) .. + 3 of column seg / (D/4)
   T v[kV];
   T yn;        // threads 0..63: squared norm of their column
   bool valid;  // threads 0..63: the column is in range
@@ -57,9 +74,20 @@ template <typename T, int D, int VS>
 __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_t j1, int tid,
                                             StageG<T, D, VS>& st) {
   constexpr int kVals = kColsG * VS;  // V values of a chunk
+  typedef StageG<T, D, VS> S;
   if (jb + kColsG <= j1) {
+    if constexpr (S::kSplit) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
+      for (int q = 0; q < S::kSegPT; ++q) {
+        const int seg = tid + q * 256;
+        if (S::kSegs % 256 == 0 || seg < S::kSegs)
+          st.y4[q] = *reinterpret_cast<const f32x4*>(J.yc + (jb + seg / (D / 4)) * D +
+                                                      4 * (seg % (D / 4)));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < S::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
+    }
 #pragma unroll
     for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
       const int e = tid + q * 256;
@@ -71,11 +99,22 @@ __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_
     }
   } else {
     const int64_t last = j1 - 1;
+    if constexpr (S::kSplit) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) {
-      const int e = tid + q * 256;
-      const int64_t col = jb + e / D < last ? jb + e / D : last;
-      st.y[q] = J.yc[col * D + e % D];
+      for (int q = 0; q < S::kSegPT; ++q) {
+        const int seg = tid + q * 256;
+        if (S::kSegs % 256 == 0 || seg < S::kSegs) {
+          const int64_t col = jb + seg / (D / 4) < last ? jb + seg / (D / 4) : last;
+          st.y4[q] = *reinterpret_cast<const f32x4*>(J.yc + col * D + 4 * (seg % (D / 4)));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < S::kY; ++q) {
+        const int e = tid + q * 256;
+        const int64_t col = jb + e / D < last ? jb + e / D : last;
+        st.y[q] = J.yc[col * D + e % D];
+      }
     }
 #pragma unroll
     for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
@@ -98,7 +137,13 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   constexpr bool kF32 = std::is_same<T, float>::value;
   constexpr int KS = D / 4;
   constexpr int NT = kColsG / 16;
-  __shared__ T sY[kColsG][D + 1];
+  constexpr bool kSplit = g_split<T, D>();
+  constexpr int NC = s3_steps<D>();  // bf16 MFMA steps of the split path
+  constexpr int PY = s3_pitch<D>();
+  // the chunk's points: their values, or (split path) their slices h | m | l
+  // per row; the form not used keeps one element
+  __shared__ T sY[kSplit ? 1 : kColsG][D + 1];
+  __shared__ __attribute__((aligned(16))) __bf16 sYb[kSplit ? kColsG : 1][PY];
   __shared__ T sAy[kColsG];
   __shared__ T sV[kColsG][17];  // [column][rhs]
 
@@ -108,14 +153,24 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   const int64_t nr = J.nr, nc = J.nc;
   const int64_t row0 = (rg * 4 + wave) * (16 * kRTg);
 
-  T xb[kRTg][KS];  // B operand: X[i0 + li][4 ks + g]
+  T xb[kRTg][kSplit ? 1 : KS];  // B operand: X[i0 + li][4 ks + g]
+  bf16x8 xbb[kRTg][kSplit ? NC : 1];  // split path: B operand of step st
+  int aoff[kSplit ? NC : 1];          // split path: LDS offset of the A operand in a row
   acc_t cinit[kRTg];
 #pragma unroll
   for (int rt = 0; rt < kRTg; ++rt) {
     int64_t i = row0 + rt * 16 + li;
     if (i > nr - 1) i = nr - 1;
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) xb[rt][ks] = J.xc[i * D + 4 * ks + g];
+      for (int st = 0; st < NC; ++st) {
+        xbb[rt][st] = s3_b_operand<D>(J.xc + i * D, st, g);
+        if (rt == 0) aoff[st] = s3_a_offset<D>(st, g);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) xb[rt][ks] = J.xc[i * D + 4 * ks + g];
+    }
     const T h = T(-0.5) * J.xn[i];
     cinit[rt] = acc_t{h, h, h, h};
   }
@@ -148,10 +203,20 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   int chunk = 0;
   for (int64_t jb = j0; jb < j1; jb += kColsG, ++chunk) {
     __syncthreads();  // the previous chunk's LDS reads are done
+    if constexpr (kSplit) {
+      typedef StageG<T, D, VS> S;
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kY; ++q) {
-      const int e = tid + q * 256;
-      sY[e / D][e % D] = st.y[q];
+      for (int q = 0; q < S::kSegPT; ++q) {
+        const int seg = tid + q * 256;
+        if (S::kSegs % 256 == 0 || seg < S::kSegs)
+          s3_store_quad<D>(st.y4[q], seg % (D / 4), sYb[seg / (D / 4)]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < StageG<T, D, VS>::kY; ++q) {
+        const int e = tid + q * 256;
+        sY[e / D][e % D] = st.y[q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
@@ -164,16 +229,31 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
     if (row0 >= nr) continue;
     acc_t dot[2][kRTg];
     auto distance = [&](int ct, acc_t* dd) {
-      T ya[KS];  // A operand: Y[ct*16 + li][4 ks + g]
+      if constexpr (kSplit) {
+        bf16x8 ya[NC];  // A operand: slices of Y[ct*16 + li]
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
-      // the first K step reads the -||x||^2 / 2 start from cinit directly
+        for (int st = 0; st < NC; ++st)
+          ya[st] = *reinterpret_cast<const bf16x8*>(&sYb[ct * 16 + li][aoff[st]]);
 #pragma unroll
-      for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[0], xb[rt][0], cinit[rt]);
+        for (int rt = 0; rt < kRTg; ++rt)
+          dd[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[0], xbb[rt][0], cinit[rt], 0, 0, 0);
 #pragma unroll
-      for (int ks = 1; ks < KS; ++ks)
+        for (int st = 1; st < NC; ++st)
 #pragma unroll
-        for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dd[rt]);
+          for (int rt = 0; rt < kRTg; ++rt)
+            dd[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[st], xbb[rt][st], dd[rt], 0, 0, 0);
+      } else {
+        T ya[KS];  // A operand: Y[ct*16 + li][4 ks + g]
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ya[ks] = sY[ct * 16 + li][4 * ks + g];
+        // the first K step reads the -||x||^2 / 2 start from cinit directly
+#pragma unroll
+        for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[0], xb[rt][0], cinit[rt]);
+#pragma unroll
+        for (int ks = 1; ks < KS; ++ks)
+#pragma unroll
+          for (int rt = 0; rt < kRTg; ++rt) dd[rt] = GT<T>::mfma(ya[ks], xb[rt][ks], dd[rt]);
+      }
     };
     // FP32: the distance MFMAs of column tile ct + 1 are issued before the
     // exp work of tile ct, which does not depend on them (the FP32 matrix

@@ -6,15 +6,10 @@
 // as the B operand, 128 per workgroup), the nonzeros of a range of sketch
 // rows are its columns, 64 at a time, with their points gathered into LDS.
 // The distance contraction runs on v_mfma_f64_16x16x4f64 as in the FP64
-// product tile.  FP32 points (padded dimension 8, 16, 24 or 32) run it on
-// v_mfma_f32_16x16x32_bf16 instead: every coordinate is split into three
-// bf16 slices, x = h + m + l (round to nearest at each step; the three
-// slices hold the FP32 value exactly), and the six slice products of
-// weight down to 2^-16 (hh, hm, mh, hl, lh, mm) are contracted with FP32
-// accumulation; each is exact in FP32, and the three dropped ones are below
-// 2^-24 |x||y| together, under the FP32 contraction's own rounding.  At
-// d = 16 that is three 16-cycle MFMAs per 256 entries against four 32-cycle
-// FP32 ones.  Other padded dimensions use v_mfma_f32_16x16x4f32.  Instead of a
+// product tile.  FP32 points (padded dimension 8, 16, 24 or 32) run it as the
+// three-slice bf16 contraction of the FP32 product tiles (gauss_mfma.h): at
+// d = 16 three 16-cycle MFMAs per 256 entries against four 32-cycle FP32
+// ones.  Other padded dimensions use v_mfma_f32_16x16x4f32.  Instead of a
 // product with V, each lane adds the exponentials of its columns (signed)
 // into the running sum of the current sketch row, and a row's sum is
 // completed across the four lanes that share a centre when the nonzeros
@@ -32,46 +27,6 @@ namespace {
 
 constexpr int kSkRT = 2;     // 16-centre tiles per wave (128 centres per workgroup)
 constexpr int kSkCols = 64;  // nonzeros per LDS chunk (four 16-column tiles)
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// FP32 points with D a multiple of 8 up to 32 take the three-slice bf16
-// contraction.
-template <typename T, int D>
-constexpr bool sk_split() {
-  return std::is_same<T, float>::value && D % 8 == 0 && D <= 32;
-}
-// The six slice products: slice of the point (A operand) and of the centre
-// (B operand) of product p; h = 0, m = 1, l = 2.
-__device__ __forceinline__ int sk_yslice(int p) { return p == 2 || p == 5 ? 1 : p == 4 ? 2 : 0; }
-__device__ __forceinline__ int sk_xslice(int p) { return p == 1 || p == 5 ? 1 : p == 3 ? 2 : 0; }
-// MFMA steps (K = 32 each) over the 6 D slice coordinates
-template <int D>
-constexpr int sk_steps() {
-  return (6 * D + 31) / 32;
-}
-// LDS row pitch (bf16) of a chunk's split points: 3 D, plus 8 when 3 D / 8
-// is even, so the 16-byte reads of 8 consecutive rows fall in distinct banks
-template <int D>
-constexpr int sk_pitch() {
-  return (3 * D / 8) % 2 ? 3 * D : 3 * D + 8;
-}
-
-// Two coordinates -> their h, m and l bf16 slices, each pair packed in a
-// 32-bit word (low half: a).  Each remainder is exact in FP32.
-__device__ __forceinline__ void split3_pair(float a, float b, uint32_t& h, uint32_t& m,
-                                            uint32_t& l) {
-  h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
-  a -= __builtin_bit_cast(float, h << 16);
-  b -= __builtin_bit_cast(float, h & 0xffff0000u);
-  m = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
-  a -= __builtin_bit_cast(float, m << 16);
-  b -= __builtin_bit_cast(float, m & 0xffff0000u);
-  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
-}
 
 template <typename T>
 struct SketchJob {
@@ -109,9 +64,9 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
   constexpr int KS = D / 4;
   constexpr int NT = kSkCols / 16;
   constexpr int kY = kSkCols * D / 256;
-  constexpr bool kSplit = sk_split<T, D>();
-  constexpr int NC = sk_steps<D>();        // bf16 MFMA steps
-  constexpr int PY = sk_pitch<D>();
+  constexpr bool kSplit = s3_split<T, D>();
+  constexpr int NC = s3_steps<D>();        // bf16 MFMA steps
+  constexpr int PY = s3_pitch<D>();
   constexpr int kSegs = kSkCols * D / 4;   // 4-coordinate segments of a chunk's points
   constexpr int kSegPT = (kSegs + 255) / 256;
   __shared__ double etab[GT<T>::kTable];  // FP64 exp table (one unused entry for FP32)
@@ -146,19 +101,8 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
     if constexpr (kSplit) {
 #pragma unroll
       for (int st = 0; st < NC; ++st) {
-        const int G = 4 * st + g, p = G / (D / 8), d0 = 8 * (G % (D / 8));
-        u32x4 w = {0u, 0u, 0u, 0u};
-        if (p < 6) {
-          const int xs = sk_xslice(p);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            uint32_t h, m, l;
-            split3_pair(J.cc[c * D + d0 + 2 * e], J.cc[c * D + d0 + 2 * e + 1], h, m, l);
-            w[e] = xs == 0 ? h : xs == 1 ? m : l;
-          }
-        }
-        xbb[rt][st] = __builtin_bit_cast(bf16x8, w);
-        if (rt == 0) aoff[st] = p < 6 ? sk_yslice(p) * D + d0 : 0;
+        xbb[rt][st] = s3_b_operand<D>(J.cc + c * D, st, g);
+        if (rt == 0) aoff[st] = s3_a_offset<D>(st, g);
       }
     } else {
 #pragma unroll
@@ -250,15 +194,8 @@ void sketch_gauss_mfma(const SketchJob<T> J) {
 #pragma unroll
       for (int q = 0; q < kSegPT; ++q) {
         const int seg = tid + q * 256;
-        if (kSegs % 256 == 0 || seg < kSegs) {
-          uint32_t h0, m0, l0, h1, m1, l1;
-          split3_pair(y4_st[q][0], y4_st[q][1], h0, m0, l0);
-          split3_pair(y4_st[q][2], y4_st[q][3], h1, m1, l1);
-          __bf16* row = &sYb[seg / (D / 4)][4 * (seg % (D / 4))];
-          *reinterpret_cast<uint2*>(row) = make_uint2(h0, h1);
-          *reinterpret_cast<uint2*>(row + D) = make_uint2(m0, m1);
-          *reinterpret_cast<uint2*>(row + 2 * D) = make_uint2(l0, l1);
-        }
+        if (kSegs % 256 == 0 || seg < kSegs)
+          s3_store_quad<D>(y4_st[q], seg % (D / 4), sYb[seg / (D / 4)]);
       }
     } else {
 #pragma unroll
