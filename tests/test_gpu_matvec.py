@@ -65,8 +65,11 @@ def check(kind, prec, Xr, Xc, V, sigma, shift=0.0):
 
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("d", [1, 3, 8, 17, 20, 32, 33, 64])
+@pytest.mark.parametrize("d", [1, 3, 8, 12, 17, 20, 23, 32, 33, 64])
 def test_square_with_shift(kind, prec, d):
+    # padded dimensions 4 to 64; FP32 Gaussian tiles contract three bf16
+    # slices per coordinate at 8, 16 (d = 12, four zero coordinates) and 32,
+    # and FP32 products at the others
     g = np.random.default_rng(100 + d)
     n = 1337  # several 512-row workgroups and a ragged tail
     X = g.standard_normal((n, d))
