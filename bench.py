@@ -183,7 +183,9 @@ def headline(a, b, torch, synth, np):
         "metric": METRIC, "value": entries / wall, "unit": "kernel entries/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
-        "precision": {"restricted_products": "f64", "rhs_and_checks": "f64", "sketch": "f32",
+        "precision": {"restricted_products": "f64", "rhs_and_checks": "f64",
+                      "sketch": "f32 (FP32 points as exact bf16 slices, FP32 accumulation, "
+                                "FP64 row sums)",
                       "factor": "f64", "cg": "f64"},
         "data": "synthetic",
         "config": {"workload": f"restricted KRR with KRILL: N={N}, d={d} standard normal with "
