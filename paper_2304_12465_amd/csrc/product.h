@@ -197,6 +197,8 @@ struct GJob {
   double s_nat;     // 1 / (2 sigma^2)
   int nsplit, M, dpad;
   int route;        // 0: the kernels evaluate the guard; 1: expansion tile; 2: direct differences
+  T* store;         // store variant: the kernel values, nr x ld (row-major), else null
+  int64_t ld;
 };
 typedef GJob<double> F64Job;
 typedef GJob<float> F32Job;
@@ -211,6 +213,14 @@ int f64_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecVie
 int f32_prepare(double sigma, const PointSet& rows, const PointSet& cols, VecView V, int c0, int mc,
                 Arena& scratch, F32Job* out, hipStream_t s);
 int f64_launch(const std::vector<F64Job>& jobs, hipStream_t s);
+// Writes the Gaussian kernel block K(rows, cols) (nr x nc, row-major with
+// leading dimension ld >= nc, zero in columns nc .. ld - 1) with the
+// expansion tiles in `prec` (KRR_FP64: FP64 values, KRR_FP32: FP32), when
+// the expansion's guard, taken on the host from the norm maxima the point
+// sets hold (learn_norm_max), admits it; *done tells whether it did (else
+// the caller evaluates the block by direct differences).
+int gauss_block_store(krr_precision prec, double sigma, const PointSet& rows,
+                      const PointSet& cols, void* out, int64_t ld, bool* done, hipStream_t s);
 int f32_launch(const std::vector<F32Job>& jobs, hipStream_t s);
 
 // bf16-split MFMA path for Gaussian tiles (product_mfma.hip).

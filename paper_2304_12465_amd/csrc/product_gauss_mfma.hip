@@ -49,20 +49,20 @@ __device__ __forceinline__ bool needs_direct(const GJob<T>& J) {
 // dimension 8, 16 and 32 (at 24 its slices spill 30-160 registers at 4 waves
 // per SIMD, against 0-36 for the FP32 contraction).
 template <typename T, int D>
-constexpr bool g_split() {
+constexpr bool g_uses_split() {
   return s3_split<T, D>() && D != 24;
 }
 
 template <typename T, int D, int VS>
 struct StageG {
-  static constexpr bool kSplit = g_split<T, D>();
+  static constexpr bool kSplit = g_uses_split<T, D>();
   // point values per thread; split path: 4-coordinate segments instead
   static constexpr int kY = kSplit ? 1 : kColsG * D / 256;
   static constexpr int kSegs = kColsG * D / 4;
   static constexpr int kSegPT = kSplit ? (kSegs + 255) / 256 : 1;
   // V: 64 columns x VS right-hand-side slots (16 for the MFMA reduction,
   // the m used for the VALU one), at most one value per thread below 256
-  static constexpr int kV = (kColsG * VS + 255) / 256;
+  static constexpr int kV = VS > 0 ? (kColsG * VS + 255) / 256 : 1;  // VS = 0: no V (store)
   T y[kY];
   f32x4 y4[kSegPT];  // split path: coordinates 4 (seg % (D/4)) .. + 3 of column seg / (D/4)
   T v[kV];
@@ -88,10 +88,12 @@ __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_
 #pragma unroll
       for (int q = 0; q < S::kY; ++q) st.y[q] = J.yc[jb * D + tid + q * 256];
     }
+    if constexpr (VS > 0) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
-      const int e = tid + q * 256;
-      if (e < kVals) st.v[q] = J.v[(jb + e / VS) * 16 + e % VS];
+      for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
+        const int e = tid + q * 256;
+        if (e < kVals) st.v[q] = J.v[(jb + e / VS) * 16 + e % VS];
+      }
     }
     if (tid < kColsG) {
       st.yn = J.yn[jb + tid];
@@ -116,11 +118,13 @@ __device__ __forceinline__ void stage_fetch(const GJob<T>& J, int64_t jb, int64_
         st.y[q] = J.yc[col * D + e % D];
       }
     }
+    if constexpr (VS > 0) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
-      const int e = tid + q * 256;
-      const int64_t col = jb + e / VS < last ? jb + e / VS : last;
-      if (e < kVals) st.v[q] = J.v[col * 16 + e % VS];
+      for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
+        const int e = tid + q * 256;
+        const int64_t col = jb + e / VS < last ? jb + e / VS : last;
+        if (e < kVals) st.v[q] = J.v[col * 16 + e % VS];
+      }
     }
     if (tid < kColsG) {
       const int64_t col = jb + tid < last ? jb + tid : last;
@@ -137,7 +141,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   constexpr bool kF32 = std::is_same<T, float>::value;
   constexpr int KS = D / 4;
   constexpr int NT = kColsG / 16;
-  constexpr bool kSplit = g_split<T, D>();
+  constexpr bool kSplit = g_uses_split<T, D>();
   constexpr int NC = s3_steps<D>();  // bf16 MFMA steps of the split path
   constexpr int PY = s3_pitch<D>();
   // the chunk's points: their values, or (split path) their slices h | m | l
@@ -178,8 +182,10 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   // odd K steps) keep independent MFMA chains in flight.  On the VALU
   // (MV = 1, 2, 4, 8 right-hand sides): lane l sums E[li][col] V[col][c] over
   // its columns.
+  // MV < 0: the store variant (the kernel values go to J.store, no V)
+  constexpr bool kStore = MV < 0;
   constexpr int MA = MV == 0 ? 2 : 1;
-  constexpr int MC = MV == 0 ? 1 : MV;
+  constexpr int MC = MV <= 0 ? 1 : MV;
   acc_t acc[kRTg][MA];
   T accv[kRTg][MC];
   double fold[kRTg][4];  // FP32 only: FP64 running sums of the output entries
@@ -197,7 +203,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
   const int64_t j0 = (int64_t)split * J.per;
   int64_t j1 = j0 + J.per;
   if (j1 > nc) j1 = nc;
-  constexpr int VS = MV == 0 ? 16 : MV;  // V slots staged per column
+  constexpr int VS = MV == 0 ? 16 : kStore ? 0 : MV;  // V slots staged per column
   StageG<T, D, VS> st;
   if (j0 < j1) stage_fetch<T, D, VS>(J, j0, j1, tid, st);
   int chunk = 0;
@@ -218,10 +224,12 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
         sY[e / D][e % D] = st.y[q];
       }
     }
+    if constexpr (VS > 0) {
 #pragma unroll
-    for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
-      const int e = tid + q * 256;
-      if (e < kColsG * VS) sV[e / VS][e % VS] = st.v[q];
+      for (int q = 0; q < StageG<T, D, VS>::kV; ++q) {
+        const int e = tid + q * 256;
+        if (e < kColsG * VS) sV[e / VS][e % VS] = st.v[q];
+      }
     }
     if (tid < kColsG) sAy[tid] = st.valid ? -J.s * st.yn : GT<T>::kFar;
     __syncthreads();
@@ -276,7 +284,30 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           e[rt][t] = GT<T>::ex(fma_g(dot[ct & 1][rt][t], s2, ay[t]), etab);
-      if constexpr (MV == 0) {
+      if constexpr (kStore) {
+        // entry (row i0 + li, column col(t, g)) of the block; FP32 lanes
+        // hold four consecutive columns (col = 4 g + t): one 16-byte store
+        // (aligned: chunks start at multiples of 64 columns, ld is a
+        // multiple of 8)
+#pragma unroll
+        for (int rt = 0; rt < kRTg; ++rt) {
+          const int64_t i = row0 + rt * 16 + li;
+          if (i >= nr) continue;
+          if constexpr (kF32) {
+            const int64_t jc = jb + ct * 16 + 4 * g;
+            if (jc + 3 < j1) {
+              *reinterpret_cast<f32x4*>(&J.store[i * J.ld + jc]) =
+                  f32x4{e[rt][0], e[rt][1], e[rt][2], e[rt][3]};
+              continue;
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int64_t j = jb + ct * 16 + GT<T>::col(t, g);
+            if (j < j1) J.store[i * J.ld + j] = e[rt][t];
+          }
+        }
+      } else if constexpr (MV == 0) {
         // A of E.V step t: lane l holds E[li][col(t, g)] (K index g)
         T vb[4];
 #pragma unroll
@@ -297,7 +328,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
           }
       }
     }
-    if constexpr (kF32) {
+    if constexpr (kF32 && !kStore) {
       if ((chunk + 1) % kFoldG == 0) {
 #pragma unroll
         for (int rt = 0; rt < kRTg; ++rt) {
@@ -317,7 +348,7 @@ __device__ __forceinline__ void g_item(const GJob<T>& J, int64_t rg, int split,
       }
     }
   }
-  if (row0 >= nr) return;
+  if (kStore || row0 >= nr) return;
   // partial slots: split-major, rows of J.M values (the product's columns)
   double* __restrict__ out = J.part + (int64_t)split * nr * J.M;
   if constexpr (MV == 0) {
@@ -370,13 +401,16 @@ struct GTable {
 // compiler's choice.  FP32 tiles up to
 // 32 padded dimensions are held to 128 VGPRs (4 waves instead of 3; d = 32
 // spills 52-184 bytes): 2-12% faster over 1-8 right-hand sides.
-template <typename T, int D>
+// The FP64 store variant (MV < 0: kernel values written out, bound by the
+// writes) keeps 2 waves per SIMD, where 3-4 would spill its store addresses.
+template <typename T, int D, int MV>
 constexpr int g_waves_per_eu() {
+  if (std::is_same<T, double>::value && MV < 0) return D <= 48 ? 2 : 1;
   return std::is_same<T, double>::value ? (D <= 16 ? 4 : D <= 48 ? 3 : 1) : (D <= 32 ? 4 : 1);
 }
 
 template <typename T, int D, int MV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g_waves_per_eu<T, D>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(g_waves_per_eu<T, D, MV>())))
 void tile_gauss_mfma(const GTable<T> tab) {
   __shared__ double etab[GT<T>::kTable];  // FP64 exp table (one unused entry for FP32 tiles)
   if constexpr (std::is_same<T, double>::value) {
@@ -714,6 +748,93 @@ int carve_f32c(int64_t n, int32_t dpad, Arena& arena, PointSet* out) {
 }
 int fill_f32c(const double* X, const double* centre, const PointSet& ps, hipStream_t s) {
   return fill_centred<float>(X, centre, ps, ps.xc32, ps.xn32, ps.xmax32, s);
+}
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_pad_cols(T* __restrict__ out, int64_t nr, int64_t nc,
+                                                     int64_t ld) {
+  const int64_t w = ld - nc;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nr * w) return;
+  out[(e / w) * ld + nc + e % w] = T(0);
+}
+
+template <typename T>
+int g_block_store(double sigma, const T* rxc, const T* rxn, const T* rxmax, const T* cxc,
+                  const T* cxn, const T* cxmax, int64_t nr, int64_t nc, int dpad,
+                  double rmax_host, double cmax_host, T* out, int64_t ld, bool* done,
+                  hipStream_t s) {
+  *done = false;
+  const double s_nat = 1.0 / (2.0 * sigma * sigma);
+  // the products' guard, on the host: unknown maxima or too coarse an
+  // expansion leave the block to direct differences
+  if (rmax_host < 0.0 || cmax_host < 0.0) return KRR_OK;
+  if (s_nat * (rmax_host + cmax_host) * (dpad + 3) > GT<T>::kBound) return KRR_OK;
+  const GSplit sp = g_split(nr, nc);
+  GTable<T> tab{};
+  GJob<T>& j = tab.job[0];
+  j.xc = rxc;
+  j.xn = rxn;
+  j.xmax = rxmax;
+  j.ymax = cxmax;
+  j.yc = cxc;
+  j.yn = cxn;
+  j.nr = nr;
+  j.nc = nc;
+  j.per = sp.per;
+  j.s = (T)(GT<T>::kExpScale * s_nat);
+  j.s_nat = s_nat;
+  j.nsplit = sp.nsplit;
+  j.dpad = dpad;
+  j.route = 1;
+  j.store = out;
+  j.ld = ld;
+  tab.njobs = 1;
+  tab.total = ceil_div(nr, (int64_t)4 * 16 * kRTg) * sp.nsplit;
+  if (tab.total > 0 && nc > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>(xcd_slots(tab.total), kGridCap);
+    switch (dpad) {
+      case 4: tile_gauss_mfma<T, 4, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 8: tile_gauss_mfma<T, 8, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 16: tile_gauss_mfma<T, 16, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 20: tile_gauss_mfma<T, 20, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 24: tile_gauss_mfma<T, 24, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 32: tile_gauss_mfma<T, 32, -1><<<grid, 256, 0, s>>>(tab); break;
+      case 48: tile_gauss_mfma<T, 48, -1><<<grid, 256, 0, s>>>(tab); break;
+      default: tile_gauss_mfma<T, 64, -1><<<grid, 256, 0, s>>>(tab); break;
+    }
+    KRR_LAUNCH_CHECK("tile_gauss_mfma (store)");
+  }
+  if (ld > nc && nr > 0) {
+    zero_pad_cols<T><<<(unsigned)ceil_div(nr * (ld - nc), 256), 256, 0, s>>>(out, nr, nc, ld);
+    KRR_LAUNCH_CHECK("zero_pad_cols");
+  }
+  *done = true;
+  return KRR_OK;
+}
+
+}  // namespace
+
+int gauss_block_store(krr_precision prec, double sigma, const PointSet& rows,
+                      const PointSet& cols, void* out, int64_t ld, bool* done, hipStream_t s) {
+  if (prec == KRR_FP64) {
+    if (!rows.xc64 || !cols.xc64) {
+      *done = false;
+      return KRR_OK;
+    }
+    return g_block_store<double>(sigma, rows.xc64, rows.xn64, rows.xmax64, cols.xc64, cols.xn64,
+                                 cols.xmax64, rows.n, cols.n, rows.dpad, rows.max_host,
+                                 cols.max_host, static_cast<double*>(out), ld, done, s);
+  }
+  if (!rows.xc32 || !cols.xc32) {
+    *done = false;
+    return KRR_OK;
+  }
+  return g_block_store<float>(sigma, rows.xc32, rows.xn32, rows.xmax32, cols.xc32, cols.xn32,
+                              cols.xmax32, rows.n, cols.n, rows.dpad, rows.max_host,
+                              cols.max_host, static_cast<float*>(out), ld, done, s);
 }
 
 int learn_norm_max(PointSet& ps, hipStream_t s) {

@@ -385,8 +385,18 @@ size_t stored_bytes(int64_t N, int64_t k, int es, int32_t m_max, size_t* part_by
 int stored_fill(Precond& P, hipStream_t s) {
   const bool f64 = P.kns_es == 8;
   const StoredPlan pl = stored_plan(P.N, P.k, P.kns_es);
-  const PointSet& X = f64 ? P.pts64 : P.pts;
-  const PointSet& C = f64 ? P.cpts64 : P.cpts;
+  PointSet& X = f64 ? P.pts64 : P.pts;
+  PointSet& C = f64 ? P.cpts64 : P.cpts;
+  if (P.kind == KRR_GAUSSIAN) {
+    // the product tiles' expansion writes the block where its guard admits
+    // the problem (the same entries the recomputing tiles evaluate); the
+    // norm maxima are learned here for that choice
+    KRR_TRY(learn_norm_max(X, s));
+    KRR_TRY(learn_norm_max(C, s));
+    bool done = false;
+    KRR_TRY(gauss_block_store(f64 ? KRR_FP64 : KRR_FP32, P.sigma, X, C, P.kns, pl.ld, &done, s));
+    if (done) return KRR_OK;
+  }
   const int D = X.dpad;
   const double log2e = 1.4426950408889634;
   const double scale = P.kind == KRR_LAPLACE ? -1.0 / P.sigma : -1.0 / (2.0 * P.sigma * P.sigma);

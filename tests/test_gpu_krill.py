@@ -483,9 +483,12 @@ def build_stored(p, prec, centers=None, m_max=1):
 def test_stored_block_and_operator(kind, prec):
     # prec 2 (KRR_MIXED): the FP64 block and operator with the sketch on FP32 tiles
     # Stored mode (Sec. 4.1 keeps A(:,S) in memory): the stored block against
-    # the oracle's A(:,S) (FP64: exp within an ulp or two; FP32: FP32 direct
-    # differences, |arg| (d + 2) 2^-24 plus FP32 rounding of the exp), then the
-    # restricted operator over it for m = 1 (one pass), 2 and 6 (two passes)
+    # the oracle's A(:,S), then the restricted operator over it for m = 1 (one
+    # pass), 2 and 6 (two passes).  Gaussian blocks come from the product
+    # tiles' expansion, whose guard holds the exponent's error to 400 eps (FP64)
+    # or 200 eps_32 (FP32), plus a few ulps of exp and, in FP32, the exponent's
+    # own rounding; Laplace blocks from direct differences (FP64: exp within an
+    # ulp or two; FP32: |arg| (d + 2) 2^-24 plus FP32 rounding of the exp)
     p = small(n=3000, k=150)
     if kind == 1:
         p.kind, p.sigma = 1, 2.0
@@ -494,11 +497,17 @@ def test_stored_block_and_operator(kind, prec):
     kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
                    seed=p.algo_seed)
     A = B().krill_export(P, 5, (p.X.shape[0], p.centers), torch.float64).cpu().numpy()
-    if prec != 1:
+    arg = -np.log(np.maximum(kr.AnS, 1e-300))
+    if kind == 0:
+        if prec != 1:
+            bound = 404 * 2.0 ** -53 * kr.AnS + 1e-300
+        else:
+            bound = (2 * (arg + 1) + 204) * 2.0 ** -24 * kr.AnS + 1e-38
+        assert np.all(np.abs(A - kr.AnS) <= bound), np.max(np.abs(A - kr.AnS) / bound)
+    elif prec != 1:
         np.testing.assert_allclose(A, kr.AnS, rtol=4e-16, atol=1e-300)
     else:
         d = p.X.shape[1]
-        arg = -np.log(np.maximum(kr.AnS, 1e-300))
         bound = ((arg + 1) * (d + 2) + 4) * 2.0 ** -24 * kr.AnS + 1e-38
         assert np.all(np.abs(A - kr.AnS) <= bound), np.max(np.abs(A - kr.AnS) / bound)
     # B, H as the recomputing build
