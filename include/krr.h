@@ -203,7 +203,10 @@ int krr_krill_build(krr_kernel_kind kind, double sigma, krr_precision prec, cons
  * (Sec. 4.1 keeps it in memory): as krr_krill_build, and in addition A(:,S)
  * is evaluated once by the build into the workspace, in FP64 (prec =
  * KRR_FP64, 8 N k bytes) or FP32 (KRR_FP32, 4 N k bytes; rows padded to a
- * multiple of 8 entries).  Every later application of the restricted
+ * multiple of 8 entries), by the same Gaussian tiles the recomputing
+ * products use when their expansion guard admits the problem (entries as
+ * those products evaluate them), else by direct differences.  Every later
+ * application of the restricted
  * operator (krr_pcg_solve, the stepped solves, krr_precond_operator) then
  * streams the stored block instead of recomputing its entries: with one
  * right-hand side one pass over it forms A(S,:)(A(:,S) v), otherwise two.
