@@ -523,6 +523,34 @@ def test_stored_block_and_operator(kind, prec):
         assert np.all(np.abs(got - ref) <= otol * scale), (m, np.max(np.abs(got - ref) / scale))
 
 
+@pytest.mark.parametrize("d", [7, 23, 30])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_gaussian_block_over_padded_dimensions(prec, d):
+    # the Gaussian stored block from the expansion tiles' store variant at
+    # padded dimensions 8, 24 and 32 (FP32: bf16 slices at 8 and 32, FP32
+    # products at 24): entries within the expansion's bound, k = 150 centres
+    # leave a ragged last chunk and the rows' padding columns zero (read back
+    # through the operator, which streams whole padded rows)
+    p = synth.c4(n=3000, k=150, d=d)
+    P = build_stored(p, prec)
+    S = np.array(P.pivots())
+    kr = OKR.Krill(p.X, p.kind, p.sigma, p.mu, S, sketch_rows=p.sketch_rows, zeta=p.zeta,
+                   seed=p.algo_seed)
+    A = B().krill_export(P, 5, (p.X.shape[0], p.centers), torch.float64).cpu().numpy()
+    arg = -np.log(np.maximum(kr.AnS, 1e-300))
+    if prec == 0:
+        bound = 404 * 2.0 ** -53 * kr.AnS + 1e-300
+    else:
+        bound = (2 * (arg + 1) + 204) * 2.0 ** -24 * kr.AnS + 1e-38
+    assert np.all(np.abs(A - kr.AnS) <= bound), np.max(np.abs(A - kr.AnS) / bound)
+    V = np.random.default_rng(40 + d).standard_normal((p.centers, 1))
+    got = P.operator(T(V)).cpu().numpy()
+    ref = kr.product(V)
+    scale = np.abs(kr.AnS).T @ (np.abs(kr.AnS) @ np.abs(V)) + np.abs(kr.H) @ np.abs(V)
+    otol = 4e-5 if prec == 1 else 1e-12
+    assert np.all(np.abs(got - ref) <= otol * scale), np.max(np.abs(got - ref) / scale)
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_stored_solve_matches_recomputed_and_oracle(prec):
     # the same KRILL preconditioner (same centres and sketch) with the block
